@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds workload definitions (parameter sets, grid sizes, boundary kinds)
+and field generators (phase profiles, velocity fields, random distribution states).
+It contains none of the lattice Boltzmann method's arithmetic: it only produces the
+numbers both the CPU reference and the GPU library are fed.  Every array it returns
+is float32 (rounded once from float64), so both sides start from identical values.
+
+Workloads (lattice units, rho_L = 1):
+  static_droplet   D2Q9 64x64 periodic, R=16, W=4, rho_H=1000, M=0.1, sigma=1e-3,
+                   nu_H=nu_L=0.01 (the paper's static-droplet case, Section 4.1, with
+                   the density ratio of 1000 used throughout).
+  rayleigh_taylor  D2Q9 256x1024, x periodic, y walls, Atwood 0.5 (rho_H=3), g=1e-5,
+                   W=5, Re=UL/nu_H=3000 with U=sqrt(gL), mu_H=mu_L, Pe=UL/M=1000,
+                   Ca=rho_H U nu_H/sigma=0.26, interface y0 = 511.5 + 0.1 L cos(2 pi x/L)
+                   (Section 4.3's rho_ratio = 3 case, rescaled to L = 256).
+  rising_bubble    D3Q19 128^3, x,y periodic, z walls, rho_H=1000, mu_H/mu_L=100,
+                   nu_H=0.01, R=16, W=4, M=0.1, g=1e-5, Eotvos g drho (2R)^2/sigma = 10.
+  droplet_impact   D3Q19 256x256x128, x,y periodic, z walls, rho_H=1000, R=32, film
+                   depth 16, impact velocity 0.05, Re=UD/nu_H=500, We=rho_H U^2 D/sigma
+                   =8000, mu_H/mu_L=100, W=4, M=0.1, g=0.
+"""
+import math
+
+import numpy as np
+
+PERIODIC = "periodic"
+WALL = "wall"
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+# ---------------------------------------------------------------------------
+# parameter sets
+# ---------------------------------------------------------------------------
+
+def static_droplet(n=64, R=16.0, W=4.0, rho_H=1000.0, sigma=1e-3, nu=0.01, M=0.1):
+    return dict(name="static_droplet", lattice=9, shape=(n, n, 1),
+                bc=(PERIODIC, PERIODIC, PERIODIC), rho_L=1.0, rho_H=rho_H, nu_L=nu,
+                nu_H=nu, M=M, W=W, sigma=sigma, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1,
+                dtheta_C=0.0, R=R, steps=1000)
+
+
+def rayleigh_taylor(nx=256, ny=1024):
+    g = 1e-5
+    U = math.sqrt(g * nx)
+    rho_H = 3.0
+    nu_H = U * nx / 3000.0
+    nu_L = nu_H * rho_H          # mu_H = mu_L
+    M = U * nx / 1000.0
+    sigma = rho_H * U * nu_H / 0.26
+    return dict(name="rayleigh_taylor", lattice=9, shape=(nx, ny, 1),
+                bc=(PERIODIC, WALL, PERIODIC), rho_L=1.0, rho_H=rho_H, nu_L=nu_L,
+                nu_H=nu_H, M=M, W=5.0, sigma=sigma, g=(0.0, -g, 0.0), eps=1e-10,
+                hoc=1, dtheta_C=0.0, amp=0.1 * nx, steps=20000)
+
+
+def rising_bubble(n=128, R=16.0):
+    rho_H, rho_L, g = 1000.0, 1.0, 1e-5
+    sigma = g * (rho_H - rho_L) * (2 * R) ** 2 / 10.0
+    return dict(name="rising_bubble", lattice=19, shape=(n, n, n),
+                bc=(PERIODIC, PERIODIC, WALL), rho_L=rho_L, rho_H=rho_H, nu_L=0.1,
+                nu_H=0.01, M=0.1, W=4.0, sigma=sigma, g=(0.0, 0.0, -g), eps=1e-10,
+                hoc=1, dtheta_C=0.0, R=R, steps=10000)
+
+
+def droplet_impact(nx=256, ny=256, nz=128, R=32.0, film=16.0, U=0.05):
+    rho_H = 1000.0
+    D = 2 * R
+    nu_H = U * D / 500.0
+    sigma = rho_H * U * U * D / 8000.0
+    return dict(name="droplet_impact", lattice=19, shape=(nx, ny, nz),
+                bc=(PERIODIC, PERIODIC, WALL), rho_L=1.0, rho_H=rho_H, nu_L=10.0 * nu_H,
+                nu_H=nu_H, M=0.1, W=4.0, sigma=sigma, g=(0.0, 0.0, 0.0), eps=1e-10,
+                hoc=1, dtheta_C=0.0, R=R, film=film, U=U, steps=5000)
+
+
+def model_params(cfg):
+    """The subset of a workload dict both sides take as model parameters."""
+    keys = ("lattice", "shape", "bc", "rho_L", "rho_H", "nu_L", "nu_H", "M", "W",
+            "sigma", "g", "eps", "hoc", "dtheta_C")
+    return {k: cfg[k] for k in keys}
+
+
+# ---------------------------------------------------------------------------
+# field generators; arrays have shape (nz, ny, nx), vectors (3, nz, ny, nx)
+# ---------------------------------------------------------------------------
+
+def _grid(shape):
+    nx, ny, nz = shape
+    return np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                       np.arange(nx, dtype=np.float64), indexing="ij")
+
+
+def drop_profile(shape, centre, R, W, inside=1.0):
+    """1/2 - 1/2 tanh(2 (r - R)/W) (value `inside` at the centre, 1 - inside far away)."""
+    z, y, x = _grid(shape)
+    cx, cy, cz = centre
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + ((z - cz) ** 2 if shape[2] > 1 else 0.0))
+    p = 0.5 - 0.5 * np.tanh(2.0 * (r - R) / W)
+    return p if inside == 1.0 else 1.0 - p
+
+
+def centre_of(shape):
+    nx, ny, nz = shape
+    return ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0 if nz > 1 else 0.0)
+
+
+def fields_static_droplet(cfg):
+    phi = drop_profile(cfg["shape"], centre_of(cfg["shape"]), cfg["R"], cfg["W"])
+    u = np.zeros((3,) + phi.shape)
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
+def fields_rayleigh_taylor(cfg):
+    nx, ny, nz = cfg["shape"]
+    z, y, x = _grid(cfg["shape"])
+    y0 = (ny - 1) / 2.0 + cfg["amp"] * np.cos(2.0 * np.pi * x / nx)
+    phi = 0.5 + 0.5 * np.tanh(2.0 * (y - y0) / cfg["W"])      # heavy fluid on top
+    u = np.zeros((3,) + phi.shape)
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
+def fields_rising_bubble(cfg):
+    nx, ny, nz = cfg["shape"]
+    centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, nz / 4.0)
+    phi = drop_profile(cfg["shape"], centre, cfg["R"], cfg["W"], inside=0.0)
+    u = np.zeros((3,) + phi.shape)
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
+def fields_droplet_impact(cfg):
+    nx, ny, nz = cfg["shape"]
+    z, y, x = _grid(cfg["shape"])
+    film = 0.5 - 0.5 * np.tanh(2.0 * (z - (cfg["film"] - 0.5)) / cfg["W"])
+    zc = cfg["film"] + cfg["W"] + cfg["R"]
+    drop = drop_profile(cfg["shape"], ((nx - 1) / 2.0, (ny - 1) / 2.0, zc), cfg["R"],
+                        cfg["W"])
+    phi = np.maximum(film, drop)
+    u = np.zeros((3,) + phi.shape)
+    u[2] = -cfg["U"] * drop
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
+FIELDS = {"static_droplet": fields_static_droplet,
+          "rayleigh_taylor": fields_rayleigh_taylor,
+          "rising_bubble": fields_rising_bubble,
+          "droplet_impact": fields_droplet_impact}
+
+
+def fields(cfg):
+    return FIELDS[cfg["name"]](cfg)
+
+
+# ---------------------------------------------------------------------------
+# seeded random states (pre-collision distributions) for one-step checks
+# ---------------------------------------------------------------------------
+
+_MAG = {9: [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4,
+        19: [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12}
+
+
+def smooth_random_field(shape, seed, modes=4, lo=0.0, hi=1.0):
+    """Sum of a few random long-wave Fourier modes mapped into [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    z, y, x = _grid(shape)
+    nx, ny, nz = shape
+    acc = np.zeros_like(x)
+    for _ in range(modes):
+        kx, ky = rng.integers(0, 3, size=2)
+        kz = rng.integers(0, 3) if nz > 1 else 0
+        ph = rng.uniform(0, 2 * np.pi)
+        acc += np.cos(2 * np.pi * (kx * x / nx + ky * y / ny + kz * z / max(nz, 1)) + ph)
+    acc = (acc - acc.min()) / max(acc.max() - acc.min(), 1e-12)
+    return lo + (hi - lo) * acc
+
+
+def random_state(q, shape, seed, phi=None, h_noise=0.02, g_scale=0.05, g_noise=0.02):
+    """Pre-collision populations (h, g), shape (Q, nz, ny, nx), float32.
+
+    h_i = a_i (phi + h_noise * N(0,1)), g_i = a_i (g_scale * s(x) + g_noise * N(0,1)),
+    with a_i the usual lattice-weight magnitudes, phi a smooth random field in [0, 1]
+    unless given, and s a smooth random field in [-1, 1]."""
+    rng = np.random.default_rng(seed + 7919)
+    a = np.asarray(_MAG[q]).reshape(q, 1, 1, 1)
+    if phi is None:
+        phi = smooth_random_field(shape, seed)
+    phi = np.asarray(phi, dtype=np.float64)
+    s = smooth_random_field(shape, seed + 1, lo=-1.0, hi=1.0)
+    nz, ny, nx = phi.shape
+    h = a * (phi[None] + h_noise * rng.standard_normal((q, nz, ny, nx)))
+    g = a * (g_scale * s[None] + g_noise * rng.standard_normal((q, nz, ny, nx)))
+    return _f32(h), _f32(g)
+
+
+def sample_sites(shape, count, seed, include_faces=True):
+    """Integer (S, 3) array of (x, y, z) sites: random ones plus (optionally) the
+    corners and face centres of the box, where the boundary rules act."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    pts = [np.stack([rng.integers(0, nx, count), rng.integers(0, ny, count),
+                     rng.integers(0, nz, count)], axis=1)]
+    if include_faces:
+        xs, ys, zs = (0, nx // 2, nx - 1), (0, ny // 2, ny - 1), (0, nz // 2, nz - 1)
+        pts.append(np.array([(x, y, z) for x in xs for y in ys for z in zs]))
+    return np.unique(np.concatenate(pts), axis=0)
