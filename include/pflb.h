@@ -1,0 +1,170 @@
+/*
+ * pflb.h -- C ABI of the phase-field lattice Boltzmann library (AMD gfx950, HIP).
+ *
+ * The library advances the two distribution sets of the conservative Allen-Cahn
+ * phase-field lattice Boltzmann method of Otomo, Zhang and Chen ("Improved
+ * phase-field-based lattice Boltzmann models with a filtered collision operator"):
+ * the order-parameter set h_i (Eq. 1-4) and the hydrodynamic set g_i with the
+ * filtered single-relaxation-time collision (Eqs. 5-12) and the high-order
+ * equilibrium correction (Eq. 13), on D2Q9 or D3Q19, with central differences for
+ * grad(phi) and lap(phi) (Section 2).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer unless its comment says "host".
+ *     The caller owns all device memory; the library only borrows pointers.
+ *   - Fields are float32, structure of arrays, site index s = (z*ny + y)*nx + x
+ *     (D2Q9: s = y*nx + x).  A vector field is [D][N] (D = 2 or 3, N = nx*ny*nz).
+ *     A distribution set in "pre-collision form" is [Q][N]: h_i(x) at step n, after
+ *     streaming and before collision, velocity ordering:
+ *       D2Q9 : 0 rest, then (+x,-x), (+y,-y), (+x+y,-x-y), (+x-y,-x+y)
+ *       D3Q19: 0 rest, then (+x,-x), (+y,-y), (+z,-z), (+x+y,-x-y), (+x-y,-x+y),
+ *              (+x+z,-x-z), (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z)
+ *     so that the opposite of i >= 1 is i+1 (i odd) or i-1 (i even).  T = 1/3.
+ *   - Functions return 0 (PFLB_OK) or a negative PFLB_ERR_* code; no exception
+ *     crosses the ABI.  pflb_last_error() describes the last failure of a context.
+ *     Asynchronous device faults surface at the next synchronous call as
+ *     PFLB_ERR_DEVICE.
+ *   - Work is enqueued on the given HIP stream (hipStream_t passed as void*; NULL is
+ *     the null stream).  Calls that return host values synchronise that stream.
+ *   - Calls on one context must not overlap (a context is not thread-safe).
+ */
+#ifndef PFLB_H
+#define PFLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PFLB_OK             0
+#define PFLB_ERR_PARAM     -1  /* invalid parameter or argument                     */
+#define PFLB_ERR_ALIGN     -2  /* device pointer not 256-byte aligned               */
+#define PFLB_ERR_UNBOUND   -3  /* buffers not bound yet                             */
+#define PFLB_ERR_DEVICE    -4  /* a HIP call or kernel launch failed                */
+#define PFLB_ERR_NONFINITE -5  /* a non-finite population was found                 */
+#define PFLB_ERR_IO        -6  /* checkpoint file could not be read or written      */
+#define PFLB_ERR_NOMEM     -7  /* host allocation failed                            */
+
+/* ---- enumerations ---- */
+#define PFLB_BC_PERIODIC 0
+#define PFLB_BC_WALL     1     /* no-slip wall half a site outside the last layer   */
+
+#define PFLB_STORE_FP32  0     /* populations stored as float32                     */
+#define PFLB_STORE_FP16S 1     /* rest population float32, moving populations fp16 */
+                               /* deviations from (w_i/w_0) x rest population      */
+
+/* buffer ids for pflb_required_bytes / pflb_bind */
+#define PFLB_BUF_H0      0     /* h set, buffer A                                   */
+#define PFLB_BUF_H1      1     /* h set, buffer B                                   */
+#define PFLB_BUF_G0      2     /* g set, buffer A                                   */
+#define PFLB_BUF_G1      3     /* g set, buffer B                                   */
+#define PFLB_BUF_SCRATCH 4     /* reduction partial sums and flags                  */
+#define PFLB_NBUF        5
+
+/*
+ * Model and domain parameters (Section 2; Section 4 gives values per case).
+ *   lattice      9 (D2Q9) or 19 (D3Q19)
+ *   nx, ny, nz   sites per axis (nz = 1 for D2Q9), each >= 1
+ *   bc[3]        boundary per axis x, y, z: PFLB_BC_PERIODIC or PFLB_BC_WALL (both
+ *                faces of an axis alike; walls: halfway bounce-back for h and g,
+ *                phi outside a wall equals phi at the adjacent site)
+ *   rho_L,rho_H  densities of the light (phi = 0) and heavy (phi = 1) phase, > 0
+ *   nu_L, nu_H   kinematic viscosities; tau = nu/T + 1/2 must exceed 1/2
+ *   M            mobility (> 0); tau_phi = M/T + 1/2 (Eq. 1)
+ *   W            interface thickness (> 0) (Eqs. 4, 8)
+ *   sigma        surface tension (>= 0) (Eq. 8)
+ *   g[3]         gravitational acceleration; the external force is rho(phi) g
+ *   eps          the small constant of the interface normal (text after Eq. 4)
+ *   hoc          1: high-order equilibrium correction and modified velocity (Eq. 13)
+ *   dtheta_C     C of the dense-bubble correction (Eq. 14); 0 switches it off
+ *   storage      PFLB_STORE_FP32 or PFLB_STORE_FP16S
+ *   scale_log2   power-of-two scale exponents of the fp16 deviations of h and g
+ *                (FP16S only; each in [-14, 24])
+ */
+typedef struct pflb_params {
+    int lattice;
+    int nx, ny, nz;
+    int bc[3];
+    double rho_L, rho_H;
+    double nu_L, nu_H;
+    double M, W, sigma;
+    double g[3];
+    double eps;
+    int hoc;
+    double dtheta_C;
+    int storage;
+    int scale_log2[2];
+} pflb_params;
+
+typedef struct pflb_ctx pflb_ctx;
+
+/* Validate p and create a context on the current HIP device.  On failure returns
+ * PFLB_ERR_PARAM and sets *out = NULL.  The library owns the context. */
+int pflb_create(const pflb_params* p, pflb_ctx** out);
+
+/* Destroy a context (NULL is ignored).  Device memory stays the caller's. */
+void pflb_destroy(pflb_ctx* ctx);
+
+/* Text of the last error on ctx (static string for ctx == NULL). */
+const char* pflb_last_error(const pflb_ctx* ctx);
+
+/* Bytes the caller must allocate for buffer `buffer` (PFLB_BUF_*) with parameters
+ * p, or 0 if p is invalid. */
+size_t pflb_required_bytes(const pflb_params* p, int buffer);
+
+/* Bind the PFLB_NBUF caller-allocated device buffers, in PFLB_BUF_* order, each at
+ * least pflb_required_bytes() long and 256-byte aligned.  The pointers are borrowed
+ * until pflb_destroy or the next pflb_bind. */
+int pflb_bind(pflb_ctx* ctx, void* const* dev_ptrs, int n);
+
+/* Pre-collision equilibrium distributions from macroscopic fields (the paper does
+ * not state its start; this evaluates Eqs. 2-4 and 6-7 plus Eq. 13 at every site with
+ * u := u0 and P := P0, so that the state reads back u0 and P0).
+ *   phi [N], u [D][N], P [N] (NULL: zero) -> h_out [Q][N], g_out [Q][N]. */
+int pflb_equilibrium(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
+                     float* h_out, float* g_out, void* stream);
+
+/* Load a pre-collision state h [Q][N], g [Q][N] as the state at step 0. */
+int pflb_set_state(pflb_ctx* ctx, const float* h, const float* g, void* stream);
+
+/* Write the current pre-collision state to h [Q][N], g [Q][N]. */
+int pflb_get_state(pflb_ctx* ctx, float* h, float* g, void* stream);
+
+/* Start from macroscopic fields: pflb_equilibrium into `work` (2*Q*N floats of
+ * caller device memory) followed by pflb_set_state. */
+int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
+                     float* work, void* stream);
+
+/* Enqueue nsteps fused stream-and-collide steps of both sets (Eqs. 1 and 10 with
+ * the central differences of Section 2).  Returns launch errors only. */
+int pflb_step(pflb_ctx* ctx, int nsteps, void* stream);
+
+/* Macroscopic fields of the current state (end of Section 2):
+ *   phi [N]   = sum_i h_i                           (required; also used as input
+ *                                                    of the second pass)
+ *   P   [N]   = T sum_i g_i + (T rho_dif/2) u.grad(phi)          (NULL: skip)
+ *   J   [D][N]= sum_i c_i g_i + (mu grad(phi) + F_ex)/2 (= rho u)  (NULL: skip)
+ *   u   [D][N]= J / (rho + lap(rho)/4) (J/rho with hoc = 0)        (NULL: skip) */
+int pflb_read(pflb_ctx* ctx, float* phi, float* P, float* J, float* u, void* stream);
+
+/* sum_x phi(x) accumulated in float64 in a fixed order (bitwise reproducible), and
+ * *nonfinite = 1 if any population of either set is NaN or Inf.  Synchronous.
+ * Returns PFLB_ERR_NONFINITE when *nonfinite is set. */
+int pflb_mass(pflb_ctx* ctx, double* sum_phi, int* nonfinite, void* stream);
+
+/* Steps completed since the last pflb_set_state / pflb_init_fields / pflb_load. */
+long long pflb_step_count(const pflb_ctx* ctx);
+
+/* Checkpoint the raw state (both sets, storage format, step count, parameters) to a
+ * host file / restore it into a context created with identical parameters.
+ * Synchronous.  Resuming is bitwise identical to not stopping. */
+int pflb_save(pflb_ctx* ctx, const char* path, void* stream);
+int pflb_load(pflb_ctx* ctx, const char* path, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFLB_H */

@@ -403,21 +403,21 @@ def step_sites(prm, h, g, sites):
         pop[:, i] = np.where(solid, lat.opp[i], i)
     ups = src.reshape(-1, 3)
     # pre-collision populations and phi stencil of each upstream site
-    hf = h.reshape(lat.Q, -1).astype(np.float64)
-    gf = g.reshape(lat.Q, -1).astype(np.float64)
+    hf = h.reshape(lat.Q, -1)
+    gf = g.reshape(lat.Q, -1)
 
     def lin(x, y, z):
         return (z * ny + y) * nx + x
 
     idx = lin(ups[:, 0], ups[:, 1], ups[:, 2])
-    hu = hf[:, idx]
-    gu = gf[:, idx]
+    hu = hf[:, idx].astype(np.float64)
+    gu = gf[:, idx].astype(np.float64)
     phi_nb = np.empty((lat.Q, len(ups)))
     for k in range(lat.Q):
         x = _map_axis(ups[:, 0] + lat.c[k, 0], nx, prm.bc[0])
         y = _map_axis(ups[:, 1] + lat.c[k, 1], ny, prm.bc[1])
         z = _map_axis(ups[:, 2] + lat.c[k, 2], nz, prm.bc[2])
-        phi_nb[k] = hf[:, lin(x, y, z)].sum(0)
+        phi_nb[k] = hf[:, lin(x, y, z)].astype(np.float64).sum(0)
     hstar, gstar, _ = collide(lat, prm, hu, gu, phi_nb)
     hstar = hstar.reshape(lat.Q, S, lat.Q)
     gstar = gstar.reshape(lat.Q, S, lat.Q)

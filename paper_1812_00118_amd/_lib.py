@@ -1,0 +1,87 @@
+"""ctypes declarations of the C ABI in include/pflb.h."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpflb.so")
+
+OK = 0
+ERRORS = {-1: "PFLB_ERR_PARAM", -2: "PFLB_ERR_ALIGN", -3: "PFLB_ERR_UNBOUND",
+          -4: "PFLB_ERR_DEVICE", -5: "PFLB_ERR_NONFINITE", -6: "PFLB_ERR_IO",
+          -7: "PFLB_ERR_NOMEM"}
+ERR_NONFINITE = -5
+
+BC_PERIODIC, BC_WALL = 0, 1
+STORE_FP32, STORE_FP16S = 0, 1
+NBUF = 5
+
+
+class PflbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("bc", ctypes.c_int * 3),
+                ("rho_L", ctypes.c_double), ("rho_H", ctypes.c_double),
+                ("nu_L", ctypes.c_double), ("nu_H", ctypes.c_double),
+                ("M", ctypes.c_double), ("W", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("g", ctypes.c_double * 3),
+                ("eps", ctypes.c_double),
+                ("hoc", ctypes.c_int),
+                ("dtheta_C", ctypes.c_double),
+                ("storage", ctypes.c_int),
+                ("scale_log2", ctypes.c_int * 2)]
+
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "pflb_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(_vp)]),
+    "pflb_destroy": (None, [_vp]),
+    "pflb_last_error": (ctypes.c_char_p, [_vp]),
+    "pflb_required_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params), ctypes.c_int]),
+    "pflb_bind": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int]),
+    "pflb_equilibrium": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pflb_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pflb_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pflb_init_fields": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pflb_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "pflb_read": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pflb_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int), _vp]),
+    "pflb_step_count": (ctypes.c_longlong, [_vp]),
+    "pflb_save": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
+    "pflb_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH, build_if_missing=True):
+    """Load libpflb.so (building it first only if no built library exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        if not build_if_missing:
+            raise OSError(f"{path} is not built")
+        from .build_lib import build
+        build()
+    so = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(so, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = so
+    return so
+
+
+def lib():
+    return load_library()
+
+
+def exported_symbols():
+    return list(_SIGS)

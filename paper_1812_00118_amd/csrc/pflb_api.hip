@@ -1,0 +1,403 @@
+// C-ABI layer of the phase-field lattice Boltzmann library: parameter validation and
+// derivation, buffer binding, launch orchestration, read-out, checkpointing.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pflb.h"
+#include "pflb_internal.hpp"
+
+using namespace pflb;
+
+struct pflb_ctx {
+    pflb_params p;
+    int Q = 0, D = 0;
+    uint32_t N = 0;
+    Launch L{};
+    void* buf[PFLB_NBUF] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t bytes[PFLB_NBUF] = {0, 0, 0, 0, 0};
+    bool bound = false;
+    int cur = 0;              // 0: state in the A buffers, 1: in the B buffers
+    long long steps = 0;
+    std::string err;
+};
+
+namespace {
+
+const double kT = 1.0 / 3.0;
+
+bool finite(double v) { return isfinite(v) != 0; }
+
+// Returns an empty string if p is valid, else the reason.
+std::string check_params(const pflb_params* p) {
+    if (!p) return "params is NULL";
+    if (p->lattice != 9 && p->lattice != 19) return "lattice must be 9 or 19";
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "nx, ny, nz must be >= 1";
+    if (p->lattice == 9 && p->nz != 1) return "D2Q9 needs nz = 1";
+    const double n = (double)p->nx * p->ny * p->nz;
+    if (n > 2147483647.0 - 4096.0) return "domain larger than 2^31 sites";
+    for (int a = 0; a < 3; ++a)
+        if (p->bc[a] != PFLB_BC_PERIODIC && p->bc[a] != PFLB_BC_WALL) return "bc must be 0 or 1";
+    if (!(finite(p->rho_L) && p->rho_L > 0) || !(finite(p->rho_H) && p->rho_H > 0))
+        return "densities must be finite and > 0";
+    if (!(finite(p->nu_L) && p->nu_L > 0) || !(finite(p->nu_H) && p->nu_H > 0))
+        return "viscosities must be > 0 (tau = nu/T + 1/2 > 1/2)";
+    if (!(finite(p->M) && p->M > 0)) return "mobility M must be > 0";
+    if (!(finite(p->W) && p->W > 0)) return "interface thickness W must be > 0";
+    if (!(finite(p->sigma) && p->sigma >= 0)) return "sigma must be >= 0";
+    if (!(finite(p->eps) && p->eps > 0)) return "eps must be > 0";
+    for (int a = 0; a < 3; ++a)
+        if (!finite(p->g[a])) return "gravity must be finite";
+    if (p->hoc != 0 && p->hoc != 1) return "hoc must be 0 or 1";
+    if (!finite(p->dtheta_C)) return "dtheta_C must be finite";
+    if (p->storage != PFLB_STORE_FP32 && p->storage != PFLB_STORE_FP16S)
+        return "storage must be PFLB_STORE_FP32 or PFLB_STORE_FP16S";
+    if (p->storage == PFLB_STORE_FP16S)
+        for (int k = 0; k < 2; ++k)
+            if (p->scale_log2[k] < -14 || p->scale_log2[k] > 24) return "scale_log2 out of [-14, 24]";
+    return "";
+}
+
+uint32_t pop_stride(uint32_t N) { return (N + 63u) & ~63u; }
+
+size_t set_bytes(const pflb_params* p, uint32_t N) {
+    const size_t S = pop_stride(N);
+    if (p->storage == PFLB_STORE_FP16S) return S * 4 + (size_t)(p->lattice - 1) * S * 2;
+    return (size_t)p->lattice * S * 4;
+}
+
+size_t scratch_bytes() {
+    const size_t b = mass_scratch_bytes();
+    return (b + 65535) & ~(size_t)65535;
+}
+
+uint32_t sites(const pflb_params* p) { return (uint32_t)p->nx * p->ny * p->nz; }
+
+void derive(pflb_ctx* c) {
+    const pflb_params& p = c->p;
+    c->Q = p.lattice;
+    c->D = p.lattice == 19 ? 3 : 2;
+    c->N = sites(&p);
+    Geom& G = c->L.G;
+    if (p.lattice == 19) {
+        G.nx = p.nx; G.ny = p.ny; G.nz = p.nz;
+        G.wx = p.bc[0]; G.wy = p.bc[1]; G.wz = p.bc[2];
+    } else {  // user (x, y) -> internal (x, z)
+        G.nx = p.nx; G.ny = 1; G.nz = p.ny;
+        G.wx = p.bc[0]; G.wy = 0; G.wz = p.bc[1];
+    }
+    G.S = pop_stride(c->N);
+    G.sxy = (uint32_t)G.nx * (uint32_t)G.ny;
+    Model& m = c->L.m;
+    const double tau_L = p.nu_L / kT + 0.5, tau_H = p.nu_H / kT + 0.5;
+    const double tau_phi = p.M / kT + 0.5;
+    m.rho_L = (float)p.rho_L;
+    m.rho_dif = (float)(p.rho_H - p.rho_L);
+    m.itau_L = (float)(1.0 / tau_L);
+    m.itau_dif = (float)(1.0 / tau_H - 1.0 / tau_L);
+    m.om_phi = (float)(1.0 / tau_phi);
+    m.mu_a = (float)(48.0 * p.sigma / p.W);
+    m.mu_b = (float)(1.5 * p.sigma * p.W);
+    m.th_a = (float)(p.M / kT / p.W);
+    m.dth = (float)(p.dtheta_C * p.M / kT);
+    m.eps = (float)p.eps;
+    if (p.lattice == 19) {
+        m.gx = (float)p.g[0]; m.gy = (float)p.g[1]; m.gz = (float)p.g[2];
+    } else {
+        m.gx = (float)p.g[0]; m.gy = 0.0f; m.gz = (float)p.g[1];
+    }
+    m.beta = p.hoc ? 1.0f : 0.0f;
+    Codec& cd = c->L.cd;
+    if (p.storage == PFLB_STORE_FP16S) {
+        cd.sh = ldexpf(1.0f, p.scale_log2[0]);
+        cd.ish = ldexpf(1.0f, -p.scale_log2[0]);
+        cd.sg = ldexpf(1.0f, p.scale_log2[1]);
+        cd.isg = ldexpf(1.0f, -p.scale_log2[1]);
+    } else {
+        cd.sh = cd.ish = cd.sg = cd.isg = 1.0f;
+    }
+    c->L.q = p.lattice;
+    c->L.half = p.storage == PFLB_STORE_FP16S;
+    // planes per workgroup: enough workgroups to fill 256 CUs with ~16 waves each
+    const long cols = (long)((G.nx + 63) / 64) * (p.lattice == 19 ? (G.ny + 3) / 4 : 1);
+    const long waves_per_wg = p.lattice == 19 ? 4 : 1;
+    const long want_wgs = 256L * 16 / waves_per_wg;
+    long chunks = (want_wgs + cols - 1) / cols;
+    if (chunks < 1) chunks = 1;
+    long bz = (G.nz + chunks - 1) / chunks;
+    if (bz < 4) bz = 4;
+    if (bz > G.nz) bz = G.nz;
+    const char* env = getenv("PFLB_BZ");
+    if (env && atoi(env) > 0) bz = atoi(env);
+    c->L.bz = (int)bz;
+}
+
+int fail(pflb_ctx* c, int code, const std::string& what) {
+    if (c) c->err = what;
+    return code;
+}
+
+int hip_fail(pflb_ctx* c, hipError_t e, const char* where) {
+    return fail(c, PFLB_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+int need_bound(pflb_ctx* c) {
+    if (!c) return PFLB_ERR_PARAM;
+    if (!c->bound) return fail(c, PFLB_ERR_UNBOUND, "buffers not bound");
+    return PFLB_OK;
+}
+
+void* hbuf(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_H0 : PFLB_BUF_H1]; }
+void* gbuf(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_G0 : PFLB_BUF_G1]; }
+
+struct FileHeader {
+    char magic[8];
+    int lattice, nx, ny, nz, bc[3], storage, scale_log2[2], hoc;
+    double rho_L, rho_H, nu_L, nu_H, M, W, sigma, g[3], eps, dtheta_C;
+    long long steps;
+    unsigned long long set_bytes;
+};
+
+void fill_header(const pflb_ctx* c, FileHeader* h) {
+    memset(h, 0, sizeof(*h));
+    memcpy(h->magic, "PFLBCK01", 8);
+    const pflb_params& p = c->p;
+    h->lattice = p.lattice; h->nx = p.nx; h->ny = p.ny; h->nz = p.nz;
+    for (int a = 0; a < 3; ++a) { h->bc[a] = p.bc[a]; h->g[a] = p.g[a]; }
+    h->storage = p.storage;
+    h->scale_log2[0] = p.storage == PFLB_STORE_FP16S ? p.scale_log2[0] : 0;
+    h->scale_log2[1] = p.storage == PFLB_STORE_FP16S ? p.scale_log2[1] : 0;
+    h->hoc = p.hoc;
+    h->rho_L = p.rho_L; h->rho_H = p.rho_H; h->nu_L = p.nu_L; h->nu_H = p.nu_H;
+    h->M = p.M; h->W = p.W; h->sigma = p.sigma; h->eps = p.eps; h->dtheta_C = p.dtheta_C;
+    h->steps = c->steps;
+    h->set_bytes = set_bytes(&c->p, c->N);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pflb_create(const pflb_params* p, pflb_ctx** out) {
+    if (!out) return PFLB_ERR_PARAM;
+    *out = nullptr;
+    if (!check_params(p).empty()) return PFLB_ERR_PARAM;
+    pflb_ctx* c = new (std::nothrow) pflb_ctx();
+    if (!c) return PFLB_ERR_NOMEM;
+    c->p = *p;
+    derive(c);
+    c->bytes[PFLB_BUF_H0] = c->bytes[PFLB_BUF_H1] = set_bytes(p, c->N);
+    c->bytes[PFLB_BUF_G0] = c->bytes[PFLB_BUF_G1] = set_bytes(p, c->N);
+    c->bytes[PFLB_BUF_SCRATCH] = scratch_bytes();
+    *out = c;
+    return PFLB_OK;
+}
+
+void pflb_destroy(pflb_ctx* ctx) { delete ctx; }
+
+const char* pflb_last_error(const pflb_ctx* ctx) {
+    if (!ctx) return "no context (pflb_create failed or was not called)";
+    return ctx->err.c_str();
+}
+
+size_t pflb_required_bytes(const pflb_params* p, int buffer) {
+    if (!check_params(p).empty()) return 0;
+    const uint32_t N = sites(p);
+    switch (buffer) {
+        case PFLB_BUF_H0: case PFLB_BUF_H1: case PFLB_BUF_G0: case PFLB_BUF_G1:
+            return set_bytes(p, N);
+        case PFLB_BUF_SCRATCH:
+            return scratch_bytes();
+        default:
+            return 0;
+    }
+}
+
+int pflb_bind(pflb_ctx* c, void* const* dev_ptrs, int n) {
+    if (!c) return PFLB_ERR_PARAM;
+    if (!dev_ptrs || n != PFLB_NBUF) return fail(c, PFLB_ERR_PARAM, "pflb_bind needs PFLB_NBUF pointers");
+    for (int k = 0; k < n; ++k) {
+        if (!dev_ptrs[k]) return fail(c, PFLB_ERR_PARAM, "NULL buffer pointer");
+        if (!aligned(dev_ptrs[k])) return fail(c, PFLB_ERR_ALIGN, "buffer not 256-byte aligned");
+    }
+    for (int k = 0; k < n; ++k) c->buf[k] = dev_ptrs[k];
+    c->bound = true;
+    c->cur = 0;
+    return PFLB_OK;
+}
+
+int pflb_equilibrium(pflb_ctx* c, const float* phi, const float* u, const float* P,
+                     float* h_out, float* g_out, void* stream) {
+    if (!c) return PFLB_ERR_PARAM;
+    if (!phi || !u || !h_out || !g_out) return fail(c, PFLB_ERR_PARAM, "NULL field pointer");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    hipError_t e = launch_equilibrium(a, c->N, phi, u, P, h_out, g_out);
+    if (e != hipSuccess) return hip_fail(c, e, "equilibrium launch");
+    return PFLB_OK;
+}
+
+int pflb_set_state(pflb_ctx* c, const float* h, const float* g, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!h || !g) return fail(c, PFLB_ERR_PARAM, "NULL distribution pointer");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    c->cur = 0;
+    hipError_t e = launch_set_state(a, c->N, h, g, hbuf(c), gbuf(c));
+    if (e != hipSuccess) return hip_fail(c, e, "set_state launch");
+    c->steps = 0;
+    return PFLB_OK;
+}
+
+int pflb_get_state(pflb_ctx* c, float* h, float* g, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!h || !g) return fail(c, PFLB_ERR_PARAM, "NULL distribution pointer");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    hipError_t e = launch_get_state(a, c->N, hbuf(c), gbuf(c), h, g);
+    if (e != hipSuccess) return hip_fail(c, e, "get_state launch");
+    return PFLB_OK;
+}
+
+int pflb_init_fields(pflb_ctx* c, const float* phi, const float* u, const float* P, float* work,
+                     void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!work) return fail(c, PFLB_ERR_PARAM, "NULL work buffer");
+    float* h = work;
+    float* g = work + (size_t)c->Q * c->N;
+    r = pflb_equilibrium(c, phi, u, P, h, g, stream);
+    if (r) return r;
+    return pflb_set_state(c, h, g, stream);
+}
+
+int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (nsteps < 0) return fail(c, PFLB_ERR_PARAM, "nsteps < 0");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    for (int s = 0; s < nsteps; ++s) {
+        void* hs = hbuf(c);
+        void* gs = gbuf(c);
+        void* hd = c->buf[c->cur == 0 ? PFLB_BUF_H1 : PFLB_BUF_H0];
+        void* gd = c->buf[c->cur == 0 ? PFLB_BUF_G1 : PFLB_BUF_G0];
+        hipError_t e = launch_step(a, hs, gs, hd, gd);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        c->cur ^= 1;
+        c->steps += 1;
+    }
+    return PFLB_OK;
+}
+
+int pflb_read(pflb_ctx* c, float* phi, float* P, float* J, float* u, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!phi) return fail(c, PFLB_ERR_PARAM, "phi output is required");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    hipError_t e = launch_read(a, c->N, hbuf(c), gbuf(c), phi, P, J, u);
+    if (e != hipSuccess) return hip_fail(c, e, "read launch");
+    return PFLB_OK;
+}
+
+int pflb_mass(pflb_ctx* c, double* sum_phi, int* nonfinite, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!sum_phi || !nonfinite) return fail(c, PFLB_ERR_PARAM, "NULL output pointer");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    hipError_t e = launch_mass(a, c->N, hbuf(c), gbuf(c), c->buf[PFLB_BUF_SCRATCH]);
+    if (e != hipSuccess) return hip_fail(c, e, "mass launch");
+    const char* base = static_cast<const char*>(c->buf[PFLB_BUF_SCRATCH]);
+    double s = 0.0;
+    int f = 0;
+    e = hipMemcpyAsync(&s, base + mass_result_offset(), sizeof(double), hipMemcpyDeviceToHost,
+                       a.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&f, base + mass_flag_offset(), sizeof(int), hipMemcpyDeviceToHost,
+                           a.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
+    if (e != hipSuccess) return hip_fail(c, e, "mass read-back");
+    *sum_phi = s;
+    *nonfinite = f;
+    if (f) return fail(c, PFLB_ERR_NONFINITE, "non-finite population in the state");
+    return PFLB_OK;
+}
+
+long long pflb_step_count(const pflb_ctx* c) { return c ? c->steps : -1; }
+
+int pflb_save(pflb_ctx* c, const char* path, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!path) return fail(c, PFLB_ERR_PARAM, "NULL path");
+    const size_t nb = set_bytes(&c->p, c->N);
+    std::vector<char> host;
+    try {
+        host.resize(2 * nb);
+    } catch (...) {
+        return fail(c, PFLB_ERR_NOMEM, "host buffer for checkpoint");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(host.data(), hbuf(c), nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data() + nb, gbuf(c), nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
+    FileHeader h;
+    fill_header(c, &h);
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, PFLB_ERR_IO, std::string("cannot open ") + path);
+    bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(host.data(), 1, 2 * nb, f) == 2 * nb;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(c, PFLB_ERR_IO, std::string("cannot write ") + path);
+    return PFLB_OK;
+}
+
+int pflb_load(pflb_ctx* c, const char* path, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!path) return fail(c, PFLB_ERR_PARAM, "NULL path");
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(c, PFLB_ERR_IO, std::string("cannot open ") + path);
+    FileHeader h, want;
+    fill_header(c, &want);
+    if (fread(&h, sizeof(h), 1, f) != 1) {
+        fclose(f);
+        return fail(c, PFLB_ERR_IO, "short checkpoint header");
+    }
+    const long long steps = h.steps;
+    h.steps = want.steps;
+    if (memcmp(&h, &want, sizeof(h)) != 0) {
+        fclose(f);
+        return fail(c, PFLB_ERR_PARAM, "checkpoint parameters differ from the context's");
+    }
+    const size_t nb = set_bytes(&c->p, c->N);
+    std::vector<char> host;
+    try {
+        host.resize(2 * nb);
+    } catch (...) {
+        fclose(f);
+        return fail(c, PFLB_ERR_NOMEM, "host buffer for checkpoint");
+    }
+    const bool ok = fread(host.data(), 1, 2 * nb, f) == 2 * nb;
+    fclose(f);
+    if (!ok) return fail(c, PFLB_ERR_IO, "short checkpoint body");
+    c->cur = 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(hbuf(c), host.data(), nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(gbuf(c), host.data() + nb, nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
+    c->steps = steps;
+    return PFLB_OK;
+}
+
+}  // extern "C"

@@ -108,6 +108,22 @@ def centre_of(shape):
     return ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0 if nz > 1 else 0.0)
 
 
+def hydrostatic_pressure(cfg, phi):
+    """Pressure in hydrostatic balance with gravity, dP/ds = rho(phi) g along the gravity
+    axis (trapezoidal sum from the first site, rho = rho_L + phi (rho_H - rho_L)), shifted
+    to zero mean.  A start with P = 0 under gravity launches a pressure shock from the
+    walls that nucleates spurious dense bubbles."""
+    g = np.asarray(cfg["g"], dtype=np.float64)
+    axis = int(np.argmax(np.abs(g)))
+    if g[axis] == 0.0:
+        return np.zeros_like(phi)
+    rho = cfg["rho_L"] + phi * (cfg["rho_H"] - cfg["rho_L"])
+    np_axis = {0: 2, 1: 1, 2: 0}[axis]            # field arrays are (z, y, x)
+    f = rho * g[axis]
+    P = np.cumsum(f, axis=np_axis) - 0.5 * f - 0.5 * np.take(f, [0], axis=np_axis)
+    return P - P.mean()
+
+
 def fields_static_droplet(cfg):
     phi = drop_profile(cfg["shape"], centre_of(cfg["shape"]), cfg["R"], cfg["W"])
     u = np.zeros((3,) + phi.shape)
@@ -120,7 +136,7 @@ def fields_rayleigh_taylor(cfg):
     y0 = (ny - 1) / 2.0 + cfg["amp"] * np.cos(2.0 * np.pi * x / nx)
     phi = 0.5 + 0.5 * np.tanh(2.0 * (y - y0) / cfg["W"])      # heavy fluid on top
     u = np.zeros((3,) + phi.shape)
-    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+    return _f32(phi), _f32(u), _f32(hydrostatic_pressure(cfg, phi))
 
 
 def fields_rising_bubble(cfg):
@@ -128,7 +144,7 @@ def fields_rising_bubble(cfg):
     centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, nz / 4.0)
     phi = drop_profile(cfg["shape"], centre, cfg["R"], cfg["W"], inside=0.0)
     u = np.zeros((3,) + phi.shape)
-    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+    return _f32(phi), _f32(u), _f32(hydrostatic_pressure(cfg, phi))
 
 
 def fields_droplet_impact(cfg):
