@@ -52,16 +52,19 @@ extern "C" {
 #define PFLB_BC_WALL     1     /* no-slip wall half a site outside the last layer   */
 
 #define PFLB_STORE_FP32  0     /* populations stored as float32                     */
-#define PFLB_STORE_FP16S 1     /* rest population float32, moving populations fp16 */
-                               /* deviations from (w_i/w_0) x rest population      */
+#define PFLB_STORE_FP16S 1     /* per site a float32 reference level R ~ phi/4 per  */
+                               /* set; populations stored as fp16 deviations from  */
+                               /* r_i R (dyadic r_i ~ 4 w_i, sum r_i = 4), the rest */
+                               /* population as r_0 R; FP32 arithmetic throughout   */
 
-/* buffer ids for pflb_required_bytes / pflb_bind */
-#define PFLB_BUF_H0      0     /* h set, buffer A                                   */
-#define PFLB_BUF_H1      1     /* h set, buffer B                                   */
-#define PFLB_BUF_G0      2     /* g set, buffer A                                   */
-#define PFLB_BUF_G1      3     /* g set, buffer B                                   */
-#define PFLB_BUF_SCRATCH 4     /* reduction partial sums and flags                  */
-#define PFLB_NBUF        5
+/* buffer ids for pflb_required_bytes / pflb_bind.  A state buffer holds both
+ * distribution sets interleaved per population (FP32: float2 (h_i, g_i) per slot;
+ * FP16S: a float2 pair of reference levels per site, then half2 deviation pairs);
+ * the step reads one state buffer and writes the other. */
+#define PFLB_BUF_STATE0  0
+#define PFLB_BUF_STATE1  1
+#define PFLB_BUF_SCRATCH 2     /* reduction partial sums and flags                  */
+#define PFLB_NBUF        3
 
 /*
  * Model and domain parameters (Section 2; Section 4 gives values per case).

@@ -13,7 +13,7 @@ ERR_NONFINITE = -5
 
 BC_PERIODIC, BC_WALL = 0, 1
 STORE_FP32, STORE_FP16S = 0, 1
-NBUF = 5
+NBUF = 3
 
 
 class PflbError(RuntimeError):

@@ -18,10 +18,10 @@ struct pflb_ctx {
     int Q = 0, D = 0;
     uint32_t N = 0;
     Launch L{};
-    void* buf[PFLB_NBUF] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t bytes[PFLB_NBUF] = {0, 0, 0, 0, 0};
+    void* buf[PFLB_NBUF] = {nullptr, nullptr, nullptr};
+    size_t bytes[PFLB_NBUF] = {0, 0, 0};
     bool bound = false;
-    int cur = 0;              // 0: state in the A buffers, 1: in the B buffers
+    int cur = 0;              // state buffer holding the current state
     long long steps = 0;
     std::string err;
 };
@@ -65,9 +65,7 @@ std::string check_params(const pflb_params* p) {
 uint32_t pop_stride(uint32_t N) { return (N + 63u) & ~63u; }
 
 size_t set_bytes(const pflb_params* p, uint32_t N) {
-    const size_t S = pop_stride(N);
-    if (p->storage == PFLB_STORE_FP16S) return S * 4 + (size_t)(p->lattice - 1) * S * 2;
-    return (size_t)p->lattice * S * 4;
+    return state_bytes(p->lattice, p->storage == PFLB_STORE_FP16S, pop_stride(N));
 }
 
 size_t scratch_bytes() {
@@ -122,14 +120,18 @@ void derive(pflb_ctx* c) {
     }
     c->L.q = p.lattice;
     c->L.half = p.storage == PFLB_STORE_FP16S;
-    // planes per workgroup: enough workgroups to fill 256 CUs with ~16 waves each
+    c->L.tile = 0;
+    const char* tenv = getenv("PFLB_TILE");
+    if (tenv && atoi(tenv) >= 0 && atoi(tenv) <= 3) c->L.tile = atoi(tenv);
+    // planes per workgroup: long z-marches (each chunk re-gathers two extra planes of h)
+    // with about two 4-wave workgroups per CU (8 one-wave workgroups for D2Q9); measured
+    // on the 256x256x128 droplet impact, 64 planes beat 32 and 16
     const long cols = (long)((G.nx + 63) / 64) * (p.lattice == 19 ? (G.ny + 3) / 4 : 1);
-    const long waves_per_wg = p.lattice == 19 ? 4 : 1;
-    const long want_wgs = 256L * 16 / waves_per_wg;
+    const long want_wgs = p.lattice == 19 ? 512 : 2048;
     long chunks = (want_wgs + cols - 1) / cols;
     if (chunks < 1) chunks = 1;
     long bz = (G.nz + chunks - 1) / chunks;
-    if (bz < 4) bz = 4;
+    if (bz < 8) bz = 8;
     if (bz > G.nz) bz = G.nz;
     const char* env = getenv("PFLB_BZ");
     if (env && atoi(env) > 0) bz = atoi(env);
@@ -153,8 +155,8 @@ int need_bound(pflb_ctx* c) {
     return PFLB_OK;
 }
 
-void* hbuf(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_H0 : PFLB_BUF_H1]; }
-void* gbuf(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_G0 : PFLB_BUF_G1]; }
+void* state(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1]; }
+void* other(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_STATE1 : PFLB_BUF_STATE0]; }
 
 struct FileHeader {
     char magic[8];
@@ -166,7 +168,7 @@ struct FileHeader {
 
 void fill_header(const pflb_ctx* c, FileHeader* h) {
     memset(h, 0, sizeof(*h));
-    memcpy(h->magic, "PFLBCK01", 8);
+    memcpy(h->magic, "PFLBCK02", 8);
     const pflb_params& p = c->p;
     h->lattice = p.lattice; h->nx = p.nx; h->ny = p.ny; h->nz = p.nz;
     for (int a = 0; a < 3; ++a) { h->bc[a] = p.bc[a]; h->g[a] = p.g[a]; }
@@ -192,8 +194,7 @@ int pflb_create(const pflb_params* p, pflb_ctx** out) {
     if (!c) return PFLB_ERR_NOMEM;
     c->p = *p;
     derive(c);
-    c->bytes[PFLB_BUF_H0] = c->bytes[PFLB_BUF_H1] = set_bytes(p, c->N);
-    c->bytes[PFLB_BUF_G0] = c->bytes[PFLB_BUF_G1] = set_bytes(p, c->N);
+    c->bytes[PFLB_BUF_STATE0] = c->bytes[PFLB_BUF_STATE1] = set_bytes(p, c->N);
     c->bytes[PFLB_BUF_SCRATCH] = scratch_bytes();
     *out = c;
     return PFLB_OK;
@@ -210,7 +211,7 @@ size_t pflb_required_bytes(const pflb_params* p, int buffer) {
     if (!check_params(p).empty()) return 0;
     const uint32_t N = sites(p);
     switch (buffer) {
-        case PFLB_BUF_H0: case PFLB_BUF_H1: case PFLB_BUF_G0: case PFLB_BUF_G1:
+        case PFLB_BUF_STATE0: case PFLB_BUF_STATE1:
             return set_bytes(p, N);
         case PFLB_BUF_SCRATCH:
             return scratch_bytes();
@@ -250,7 +251,7 @@ int pflb_set_state(pflb_ctx* c, const float* h, const float* g, void* stream) {
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
     c->cur = 0;
-    hipError_t e = launch_set_state(a, c->N, h, g, hbuf(c), gbuf(c));
+    hipError_t e = launch_set_state(a, c->N, h, g, state(c));
     if (e != hipSuccess) return hip_fail(c, e, "set_state launch");
     c->steps = 0;
     return PFLB_OK;
@@ -262,7 +263,7 @@ int pflb_get_state(pflb_ctx* c, float* h, float* g, void* stream) {
     if (!h || !g) return fail(c, PFLB_ERR_PARAM, "NULL distribution pointer");
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
-    hipError_t e = launch_get_state(a, c->N, hbuf(c), gbuf(c), h, g);
+    hipError_t e = launch_get_state(a, c->N, state(c), h, g);
     if (e != hipSuccess) return hip_fail(c, e, "get_state launch");
     return PFLB_OK;
 }
@@ -286,11 +287,7 @@ int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
     for (int s = 0; s < nsteps; ++s) {
-        void* hs = hbuf(c);
-        void* gs = gbuf(c);
-        void* hd = c->buf[c->cur == 0 ? PFLB_BUF_H1 : PFLB_BUF_H0];
-        void* gd = c->buf[c->cur == 0 ? PFLB_BUF_G1 : PFLB_BUF_G0];
-        hipError_t e = launch_step(a, hs, gs, hd, gd);
+        hipError_t e = launch_step(a, state(c), other(c));
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->cur ^= 1;
         c->steps += 1;
@@ -304,7 +301,7 @@ int pflb_read(pflb_ctx* c, float* phi, float* P, float* J, float* u, void* strea
     if (!phi) return fail(c, PFLB_ERR_PARAM, "phi output is required");
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
-    hipError_t e = launch_read(a, c->N, hbuf(c), gbuf(c), phi, P, J, u);
+    hipError_t e = launch_read(a, c->N, state(c), phi, P, J, u);
     if (e != hipSuccess) return hip_fail(c, e, "read launch");
     return PFLB_OK;
 }
@@ -315,7 +312,7 @@ int pflb_mass(pflb_ctx* c, double* sum_phi, int* nonfinite, void* stream) {
     if (!sum_phi || !nonfinite) return fail(c, PFLB_ERR_PARAM, "NULL output pointer");
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
-    hipError_t e = launch_mass(a, c->N, hbuf(c), gbuf(c), c->buf[PFLB_BUF_SCRATCH]);
+    hipError_t e = launch_mass(a, c->N, state(c), c->buf[PFLB_BUF_SCRATCH]);
     if (e != hipSuccess) return hip_fail(c, e, "mass launch");
     const char* base = static_cast<const char*>(c->buf[PFLB_BUF_SCRATCH]);
     double s = 0.0;
@@ -342,20 +339,19 @@ int pflb_save(pflb_ctx* c, const char* path, void* stream) {
     const size_t nb = set_bytes(&c->p, c->N);
     std::vector<char> host;
     try {
-        host.resize(2 * nb);
+        host.resize(nb);
     } catch (...) {
         return fail(c, PFLB_ERR_NOMEM, "host buffer for checkpoint");
     }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(host.data(), hbuf(c), nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.data() + nb, gbuf(c), nb, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(host.data(), state(c), nb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
     FileHeader h;
     fill_header(c, &h);
     FILE* f = fopen(path, "wb");
     if (!f) return fail(c, PFLB_ERR_IO, std::string("cannot open ") + path);
-    bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(host.data(), 1, 2 * nb, f) == 2 * nb;
+    bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(host.data(), 1, nb, f) == nb;
     ok = (fclose(f) == 0) && ok;
     if (!ok) return fail(c, PFLB_ERR_IO, std::string("cannot write ") + path);
     return PFLB_OK;
@@ -382,18 +378,17 @@ int pflb_load(pflb_ctx* c, const char* path, void* stream) {
     const size_t nb = set_bytes(&c->p, c->N);
     std::vector<char> host;
     try {
-        host.resize(2 * nb);
+        host.resize(nb);
     } catch (...) {
         fclose(f);
         return fail(c, PFLB_ERR_NOMEM, "host buffer for checkpoint");
     }
-    const bool ok = fread(host.data(), 1, 2 * nb, f) == 2 * nb;
+    const bool ok = fread(host.data(), 1, nb, f) == nb;
     fclose(f);
     if (!ok) return fail(c, PFLB_ERR_IO, "short checkpoint body");
     c->cur = 0;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(hbuf(c), host.data(), nb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(gbuf(c), host.data() + nb, nb, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(state(c), host.data(), nb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "checkpoint upload");
     c->steps = steps;

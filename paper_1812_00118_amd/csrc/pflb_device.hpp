@@ -124,66 +124,121 @@ struct Codec {                // FP16S: power-of-two scales of the fp16 deviatio
 };
 
 // ---------------------------------------------------------------------------
-// storage codecs
+// storage codecs.  One state buffer holds both sets, interleaved per population so
+// that one load brings h_i and g_i of a slot:
+//   FP32 : [Q][S] float2 (h_i, g_i)
+//   FP16S: [S] float2 (R_h, R_g), then [Q-1][S] half2 (dev_h_i, dev_g_i).  Slot (s, i)
+//          decodes to r_i R(s) + dev_i(s)/scale (i >= 1), the rest slot to r_0 R(s),
+//          with the dyadic r_i ~ 4 w_i of the lattice (sum r_i = 4): R ~ phi/4 is the
+//          site's zeroth-order equilibrium level and the fp16 words hold deviations.
 // ---------------------------------------------------------------------------
 struct StoreF32 {
     static constexpr bool HALF = false;
-    // raw value of slot (site, pop) of direction I (I fixes the weight ratio only)
-    template <class L, int I>
-    __device__ __forceinline__ static float load(const char* __restrict__ b, int pop,
-                                                 uint32_t site, uint32_t S, float) {
-        return reinterpret_cast<const float*>(b)[(size_t)pop * S + site];
-    }
+    __host__ __device__ static constexpr size_t bytes_per_site(int q) { return (size_t)q * 8; }
 };
 
-// FP16S layout of a set: [R: S floats][dev_1..dev_{Q-1}: S halves each].  Slot (s, i)
-// decodes to r_i R(s) + dev_i(s)/scale (i >= 1) and the rest slot to r_0 R(s), with the
-// dyadic r_i ~ 4 w_i of the lattice (sum r_i = 4): R ~ phi/4 is the site's zeroth-order
-// equilibrium level and the fp16 words hold the deviations from it.
 struct StoreF16S {
     static constexpr bool HALF = true;
-    template <class L, int I>
-    __device__ __forceinline__ static float load(const char* __restrict__ b, int pop,
-                                                 uint32_t site, uint32_t S, float iscale) {
-        const float R = reinterpret_cast<const float*>(b)[site];
-        if constexpr (I == 0) {
-            return L::r(0) * R;
-        } else {
-            const __half* dev = reinterpret_cast<const __half*>(b + (size_t)S * 4);
-            const float d = __half2float(dev[(size_t)(pop - 1) * S + site]);
-            return fmaf(d, iscale, L::r(I) * R);
-        }
+    __host__ __device__ static constexpr size_t bytes_per_site(int q) {
+        return 8 + (size_t)(q - 1) * 4;
     }
 };
 
-// Write the Q post-collision values of one site.  FP16S: the moving populations are
-// rounded as deviations from r_i f_0 / r_0, and R is the complement
-// (total - sum of decoded deviations) / 4 (an exact scaling), so that the decoded values
-// of the site sum to `total` up to one float32 rounding (sum(phi) conservation).
+// Encode pre-collision values of a slot-site without the complement (state upload).
 template <class L, class ST>
-__device__ __forceinline__ void store_site(char* __restrict__ b, uint32_t site, uint32_t S,
-                                           const float (&f)[L::Q], float total, float total_lo,
-                                           float scale, float iscale) {
+__device__ __forceinline__ void encode_site(char* __restrict__ b, uint32_t site, uint32_t S,
+                                            const float (&h)[L::Q], const float (&g)[L::Q],
+                                            const Codec& cd) {
     if constexpr (!ST::HALF) {
-        float* o = reinterpret_cast<float*>(b);
+        float2* o = reinterpret_cast<float2*>(b);
         static_for<0, L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            o[(size_t)i * S + site] = f[i];
+            o[(size_t)i * S + site] = make_float2(h[i], g[i]);
         });
     } else {
-        static_assert(dyadic_refs_sum_to_four<L>(), "reference coefficients must sum to 4");
-        __half* dev = reinterpret_cast<__half*>(b + (size_t)S * 4);
-        const float R0 = f[0] * (1.0f / L::r(0));
-        float dsum = 0.0f;
+        __half2* dev = reinterpret_cast<__half2*>(b + (size_t)S * 8);
+        const float Rh = h[0] / L::r(0), Rg = g[0] / L::r(0);
+        reinterpret_cast<float2*>(b)[site] = make_float2(Rh, Rg);
         static_for<1, L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const __half q = __float2half_rn((f[i] - L::r(i) * R0) * scale);
-            dsum += __half2float(q) * iscale;
-            dev[(size_t)(i - 1) * S + site] = q;
+            dev[(size_t)(i - 1) * S + site] =
+                __halves2half2(__float2half_rn((h[i] - L::r(i) * Rh) * cd.sh),
+                               __float2half_rn((g[i] - L::r(i) * Rg) * cd.sg));
         });
-        reinterpret_cast<float*>(b)[site] = 0.25f * ((total - dsum) + total_lo);
     }
 }
+
+// Streaming writer of one site's post-collision pairs.  Pairs arrive rest population
+// first.  FP16S: the moving populations are rounded as deviations from r_i f_0 / r_0,
+// and R is written last as the complement (total - sum of decoded deviations) / 4 (an
+// exact scaling), so that the decoded values of the site sum to the total up to one
+// float32 rounding; for h this keeps sum(phi) conserved as with float32 storage.
+template <class L, class ST>
+struct SiteWriter;
+
+// Streaming stores: the written state is read back only by the next launch, after far
+// more data than the caches hold has passed, so the stores bypass cache allocation.
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void store_nt(char* p, float a, float b) {
+    nt_float2 v = {a, b};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_float2*>(p));
+}
+
+__device__ __forceinline__ void store_nt(char* p, __half2 v) {
+    __builtin_nontemporal_store(*reinterpret_cast<uint32_t*>(&v), reinterpret_cast<uint32_t*>(p));
+}
+
+template <class L>
+struct SiteWriter<L, StoreF32> {
+    char* __restrict__ b;
+    uint32_t off8;                 // site * 8
+    uint32_t S;
+    __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site, uint32_t S_,
+                                          const Codec&, float, float)
+        : b(b_), off8(site * 8u), S(S_) {}
+    template <int I>
+    __device__ __forceinline__ void put(float h, float g) {
+        char* base = b + (size_t)I * ((size_t)S * 8);
+        store_nt(base + off8, h, g);
+    }
+    __device__ __forceinline__ void finish() {}
+};
+
+template <class L>
+struct SiteWriter<L, StoreF16S> {
+    char* __restrict__ b;
+    uint32_t site, S;
+    const Codec& cd;
+    float th, th_lo;               // h total (phi, as hi + lo)
+    float Rh0, Rg0, dh, dg;
+    double tg;                     // g total
+    __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site_, uint32_t S_,
+                                          const Codec& cd_, float th_, float th_lo_)
+        : b(b_), site(site_), S(S_), cd(cd_), th(th_), th_lo(th_lo_), Rh0(0.f), Rg0(0.f),
+          dh(0.f), dg(0.f), tg(0.0) {}
+    template <int I>
+    __device__ __forceinline__ void put(float h, float g) {
+        static_assert(dyadic_refs_sum_to_four<L>(), "reference coefficients must sum to 4");
+        tg += (double)g;
+        if constexpr (I == 0) {
+            Rh0 = h * (1.0f / L::r(0));
+            Rg0 = g * (1.0f / L::r(0));
+        } else {
+            const __half qh = __float2half_rn((h - L::r(I) * Rh0) * cd.sh);
+            const __half qg = __float2half_rn((g - L::r(I) * Rg0) * cd.sg);
+            dh += __half2float(qh) * cd.ish;
+            dg += __half2float(qg) * cd.isg;
+            char* base = b + (size_t)S * 8 + (size_t)(I - 1) * ((size_t)S * 4);
+            store_nt(base + site * 4u, __halves2half2(qh, qg));
+        }
+    }
+    __device__ __forceinline__ void finish() {
+        const float tg_hi = (float)tg;
+        const float tg_lo = (float)(tg - (double)tg_hi);
+        store_nt(b + site * 8u, 0.25f * ((th - dh) + th_lo), 0.25f * ((tg_hi - dg) + tg_lo));
+    }
+};
 
 // ---------------------------------------------------------------------------
 // boundary-aware gather
@@ -231,33 +286,141 @@ __device__ __forceinline__ ZRow make_zrow(const Geom& G, int z) {
     return r;
 }
 
-// Gather the Q pre-collision populations of one site.
-template <class L, class ST, bool WALLS>
-__device__ __forceinline__ void pull_site(const char* __restrict__ b, const Geom& G,
-                                          const Col& c, const ZRow& r, float iscale,
-                                          float (&f)[L::Q]) {
+// Which boundaries a kernel variant handles: walls across x or y (a per-lane test) and
+// walls across z (uniform over a plane, so a scalar test in the z-marching kernel).
+enum WallSet { WALLS_NONE = 0, WALLS_Z = 1, WALLS_XY = 2, WALLS_XYZ = 3 };
+
+// Upstream slot of direction I for the site (c, r): (site - c_I, I), or (site, opp(I))
+// when the upstream site lies beyond a wall (flip = true).
+template <class L, int I, int WALLS>
+struct Up {
+    static constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+    static constexpr uint32_t need_xy = (ex > 0 ? 1u : 0u) | (ex < 0 ? 2u : 0u) |
+                                        (ey > 0 ? 4u : 0u) | (ey < 0 ? 8u : 0u);
+    static constexpr uint32_t need_z = (ez > 0 ? 16u : 0u) | (ez < 0 ? 32u : 0u);
+    static constexpr bool test_xy = (WALLS & WALLS_XY) && need_xy != 0u;
+    static constexpr bool test_z = (WALLS & WALLS_Z) && need_z != 0u;
+    static constexpr bool MAYFLIP = I != 0 && (test_xy || test_z);
+    // the population pair (lo, lo + 1) containing I
+    static constexpr int LO = I == 0 ? 0 : ((I & 1) ? I : I - 1);
+};
+
+template <class L, int I, int WALLS>
+__device__ __forceinline__ void upstream(const Col& c, const ZRow& r, uint32_t& slot_site,
+                                         bool& flip) {
+    using U = Up<L, I, WALLS>;
     const uint32_t site = c.base + r.base;
-    const uint32_t solid = c.solid | r.solid;
+    int off = 0;
+    if constexpr (U::ex > 0) off += c.dxm;
+    if constexpr (U::ex < 0) off += c.dxp;
+    if constexpr (U::ey > 0) off += c.dym;
+    if constexpr (U::ey < 0) off += c.dyp;
+    if constexpr (U::ez > 0) off += r.dzm;
+    if constexpr (U::ez < 0) off += r.dzp;
+    flip = false;
+    if constexpr (U::MAYFLIP) {
+        bool bb = false;
+        if constexpr (U::test_xy) bb = bb || (c.solid & U::need_xy) != 0u;
+        if constexpr (U::test_z) bb = bb || (r.solid & U::need_z) != 0u;
+        flip = bb;
+        slot_site = bb ? site : site + off;
+    } else {
+        slot_site = site + off;
+    }
+}
+
+// Address of slot (slot_site, I or opp(I)) in an array of Q populations with stride
+// S * esize bytes: a uniform base (kernel argument plus a multiple of the stride) and a
+// 32-bit per-lane byte offset, the form the scalar-base loads take.
+template <class L, int I, int WALLS, int ESIZE>
+__device__ __forceinline__ const char* slot_addr(const char* __restrict__ base0, uint32_t S,
+                                                 uint32_t slot_site, bool flip,
+                                                 uint32_t& off) {
+    using U = Up<L, I, WALLS>;
+    const size_t stride = (size_t)S * ESIZE;
+    if constexpr (!U::MAYFLIP) {
+        off = slot_site * (uint32_t)ESIZE;
+        return base0 + (size_t)I * stride;
+    } else {
+        // pop = flip ? opp(I) : I; second member of the pair when pop != LO
+        const bool second = flip ? (I == U::LO) : (I != U::LO);
+        off = slot_site * (uint32_t)ESIZE + (second ? (uint32_t)stride : 0u);
+        return base0 + (size_t)U::LO * stride;
+    }
+}
+
+// Load slot pair (h, g) of direction I.
+template <class L, class ST, int I, int WALLS>
+__device__ __forceinline__ float2 load_pair(const char* __restrict__ b, uint32_t S,
+                                            uint32_t slot_site, bool flip, const Codec& cd) {
+    if constexpr (!ST::HALF) {
+        uint32_t off;
+        const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
+        return *reinterpret_cast<const float2*>(base + off);
+    } else {
+        const float2 R = *reinterpret_cast<const float2*>(b + slot_site * 8u);
+        if constexpr (I == 0) {
+            return make_float2(L::r(0) * R.x, L::r(0) * R.y);
+        } else {
+            uint32_t off;
+            // deviation arrays start after the R pairs; population i >= 1 is entry i - 1
+            const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8 - (size_t)S * 4, S,
+                                                         slot_site, flip, off);
+            const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
+            return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
+        }
+    }
+}
+
+// Load h of slot of direction I.
+template <class L, class ST, int I, int WALLS>
+__device__ __forceinline__ float load_h(const char* __restrict__ b, uint32_t S,
+                                        uint32_t slot_site, bool flip, const Codec& cd) {
+    if constexpr (!ST::HALF) {
+        uint32_t off;
+        const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
+        return *reinterpret_cast<const float*>(base + off);
+    } else {
+        const float R = *reinterpret_cast<const float*>(b + slot_site * 8u);
+        if constexpr (I == 0) {
+            return L::r(0) * R;
+        } else {
+            uint32_t off;
+            const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8 - (size_t)S * 4, S,
+                                                         slot_site, flip, off);
+            return fmaf(__half2float(*reinterpret_cast<const __half*>(base + off)), cd.ish,
+                        L::r(I) * R);
+        }
+    }
+}
+
+// Gather the Q pre-collision populations of both sets of one site.
+template <class L, class ST, int WALLS>
+__device__ __forceinline__ void pull_site(const char* __restrict__ b, const Geom& G,
+                                          const Col& c, const ZRow& r, const Codec& cd,
+                                          float (&h)[L::Q], float (&g)[L::Q]) {
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-        int off = 0;
-        if constexpr (ex > 0) off += c.dxm;
-        if constexpr (ex < 0) off += c.dxp;
-        if constexpr (ey > 0) off += c.dym;
-        if constexpr (ey < 0) off += c.dyp;
-        if constexpr (ez > 0) off += r.dzm;
-        if constexpr (ez < 0) off += r.dzp;
-        constexpr uint32_t need = (ex > 0 ? 1u : 0u) | (ex < 0 ? 2u : 0u) | (ey > 0 ? 4u : 0u) |
-                                  (ey < 0 ? 8u : 0u) | (ez > 0 ? 16u : 0u) | (ez < 0 ? 32u : 0u);
-        if constexpr (i == 0) {
-            f[i] = ST::template load<L, i>(b, 0, site, G.S, iscale);
-        } else if constexpr (WALLS) {
-            const bool bb = (solid & need) != 0u;
-            f[i] = ST::template load<L, i>(b, bb ? opp(i) : i, bb ? site : site + off, G.S, iscale);
-        } else {
-            f[i] = ST::template load<L, i>(b, i, site + off, G.S, iscale);
-        }
+        uint32_t s;
+        bool flip;
+        upstream<L, i, WALLS>(c, r, s, flip);
+        const float2 v = load_pair<L, ST, i, WALLS>(b, G.S, s, flip, cd);
+        h[i] = v.x;
+        g[i] = v.y;
+    });
+}
+
+// Gather only the h populations of one site.
+template <class L, class ST, int WALLS>
+__device__ __forceinline__ void pull_site_h(const char* __restrict__ b, const Geom& G,
+                                            const Col& c, const ZRow& r, const Codec& cd,
+                                            float (&h)[L::Q]) {
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        uint32_t s;
+        bool flip;
+        upstream<L, i, WALLS>(c, r, s, flip);
+        h[i] = load_h<L, ST, i, WALLS>(b, G.S, s, flip, cd);
     });
 }
 
@@ -382,46 +545,100 @@ __device__ __forceinline__ float phi_sum(const float (&f)[L::Q], float& lo) {
     return hi;
 }
 
-// Full collision of one site: h BGK (Eq. 1) and the filtered g update (Eq. 10).
-// a.phi + phi_lo is the site's phi (see phi_sum).
-template <class L>
-__device__ __forceinline__ void collide(const Model& m, const Macro& a, float phi_lo,
-                                        const float (&h)[L::Q], const float (&g)[L::Q],
-                                        float (&ho)[L::Q], float (&go)[L::Q]) {
-    const EqTerms t = eq_terms(m, a);
-    float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        float hdev, geq, K;
-        eq_dir<L, i>(a, t, hdev, geq, K);
-        if constexpr (i == 0) hdev = fmaf(a.phi, kappa<L>(), hdev);
-        // h + (h^eq - h)/tau_phi with h^eq - h = (phi w_i - h) + hdev
-        ho[i] = fmaf(m.om_phi, fmaf(a.phi, L::w(i), -h[i]) + fmaf(phi_lo, L::w(i), hdev), h[i]);
-        const float neq = g[i] - geq;
-        constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-        if constexpr (ex != 0) pxx += neq;
-        if constexpr (ey != 0) pyy += neq;
-        if constexpr (ez != 0) pzz += neq;
-        if constexpr (ex * ey != 0) pxy += (float)(ex * ey) * neq;
-        if constexpr (ex * ez != 0) pxz += (float)(ex * ez) * neq;
-        if constexpr (ey * ez != 0) pyz += (float)(ey * ez) * neq;
-        go[i] = geq + K;                                          // G^eq = g^eq + K
-    });
-    const float tr3 = (pxx + pyy + pzz) * (1.0f / 3.0f);
+// Full collision of one site, h BGK (Eq. 1) and the filtered g update (Eq. 10), with
+// each post-collision pair handed to `out` as soon as it is formed.
+//
+// Pi = sum_l c_l c_l (g_l - g^eq_l) is built from the raw second moment of g and the
+// closed form of the equilibrium's: with 4th-order isotropic weights (D2Q9, D3Q19),
+//   sum_l c_a c_b g^eq_l = P delta_ab + rho u_a u_b - (1/2) sum_l c_a c_b K_l,
+//   sum_l c_a c_b K_l = A [(u_a d_b + u_b d_a)/3 - u_a u_b (u.d)] + (rho_dif/3) delta_ab (u.d)
+//                       + (u_a F_b + u_b F_a) - 3 u_a u_b (u.F),
+// with d = grad(phi), A = rho_dif + 3 mu (T = 1/3); the delta f^eq term of Eq. 13 is odd
+// in c and has no second moment.  Opposite velocities are handled as pairs, sharing
+// c.u, c.d, c.F and c.n.  a.phi + phi_lo is the site's phi (see phi_sum).
+template <class L, class Out>
+__device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, float phi_lo,
+                                               const float (&h)[L::Q], const float (&g)[L::Q],
+                                               Out& out) {
+    constexpr float third = 1.0f / 3.0f;
+    const float ux = a.ux, uy = a.uy, uz = a.uz;
+    const float E0 = -1.5f * (ux * ux + uy * uy + uz * uz);
+    const float ug = ux * a.gx + uy * a.gy + uz * a.gz;
+    const float uF = ux * a.Fx + uy * a.Fy + uz * a.Fz;
+    const float A = fmaf(3.0f, a.mu, m.rho_dif);
+    const float mu3 = 3.0f * a.mu;
+    const float dcoef = m.beta * 0.75f * m.rho_dif * a.lap;
+    const float P3 = 3.0f * a.P;
     const float om1 = 1.0f - a.itau;
-    static_for<0, L::Q>([&](auto I) {
+    // raw second moments of g over the lattice's axes
+    float Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
+    static_for<1, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-        float ccP = 0.f;                                           // c_i c_i : Pi
-        if constexpr (ex != 0) ccP += pxx;
-        if constexpr (ey != 0) ccP += pyy;
-        if constexpr (ez != 0) ccP += pzz;
-        if constexpr (ex * ey != 0) ccP += 2.0f * (float)(ex * ey) * pxy;
-        if constexpr (ex * ez != 0) ccP += 2.0f * (float)(ex * ez) * pxz;
-        if constexpr (ey * ez != 0) ccP += 2.0f * (float)(ey * ez) * pyz;
-        // w_i / (2 T^2) (c_i c_i : Pi - T tr Pi) = 4.5 w_i (ccP - tr/3)
-        go[i] = fmaf(om1 * 4.5f * L::w(i), ccP - tr3, go[i]);
+        if constexpr (ex != 0) Mxx += g[i];
+        if constexpr (ey != 0) Myy += g[i];
+        if constexpr (ez != 0) Mzz += g[i];
+        if constexpr (ex * ey > 0) Mxy += g[i];
+        if constexpr (ex * ey < 0) Mxy -= g[i];
+        if constexpr (ex * ez > 0) Mxz += g[i];
+        if constexpr (ex * ez < 0) Mxz -= g[i];
+        if constexpr (ey * ez > 0) Myz += g[i];
+        if constexpr (ey * ez < 0) Myz -= g[i];
     });
+    auto pi = [&](float M, float ua, float ub, float da, float db, float Fa, float Fb,
+                  bool diag) {
+        float sK = A * (fmaf(ua, db, ub * da) * third - ua * ub * ug) + fmaf(ua, Fb, ub * Fa) -
+                   3.0f * ua * ub * uF;
+        float eq = fmaf(a.rho * ua, ub, -0.5f * sK);
+        if (diag) eq += a.P - (0.5f * third) * m.rho_dif * ug;
+        return M - eq;
+    };
+    constexpr bool HX = true, HY = L::USES_Y, HZ = true;
+    const float Pxx = HX ? pi(Mxx, ux, ux, a.gx, a.gx, a.Fx, a.Fx, true) : 0.f;
+    const float Pyy = HY ? pi(Myy, uy, uy, a.gy, a.gy, a.Fy, a.Fy, true) : 0.f;
+    const float Pzz = HZ ? pi(Mzz, uz, uz, a.gz, a.gz, a.Fz, a.Fz, true) : 0.f;
+    const float Pxy = HY ? pi(Mxy, ux, uy, a.gx, a.gy, a.Fx, a.Fy, false) : 0.f;
+    const float Pxz = pi(Mxz, ux, uz, a.gx, a.gz, a.Fx, a.Fz, false);
+    const float Pyz = HY ? pi(Myz, uy, uz, a.gy, a.gz, a.Fy, a.Fz, false) : 0.f;
+    const float tr3 = (Pxx + Pyy + Pzz) * third;
+    const float hw0 = fmaf(a.phi, L::w(0), -h[0]);
+    {   // rest population: c = 0
+        constexpr float w = L::w(0);
+        const float hdev = fmaf(a.phi, w * E0, a.phi * kappa<L>());
+        const float ho = fmaf(m.om_phi, hw0 + fmaf(phi_lo, w, hdev), h[0]);
+        const float K = w * (fmaf(E0, A, mu3) * (-ug) + 3.0f * (1.0f + E0) * (-uF));
+        const float go = fmaf(w, fmaf(a.rho, E0, P3), fmaf(0.5f, K, om1 * 4.5f * w * (-tr3)));
+        out.template put<0>(ho, go);
+    }
+    static_for<0, (L::Q - 1) / 2>([&](auto K_) {
+        constexpr int i = 2 * decltype(K_)::value + 1;          // pair (i, i + 1), c_{i+1} = -c_i
+        constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
+        constexpr float w = L::w(i);
+        float cu = 0.f, cd = 0.f, cF = 0.f, cn = 0.f, ccP = 0.f;
+        if constexpr (ex != 0) { cu += ex * ux; cd += ex * a.gx; cF += ex * a.Fx; cn += ex * a.nx; ccP += Pxx; }
+        if constexpr (ey != 0) { cu += ey * uy; cd += ey * a.gy; cF += ey * a.Fy; cn += ey * a.ny; ccP += Pyy; }
+        if constexpr (ez != 0) { cu += ez * uz; cd += ez * a.gz; cF += ez * a.Fz; cn += ez * a.nz; ccP += Pzz; }
+        if constexpr (ex * ey != 0) ccP += (float)(2 * ex * ey) * Pxy;
+        if constexpr (ex * ez != 0) ccP += (float)(2 * ex * ez) * Pxz;
+        if constexpr (ey * ez != 0) ccP += (float)(2 * ey * ez) * Pyz;
+        const float Ee = fmaf(4.5f * cu, cu, E0);                // even part of e
+        const float O = 3.0f * cu;                               // odd part of e
+        const float ep = Ee + O, em = Ee - O;
+        // h: h + (h^eq - h)/tau_phi, h^eq - h = (phi w - h) + w (phi e + theta c.n)
+        const float tn = a.theta * cn;
+        const float hp = fmaf(m.om_phi, fmaf(a.phi, w, -h[i]) + fmaf(phi_lo, w, w * fmaf(a.phi, ep, tn)), h[i]);
+        const float hm = fmaf(m.om_phi, fmaf(a.phi, w, -h[i + 1]) + fmaf(phi_lo, w, w * fmaf(a.phi, em, -tn)), h[i + 1]);
+        // K_i = w [(e A + 3 mu)(c.d - u.d) + 3 (1 + e)(c.F - u.F)]             (Eq. 7)
+        const float Kp = w * fmaf(fmaf(ep, A, mu3), cd - ug, 3.0f * (1.0f + ep) * (cF - uF));
+        const float Km = w * fmaf(fmaf(em, A, mu3), -cd - ug, 3.0f * (1.0f + em) * (-cF - uF));
+        // g* = w (rho e + 3P + (c.u) dcoef) + K/2 + (1 - 1/tau) 4.5 w (c c : Pi - tr/3)
+        const float filt = om1 * 4.5f * w * (ccP - tr3);
+        const float gp = fmaf(w, fmaf(a.rho, ep, P3) + cu * dcoef, fmaf(0.5f, Kp, filt));
+        const float gm = fmaf(w, fmaf(a.rho, em, P3) - cu * dcoef, fmaf(0.5f, Km, filt));
+        out.template put<i>(hp, gp);
+        out.template put<i + 1>(hm, gm);
+    });
+    out.finish();
 }
 
 }  // namespace pflb

@@ -13,23 +13,23 @@ struct Launch {
     int q;              // 9 or 19
     bool half;          // FP16S storage
     int bz;             // planes per workgroup in the fused step
+    int tile;           // D3Q19 tile shape: 0: 64x4, 1: 64x8, 2: 32x8, 3: 32x4
     Geom G;
     Model m;
     Codec cd;
     hipStream_t stream;
 };
 
-hipError_t launch_step(const Launch& a, const void* hs, const void* gs, void* hd, void* gd);
+hipError_t launch_step(const Launch& a, const void* src, void* dst);
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
                               const float* P, float* h, float* g);
 hipError_t launch_set_state(const Launch& a, uint32_t N, const float* h, const float* g,
-                            void* hb, void* gb);
-hipError_t launch_get_state(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                            float* h, float* g);
-hipError_t launch_read(const Launch& a, uint32_t N, const void* hb, const void* gb, float* phi,
-                       float* P, float* J, float* U);
-hipError_t launch_mass(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                       void* scratch);
+                            void* b);
+hipError_t launch_get_state(const Launch& a, uint32_t N, const void* b, float* h, float* g);
+hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, float* P,
+                       float* J, float* U);
+hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch);
+size_t state_bytes(int q, bool half, uint32_t S);
 size_t mass_scratch_bytes();
 size_t mass_result_offset();
 size_t mass_flag_offset();

@@ -11,19 +11,27 @@
 
 namespace pflb {
 
+// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs (each with
+// its own L2); tile t goes to the workgroup that makes each XCD sweep a contiguous run
+// of tiles, so the y-neighbours whose halos overlap share an L2 while they run.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    const int xcd = b & 7, loc = b >> 3, per = nblk >> 3, rem = nblk & 7;
+    return xcd < rem ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+}
+
 // ---------------------------------------------------------------------------
 // Fused step.  A workgroup owns a TX x TY column tile (D2Q9: TX x 1) and marches
 // along z over BZ planes.  phi of plane z+1 on the tile plus a one-site ring is
-// gathered into a 4-plane rolling LDS buffer (the h values of the tile's own sites
-// are kept in registers for the collision of the next plane), then plane z is
+// gathered into a 4-plane rolling LDS buffer (the h and g values of the tile's own
+// sites are kept in registers for the collision of the next plane), then plane z is
 // collided with grad(phi) and lap(phi) read from the LDS planes z-1, z, z+1.
 // One barrier per plane: plane z+2 is written into the slot plane z-2 used, which
 // no thread can still be reading once it has passed the barrier after plane z+1.
 // ---------------------------------------------------------------------------
-template <class L, class ST, int TX, int TY, bool WALLS>
+template <class L, class ST, int TX, int TY, int WALLS>
 __global__ void __launch_bounds__(TX * TY)
-k_step(Geom G, Model m, Codec cd, int BZ, const char* __restrict__ hs,
-       const char* __restrict__ gs, char* __restrict__ hd, char* __restrict__ gd) {
+k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
+       const char* __restrict__ src, char* __restrict__ dst) {
     constexpr int Q = L::Q;
     constexpr int HX = TX + 2;
     constexpr int HY = L::USES_Y ? TY + 2 : 1;
@@ -33,9 +41,14 @@ k_step(Geom G, Model m, Codec cd, int BZ, const char* __restrict__ hs,
     static_assert(NR <= TX * TY, "ring larger than the workgroup");
     __shared__ float sphi[4][HY][HX];
 
+    const int t = xcd_tile(blockIdx.x, nblk);
+    const int bx = t % ntx;
+    const int byz = t / ntx;
+    const int by = byz % nty;
+    const int bzi = byz / nty;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * BZ;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bzi * BZ;
     const int zend = min(z0 + BZ, G.nz);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < G.nx && y < G.ny;
@@ -57,55 +70,49 @@ k_step(Geom G, Model m, Codec cd, int BZ, const char* __restrict__ hs,
 
     auto ring_phi = [&](const ZRow& r) {
         float f[Q], lo;
-        pull_site<L, ST, WALLS>(hs, G, ring, r, cd.ish, f);
+        pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f);
         return phi_sum<L>(f, lo);
     };
 
-    float hc[Q], lo_c;
+    float hA[Q], gA[Q], loA, hB[Q], gB[Q], loB;
     {   // plane z0 - 1 (phi only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
         float f[Q], lo;
-        pull_site<L, ST, WALLS>(hs, G, own, rm, cd.ish, f);
+        pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f);
         sphi[(z0 - 1) & 3][ty + OY][tx + 1] = phi_sum<L>(f, lo);
         if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm);
         const ZRow r0 = make_zrow(G, z0);
-        pull_site<L, ST, WALLS>(hs, G, own, r0, cd.ish, hc);
-        sphi[z0 & 3][ty + OY][tx + 1] = phi_sum<L>(hc, lo_c);
+        pull_site<L, ST, WALLS>(src, G, own, r0, cd, hA, gA);
+        sphi[z0 & 3][ty + OY][tx + 1] = phi_sum<L>(hA, loA);
         if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0);
     }
-    for (int z = z0; z < zend; ++z) {
-        // phase A: plane z + 1
-        float hn[Q], lo_n;
+    // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc).
+    auto plane = [&](int z, const float (&hc)[Q], const float (&gc)[Q], float lo_c,
+                     float (&hn)[Q], float (&gn)[Q], float& lo_n) {
         const ZRow rn = make_zrow(G, map_coord(z + 1, G.nz, G.wz));
-        pull_site<L, ST, WALLS>(hs, G, own, rn, cd.ish, hn);
+        if (z + 1 < zend) {
+            pull_site<L, ST, WALLS>(src, G, own, rn, cd, hn, gn);
+        } else {
+            pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
+        }
         sphi[(z + 1) & 3][ty + OY][tx + 1] = phi_sum<L>(hn, lo_n);
         if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
         __syncthreads();
-        // phase B: collide plane z
         if (active) {
             const ZRow r = make_zrow(G, z);
-            float gv[Q];
-            pull_site<L, ST, WALLS>(gs, G, own, r, cd.isg, gv);
             float pn[Q];
             static_for<0, Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 pn[i] = sphi[(z + L::cz(i)) & 3][ty + OY + L::cy(i)][tx + 1 + L::cx(i)];
             });
-            const Macro a = macros<L>(m, pn, gv);
-            float ho[Q], go[Q];
-            collide<L>(m, a, lo_c, hc, gv, ho, go);
-            const uint32_t site = own.base + r.base;
-            store_site<L, ST>(hd, site, G.S, ho, a.phi, lo_c, cd.sh, cd.ish);
-            if constexpr (ST::HALF) {
-                float glo;
-                const float gsum = phi_sum<L>(go, glo);
-                store_site<L, ST>(gd, site, G.S, go, gsum, glo, cd.sg, cd.isg);
-            } else {
-                store_site<L, ST>(gd, site, G.S, go, 0.0f, 0.0f, 1.0f, 1.0f);
-            }
+            const Macro a = macros<L>(m, pn, gc);
+            SiteWriter<L, ST> out(dst, own.base + r.base, G.S, cd, a.phi, lo_c);
+            collide_stream<L>(m, a, lo_c, hc, gc, out);
         }
-        static_for<0, Q>([&](auto I) { hc[decltype(I)::value] = hn[decltype(I)::value]; });
-        lo_c = lo_n;
+    };
+    for (int z = z0; z < zend; z += 2) {
+        plane(z, hA, gA, loA, hB, gB, loB);
+        if (z + 1 < zend) plane(z + 1, hB, gB, loB, hA, gA, loA);
     }
 }
 
@@ -184,7 +191,7 @@ k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
 template <class L, class ST>
 __global__ void __launch_bounds__(256)
 k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
-            const float* __restrict__ g, char* __restrict__ hb, char* __restrict__ gb) {
+            const float* __restrict__ g, char* __restrict__ b) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
     int x, y, z;
@@ -192,7 +199,7 @@ k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
     float fh[L::Q], fg[L::Q];
     static_for<0, L::Q>([&](auto I) {
         constexpr int j = decltype(I)::value;
-        int xx = x + L::cx(j), yy = y + L::cy(j), zz = z + L::cz(j);
+        const int xx = x + L::cx(j), yy = y + L::cy(j), zz = z + L::cz(j);
         const bool solid = (G.wx && (xx < 0 || xx >= G.nx)) || (G.wy && (yy < 0 || yy >= G.ny)) ||
                            (G.wz && (zz < 0 || zz >= G.nz));
         if (solid) {
@@ -205,38 +212,19 @@ k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
             fg[j] = g[(size_t)j * N + t];
         }
     });
-    if constexpr (!ST::HALF) {
-        store_site<L, ST>(hb, s, G.S, fh, 0.f, 0.f, 1.f, 1.f);
-        store_site<L, ST>(gb, s, G.S, fg, 0.f, 0.f, 1.f, 1.f);
-    } else {
-        // plain encoding: R from the rest population, deviations from r_i R
-        auto enc = [&](char* b, const float (&f)[L::Q], float sc) {
-            __half* dev = reinterpret_cast<__half*>(b + (size_t)G.S * 4);
-            const float R = f[0] / L::r(0);
-            reinterpret_cast<float*>(b)[s] = R;
-            static_for<1, L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                dev[(size_t)(i - 1) * G.S + s] = __float2half_rn((f[i] - L::r(i) * R) * sc);
-            });
-        };
-        enc(hb, fh, cd.sh);
-        enc(gb, fg, cd.sg);
-    }
+    encode_site<L, ST>(b, s, G.S, fh, fg, cd);
 }
 
-template <class L, class ST, bool WALLS>
+template <class L, class ST, int WALLS>
 __global__ void __launch_bounds__(256)
-k_get_state(Geom G, Codec cd, uint32_t N, const char* __restrict__ hb,
-            const char* __restrict__ gb, float* __restrict__ h, float* __restrict__ g) {
+k_get_state(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __restrict__ h,
+            float* __restrict__ g) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
     int x, y, z;
     site_coords(G, s, x, y, z);
-    const Col c = make_col(G, x, y);
-    const ZRow r = make_zrow(G, z);
     float fh[L::Q], fg[L::Q];
-    pull_site<L, ST, WALLS>(hb, G, c, r, cd.ish, fh);
-    pull_site<L, ST, WALLS>(gb, G, c, r, cd.isg, fg);
+    pull_site<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, fh, fg);
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         h[(size_t)i * N + s] = fh[i];
@@ -247,31 +235,30 @@ k_get_state(Geom G, Codec cd, uint32_t N, const char* __restrict__ hb,
 // ---------------------------------------------------------------------------
 // read-out
 // ---------------------------------------------------------------------------
-template <class L, class ST, bool WALLS>
+template <class L, class ST, int WALLS>
 __global__ void __launch_bounds__(256)
-k_phi(Geom G, Codec cd, uint32_t N, const char* __restrict__ hb, float* __restrict__ phi) {
+k_phi(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __restrict__ phi) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
     int x, y, z;
     site_coords(G, s, x, y, z);
-    float f[L::Q];
-    pull_site<L, ST, WALLS>(hb, G, make_col(G, x, y), make_zrow(G, z), cd.ish, f);
-    float lo;
+    float f[L::Q], lo;
+    pull_site_h<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, f);
     phi[s] = phi_sum<L>(f, lo);
 }
 
-template <class L, class ST, bool WALLS>
+template <class L, class ST, int WALLS>
 __global__ void __launch_bounds__(256)
-k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ gb,
+k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ b,
         const float* __restrict__ phi, float* __restrict__ P, float* __restrict__ J,
         float* __restrict__ U) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
     int x, y, z;
     site_coords(G, s, x, y, z);
-    float pn[L::Q], gv[L::Q];
+    float pn[L::Q], hv[L::Q], gv[L::Q];
     phi_stencil<L>(G, phi, x, y, z, pn);
-    pull_site<L, ST, WALLS>(gb, G, make_col(G, x, y), make_zrow(G, z), cd.isg, gv);
+    pull_site<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, hv, gv);
     const Macro a = macros<L>(m, pn, gv);
     if (P) P[s] = a.P;
     const float jv[3] = {a.jx, a.jy, a.jz};
@@ -284,32 +271,33 @@ k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ gb,
 
 // ---------------------------------------------------------------------------
 // sum of phi: every slot is gathered exactly once per step, so sum_x phi(x) is the
-// sum of all decoded slots.  Per site in float64, per block by a fixed tree, then
+// sum of all decoded h slots.  Per site in float64, per block by a fixed tree, then
 // one block over the partial sums: the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 constexpr int MASS_BLOCKS = 1024;
 constexpr int MASS_THREADS = 256;
 
 template <class L, class ST>
-__device__ __forceinline__ double slot_sum(const char* b, uint32_t s, uint32_t S, float isc,
-                                           bool& bad) {
+__device__ __forceinline__ double slot_sum(const char* b, uint32_t s, uint32_t S,
+                                           const Codec& cd, bool& bad) {
     double acc = 0.0;
     if constexpr (!ST::HALF) {
         static_for<0, L::Q>([&](auto I) {
-            const float v = reinterpret_cast<const float*>(b)[(size_t)decltype(I)::value * S + s];
-            bad |= !isfinite(v);
-            acc += (double)v;
+            const float2 v =
+                reinterpret_cast<const float2*>(b)[(size_t)decltype(I)::value * S + s];
+            bad |= !isfinite(v.x) || !isfinite(v.y);
+            acc += (double)v.x;
         });
     } else {
-        const float R = reinterpret_cast<const float*>(b)[s];
-        bad |= !isfinite(R);
-        acc = (double)L::r(0) * (double)R;
-        const __half* dev = reinterpret_cast<const __half*>(b + (size_t)S * 4);
+        const float2 R = reinterpret_cast<const float2*>(b)[s];
+        bad |= !isfinite(R.x) || !isfinite(R.y);
+        acc = (double)L::r(0) * (double)R.x;
+        const __half2* dev = reinterpret_cast<const __half2*>(b + (size_t)S * 8);
         static_for<1, L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const float d = __half2float(dev[(size_t)(i - 1) * S + s]);
-            bad |= !isfinite(d);
-            acc += (double)L::r(i) * (double)R + (double)d * (double)isc;
+            const float2 d = __half22float2(dev[(size_t)(i - 1) * S + s]);
+            bad |= !isfinite(d.x) || !isfinite(d.y);
+            acc += (double)L::r(i) * (double)R.x + (double)d.x * (double)cd.ish;
         });
     }
     return acc;
@@ -317,17 +305,15 @@ __device__ __forceinline__ double slot_sum(const char* b, uint32_t s, uint32_t S
 
 template <class L, class ST>
 __global__ void __launch_bounds__(MASS_THREADS)
-k_mass_partial(Geom G, Codec cd, uint32_t N, const char* __restrict__ hb,
-               const char* __restrict__ gb, double* __restrict__ part, int* __restrict__ flag) {
+k_mass_partial(Geom G, Codec cd, uint32_t N, const char* __restrict__ b,
+               double* __restrict__ part, int* __restrict__ flag) {
     __shared__ double sd[MASS_THREADS];
     __shared__ int sb[MASS_THREADS];
     double acc = 0.0;
     bool bad = false;
     for (uint32_t s = blockIdx.x * MASS_THREADS + threadIdx.x; s < N;
-         s += MASS_BLOCKS * MASS_THREADS) {
-        acc += slot_sum<L, ST>(hb, s, G.S, cd.ish, bad);
-        (void)slot_sum<L, ST>(gb, s, G.S, cd.isg, bad);
-    }
+         s += MASS_BLOCKS * MASS_THREADS)
+        acc += slot_sum<L, ST>(b, s, G.S, cd, bad);
     sd[threadIdx.x] = acc;
     sb[threadIdx.x] = bad ? 1 : 0;
     __syncthreads();
@@ -370,41 +356,54 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(uint32_t N) { return dim3((N + 255u) / 256u); }
 
-template <class L, class ST, bool WALLS>
-static hipError_t launch_step_t(const Launch& a, const char* hs, const char* gs, char* hd,
-                                char* gd) {
-    if constexpr (L::USES_Y) {
-        constexpr int TX = 64, TY = 4;
-        dim3 grid((a.G.nx + TX - 1) / TX, (a.G.ny + TY - 1) / TY, (a.G.nz + a.bz - 1) / a.bz);
-        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS>), grid, dim3(TX * TY), 0, a.stream,
-                           a.G, a.m, a.cd, a.bz, hs, gs, hd, gd);
-    } else {
-        constexpr int TX = 64;
-        dim3 grid((a.G.nx + TX - 1) / TX, 1, (a.G.nz + a.bz - 1) / a.bz);
-        hipLaunchKernelGGL((k_step<L, ST, TX, 1, WALLS>), grid, dim3(TX), 0, a.stream,
-                           a.G, a.m, a.cd, a.bz, hs, gs, hd, gd);
-    }
+template <class L, class ST, int WALLS, int TX, int TY>
+static hipError_t launch_tile(const Launch& a, const char* s, char* d) {
+    const int ntx = (a.G.nx + TX - 1) / TX;
+    const int nty = (a.G.ny + TY - 1) / TY;
+    const int ntz = (a.G.nz + a.bz - 1) / a.bz;
+    const int nblk = ntx * nty * ntz;
+    hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS>), dim3(nblk), dim3(TX * TY), 0, a.stream,
+                       a.G, a.m, a.cd, a.bz, ntx, nty, nblk, s, d);
     return hipGetLastError();
 }
 
-template <class L, class ST>
-static hipError_t dispatch_walls(const Launch& a, const char* hs, const char* gs, char* hd,
-                                 char* gd) {
-    if (a.G.wx || a.G.wy || a.G.wz) return launch_step_t<L, ST, true>(a, hs, gs, hd, gd);
-    return launch_step_t<L, ST, false>(a, hs, gs, hd, gd);
+template <class L, class ST, int WALLS>
+static hipError_t launch_step_t(const Launch& a, const char* s, char* d) {
+    if constexpr (L::USES_Y) {
+        switch (a.tile) {
+            case 1: return launch_tile<L, ST, WALLS, 64, 8>(a, s, d);
+            case 2: return launch_tile<L, ST, WALLS, 32, 8>(a, s, d);
+            case 3: return launch_tile<L, ST, WALLS, 32, 4>(a, s, d);
+            default: return launch_tile<L, ST, WALLS, 64, 4>(a, s, d);
+        }
+    } else {
+        return launch_tile<L, ST, WALLS, 64, 1>(a, s, d);
+    }
 }
 
-hipError_t launch_step(const Launch& a, const void* hs, const void* gs, void* hd, void* gd) {
-    auto h_s = static_cast<const char*>(hs);
-    auto g_s = static_cast<const char*>(gs);
-    auto h_d = static_cast<char*>(hd);
-    auto g_d = static_cast<char*>(gd);
-    if (a.q == 19) {
-        if (a.half) return dispatch_walls<LatD3Q19, StoreF16S>(a, h_s, g_s, h_d, g_d);
-        return dispatch_walls<LatD3Q19, StoreF32>(a, h_s, g_s, h_d, g_d);
+static inline int wallset(const Geom& G) {
+    return ((G.wx || G.wy) ? WALLS_XY : 0) | (G.wz ? WALLS_Z : 0);
+}
+
+template <class L, class ST>
+static hipError_t dispatch_walls(const Launch& a, const char* s, char* d) {
+    switch (wallset(a.G)) {
+        case WALLS_XYZ: return launch_step_t<L, ST, WALLS_XYZ>(a, s, d);
+        case WALLS_XY: return launch_step_t<L, ST, WALLS_XY>(a, s, d);
+        case WALLS_Z: return launch_step_t<L, ST, WALLS_Z>(a, s, d);
+        default: return launch_step_t<L, ST, WALLS_NONE>(a, s, d);
     }
-    if (a.half) return dispatch_walls<LatD2Q9, StoreF16S>(a, h_s, g_s, h_d, g_d);
-    return dispatch_walls<LatD2Q9, StoreF32>(a, h_s, g_s, h_d, g_d);
+}
+
+hipError_t launch_step(const Launch& a, const void* src, void* dst) {
+    auto s = static_cast<const char*>(src);
+    auto d = static_cast<char*>(dst);
+    if (a.q == 19) {
+        if (a.half) return dispatch_walls<LatD3Q19, StoreF16S>(a, s, d);
+        return dispatch_walls<LatD3Q19, StoreF32>(a, s, d);
+    }
+    if (a.half) return dispatch_walls<LatD2Q9, StoreF16S>(a, s, d);
+    return dispatch_walls<LatD2Q9, StoreF32>(a, s, d);
 }
 
 template <class L>
@@ -423,92 +422,86 @@ hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, con
 
 template <class L, class ST>
 static hipError_t set_state_t(const Launch& a, uint32_t N, const float* h, const float* g,
-                              void* hb, void* gb) {
+                              void* b) {
     hipLaunchKernelGGL((k_set_state<L, ST>), grid1(N), dim3(256), 0, a.stream, a.G, a.cd, N, h,
-                       g, static_cast<char*>(hb), static_cast<char*>(gb));
+                       g, static_cast<char*>(b));
     return hipGetLastError();
 }
 
 hipError_t launch_set_state(const Launch& a, uint32_t N, const float* h, const float* g,
-                            void* hb, void* gb) {
+                            void* b) {
     if (a.q == 19)
-        return a.half ? set_state_t<LatD3Q19, StoreF16S>(a, N, h, g, hb, gb)
-                      : set_state_t<LatD3Q19, StoreF32>(a, N, h, g, hb, gb);
-    return a.half ? set_state_t<LatD2Q9, StoreF16S>(a, N, h, g, hb, gb)
-                  : set_state_t<LatD2Q9, StoreF32>(a, N, h, g, hb, gb);
+        return a.half ? set_state_t<LatD3Q19, StoreF16S>(a, N, h, g, b)
+                      : set_state_t<LatD3Q19, StoreF32>(a, N, h, g, b);
+    return a.half ? set_state_t<LatD2Q9, StoreF16S>(a, N, h, g, b)
+                  : set_state_t<LatD2Q9, StoreF32>(a, N, h, g, b);
 }
 
-template <class L, class ST, bool WALLS>
-static hipError_t get_state_t(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                              float* h, float* g) {
+template <class L, class ST, int WALLS>
+static hipError_t get_state_t(const Launch& a, uint32_t N, const void* b, float* h, float* g) {
     hipLaunchKernelGGL((k_get_state<L, ST, WALLS>), grid1(N), dim3(256), 0, a.stream, a.G, a.cd,
-                       N, static_cast<const char*>(hb), static_cast<const char*>(gb), h, g);
+                       N, static_cast<const char*>(b), h, g);
     return hipGetLastError();
 }
 
 template <class L, class ST>
-static hipError_t get_state_w(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                              float* h, float* g) {
-    if (a.G.wx || a.G.wy || a.G.wz) return get_state_t<L, ST, true>(a, N, hb, gb, h, g);
-    return get_state_t<L, ST, false>(a, N, hb, gb, h, g);
+static hipError_t get_state_w(const Launch& a, uint32_t N, const void* b, float* h, float* g) {
+    if (wallset(a.G)) return get_state_t<L, ST, WALLS_XYZ>(a, N, b, h, g);
+    return get_state_t<L, ST, WALLS_NONE>(a, N, b, h, g);
 }
 
-hipError_t launch_get_state(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                            float* h, float* g) {
+hipError_t launch_get_state(const Launch& a, uint32_t N, const void* b, float* h, float* g) {
     if (a.q == 19)
-        return a.half ? get_state_w<LatD3Q19, StoreF16S>(a, N, hb, gb, h, g)
-                      : get_state_w<LatD3Q19, StoreF32>(a, N, hb, gb, h, g);
-    return a.half ? get_state_w<LatD2Q9, StoreF16S>(a, N, hb, gb, h, g)
-                  : get_state_w<LatD2Q9, StoreF32>(a, N, hb, gb, h, g);
+        return a.half ? get_state_w<LatD3Q19, StoreF16S>(a, N, b, h, g)
+                      : get_state_w<LatD3Q19, StoreF32>(a, N, b, h, g);
+    return a.half ? get_state_w<LatD2Q9, StoreF16S>(a, N, b, h, g)
+                  : get_state_w<LatD2Q9, StoreF32>(a, N, b, h, g);
 }
 
-template <class L, class ST, bool WALLS>
-static hipError_t read_t(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                         float* phi, float* P, float* J, float* U) {
+template <class L, class ST, int WALLS>
+static hipError_t read_t(const Launch& a, uint32_t N, const void* b, float* phi, float* P,
+                         float* J, float* U) {
     hipLaunchKernelGGL((k_phi<L, ST, WALLS>), grid1(N), dim3(256), 0, a.stream, a.G, a.cd, N,
-                       static_cast<const char*>(hb), phi);
+                       static_cast<const char*>(b), phi);
     if (P || J || U)
         hipLaunchKernelGGL((k_macro<L, ST, WALLS>), grid1(N), dim3(256), 0, a.stream, a.G, a.m,
-                           a.cd, N, static_cast<const char*>(gb), phi, P, J, U);
+                           a.cd, N, static_cast<const char*>(b), phi, P, J, U);
     return hipGetLastError();
 }
 
 template <class L, class ST>
-static hipError_t read_w(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                         float* phi, float* P, float* J, float* U) {
-    if (a.G.wx || a.G.wy || a.G.wz) return read_t<L, ST, true>(a, N, hb, gb, phi, P, J, U);
-    return read_t<L, ST, false>(a, N, hb, gb, phi, P, J, U);
+static hipError_t read_w(const Launch& a, uint32_t N, const void* b, float* phi, float* P,
+                         float* J, float* U) {
+    if (wallset(a.G)) return read_t<L, ST, WALLS_XYZ>(a, N, b, phi, P, J, U);
+    return read_t<L, ST, WALLS_NONE>(a, N, b, phi, P, J, U);
 }
 
-hipError_t launch_read(const Launch& a, uint32_t N, const void* hb, const void* gb, float* phi,
-                       float* P, float* J, float* U) {
+hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, float* P,
+                       float* J, float* U) {
     if (a.q == 19)
-        return a.half ? read_w<LatD3Q19, StoreF16S>(a, N, hb, gb, phi, P, J, U)
-                      : read_w<LatD3Q19, StoreF32>(a, N, hb, gb, phi, P, J, U);
-    return a.half ? read_w<LatD2Q9, StoreF16S>(a, N, hb, gb, phi, P, J, U)
-                  : read_w<LatD2Q9, StoreF32>(a, N, hb, gb, phi, P, J, U);
+        return a.half ? read_w<LatD3Q19, StoreF16S>(a, N, b, phi, P, J, U)
+                      : read_w<LatD3Q19, StoreF32>(a, N, b, phi, P, J, U);
+    return a.half ? read_w<LatD2Q9, StoreF16S>(a, N, b, phi, P, J, U)
+                  : read_w<LatD2Q9, StoreF32>(a, N, b, phi, P, J, U);
 }
 
 template <class L, class ST>
-static hipError_t mass_t(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                         void* scratch) {
+static hipError_t mass_t(const Launch& a, uint32_t N, const void* b, void* scratch) {
     double* part = static_cast<double*>(scratch);
     int* flag = reinterpret_cast<int*>(part + MASS_BLOCKS + 1);
     hipLaunchKernelGGL((k_mass_partial<L, ST>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0,
-                       a.stream, a.G, a.cd, N, static_cast<const char*>(hb),
-                       static_cast<const char*>(gb), part, flag);
+                       a.stream, a.G, a.cd, N, static_cast<const char*>(b), part, flag);
     hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(MASS_BLOCKS), 0, a.stream, part, flag,
                        part + MASS_BLOCKS, flag + MASS_BLOCKS);
     return hipGetLastError();
 }
 
-hipError_t launch_mass(const Launch& a, uint32_t N, const void* hb, const void* gb,
-                       void* scratch) {
+hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch) {
     if (a.q == 19)
-        return a.half ? mass_t<LatD3Q19, StoreF16S>(a, N, hb, gb, scratch)
-                      : mass_t<LatD3Q19, StoreF32>(a, N, hb, gb, scratch);
-    return a.half ? mass_t<LatD2Q9, StoreF16S>(a, N, hb, gb, scratch)
-                  : mass_t<LatD2Q9, StoreF32>(a, N, hb, gb, scratch);
+        return a.half ? mass_t<LatD3Q19, StoreF16S>(a, N, b, scratch)
+                      : mass_t<LatD3Q19, StoreF32>(a, N, b, scratch);
+    return a.half ? mass_t<LatD2Q9, StoreF16S>(a, N, b, scratch)
+                  : mass_t<LatD2Q9, StoreF32>(a, N, b, scratch);
 }
 
 size_t mass_scratch_bytes() {
@@ -518,6 +511,10 @@ size_t mass_scratch_bytes() {
 size_t mass_result_offset() { return MASS_BLOCKS * sizeof(double); }
 size_t mass_flag_offset() {
     return (MASS_BLOCKS + 1) * sizeof(double) + MASS_BLOCKS * sizeof(int);
+}
+
+size_t state_bytes(int q, bool half, uint32_t S) {
+    return half ? StoreF16S::bytes_per_site(q) * S : StoreF32::bytes_per_site(q) * S;
 }
 
 }  // namespace pflb

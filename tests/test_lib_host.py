@@ -66,18 +66,21 @@ def test_required_bytes_and_unbound_errors(L):
     assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
     try:
         N = 8 * 8 * 8
-        assert L.pflb_required_bytes(ctypes.byref(p), 0) >= 19 * N * 4
+        # a state buffer holds both sets: 19 float pairs per site, or a float pair plus
+        # 18 half pairs per site in FP16S storage
+        assert L.pflb_required_bytes(ctypes.byref(p), 0) >= 19 * N * 8
         p16 = _params(storage=1, scale=(16, 8))
-        assert L.pflb_required_bytes(ctypes.byref(p16), 0) >= N * 4 + 18 * N * 2
-        assert L.pflb_required_bytes(ctypes.byref(p16), 0) < 19 * N * 4
+        assert L.pflb_required_bytes(ctypes.byref(p16), 1) >= N * 8 + 18 * N * 4
+        assert L.pflb_required_bytes(ctypes.byref(p16), 1) < 19 * N * 8
+        assert L.pflb_required_bytes(ctypes.byref(p), 2) > 0
         assert L.pflb_required_bytes(ctypes.byref(p), 9) == 0
         # every state call before pflb_bind reports PFLB_ERR_UNBOUND without GPU work
         assert L.pflb_step(ctx, 1, None) == -3
         assert L.pflb_set_state(ctx, None, None, None) == -3
         assert b"bound" in L.pflb_last_error(ctx)
         # misaligned pointers are refused
-        arr = (ctypes.c_void_p * 5)(*[4096 + 16] * 5)
-        assert L.pflb_bind(ctx, arr, 5) == -2
-        assert L.pflb_bind(ctx, arr, 4) == -1
+        arr = (ctypes.c_void_p * 3)(*[4096 + 16] * 3)
+        assert L.pflb_bind(ctx, arr, 3) == -2
+        assert L.pflb_bind(ctx, arr, 2) == -1
     finally:
         L.pflb_destroy(ctx)
