@@ -1,9 +1,10 @@
 """Benchmark of the fused phase-field lattice Boltzmann step on one MI355X.
 
-Workload: D3Q19 droplet impact on a thin film, 256x256x128 sites, periodic in x and y,
-walls in z, rho_H/rho_L = 1000, R = 32, film depth 16, impact velocity 0.05, Re = 500,
-We = 8000, distributions stored as FP16 deviations (FP32 arithmetic).  The same run
-with FP32 storage is timed beside it.
+Workload: D3Q19 rising bubble, 128^3 sites, periodic in x and y, walls in z,
+rho_H/rho_L = 1000, mu_H/mu_L = 100, R = 16, W = 4, Eotvos number 10, hydrostatic
+start; distributions stored in FP32 (the value), with FP16-shifted storage timed beside
+it (speed-up and the phi difference between the two after the same steps).  The D3Q19
+droplet impact on a film (256x256x128, both storages) is timed as a second block.
 
 A step is one fused stream-and-collide pass over both distribution sets (every site,
 every population); the sum(phi)/non-finite guard runs once at the end of the timed
@@ -12,6 +13,7 @@ lattice-site updates per second (MLUPS) of the whole GPU.
 
 Prints one JSON line.
 """
+import hashlib
 import argparse
 import json
 import os
@@ -24,17 +26,30 @@ sys.path.insert(0, ROOT)
 METRIC = "D3Q19 two-set MLUPS & % HBM roofline; FP16-store/surrogate vs FP32 at stated φ err"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per site update: read + write of both sets once
-BYTES_PER_SITE = {("19", "fp32"): 2 * 2 * 19 * 4, ("19", "fp16s"): 2 * 2 * (4 + 18 * 2),
-                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * 2 * (4 + 8 * 2)}
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_droplet_impact_traffic.txt")
+# (FP16S: per site a float32 reference level and one fp16 word per population, per set)
+BYTES_PER_SITE = {("19", "fp32"): 2 * 2 * 19 * 4, ("19", "fp16s"): 2 * 2 * (4 + 19 * 2),
+                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * 2 * (4 + 9 * 2)}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rising_bubble_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_1812_00118_amd", "csrc")
+
+
+def kernel_source_sha1():
+    """Hash of the HIP sources: counter figures taken for another build are not used."""
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", choices=["fp16s", "fp32"], default="fp16s")
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", choices=["fp16s", "fp32"], default="fp32")
+    ap.add_argument("--workload", choices=["rising_bubble", "droplet_impact"],
+                    default="rising_bubble")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other storage mode and the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -89,19 +104,24 @@ def read_traffic(storage):
         lines = open(PROFILE_TRAFFIC).read().splitlines()
     except OSError:
         return None
+    vals = {}
     for ln in lines:
-        if ln.startswith(f"traffic_bytes_per_launch[{storage}]"):
-            return float(ln.split("=")[1].split()[0])
-    return None
+        if "=" in ln:
+            k, v = ln.split("=", 1)
+            vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if vals.get("source_sha1") != kernel_source_sha1():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch[{storage}]")
+    return float(v) if v else None
 
 
 def cpu_baseline(seconds):
-    """The FP64 oracle on a bounded sub-box of the same workload (same parameters,
-    64x64x32 sites with the drop scaled to R = 8 and film depth 4), timed on the host."""
+    """The FP64 oracle on a bounded sub-box of the same workload (same fluid parameters,
+    48^3 sites with the bubble scaled to R = 6), timed on the host."""
     import numpy as np
     import pfinputs
     from oracle import pflbm as O
-    cfg = pfinputs.droplet_impact(nx=64, ny=64, nz=32, R=8.0, film=4.0)
+    cfg = pfinputs.rising_bubble(n=48, R=6.0)
     prm = O.Params.from_dict(pfinputs.model_params(cfg))
     phi, u, P = pfinputs.fields(cfg)
     h, g = O.init(prm, phi.astype(np.float64), u.astype(np.float64), P.astype(np.float64))
@@ -114,11 +134,10 @@ def cpu_baseline(seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    sites = 64 * 64 * 32
+    sites = 48 ** 3
     return {"value": sites * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"droplet impact sub-box 64x64x32 (R 8, film 4, same fluid "
-                      f"parameters), {n} whole-domain FP64 steps in {el:.1f} s, "
-                      f"numpy single thread"}
+            "sample": f"rising bubble sub-box 48^3 (R 6, same fluid parameters), {n} "
+                      f"whole-domain FP64 steps in {el:.1f} s, numpy single thread"}
 
 
 def main():
@@ -135,9 +154,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    cfg = pfinputs.droplet_impact()
-    N = 256 * 256 * 128
-    print(f"[bench] workload droplet_impact 256x256x128, storage {args.storage}, "
+    cfg = pfinputs.rising_bubble() if args.workload == "rising_bubble" else pfinputs.droplet_impact()
+    nx, ny, nz = cfg["shape"]
+    N = nx * ny * nz
+    desc = {"rising_bubble": "rising_bubble D3Q19 128^3 (x,y periodic, z walls, rho 1000, "
+                             "mu 100, R 16, W 4, Eo 10, hydrostatic start)",
+            "droplet_impact": "droplet_impact D3Q19 256x256x128 (x,y periodic, z walls, "
+                              "rho 1000, R 32, film 16, U 0.05, Re 500, We 8000)"}
+    print(f"[bench] workload {args.workload} {nx}x{ny}x{nz}, storage {args.storage}, "
           f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
     main_run = time_storage(cfg, args.storage, args.steps, args.warmup)
     ms = main_run["kernel_ms"]
@@ -157,9 +181,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "droplet_impact D3Q19 256x256x128 (x,y periodic, z walls, "
-                               "rho 1000, R 32, film 16, U 0.05, Re 500, We 8000)",
-                   "storage": args.storage, "sites": N},
+        "config": {"workload": desc[args.workload], "storage": args.storage, "sites": N},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": read_traffic(args.storage),
@@ -167,7 +189,7 @@ def main():
                      "kernel_ms": round(ms, 4)},
         "nonfinite": main_run["nonfinite"],
     }
-    print(f"[bench] {args.storage}: {ms:.3f} ms/step, {mlups:.0f} MLUPS, "
+    print(f"[bench] {args.storage}: {ms:.4f} ms/step, {mlups:.0f} MLUPS, "
           f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_compare:
         other = "fp32" if args.storage == "fp16s" else "fp16s"
@@ -179,12 +201,25 @@ def main():
             "mlups": round(N / (oms * 1e-3) / 1e6, 1),
             "kernel_ms": round(oms, 4),
             "achieved_GBs": round(BYTES_PER_SITE[("19", other)] * N / (oms * 1e-3) / 1e9, 1),
-            "speedup_fp16s_vs_fp32": round((oms / ms) if args.storage == "fp16s" else (ms / oms), 3),
+            "speedup_fp16s_vs_fp32": round((ms / oms) if other == "fp16s" else (oms / ms), 3),
             "max_abs_dphi_fp16s_vs_fp32": dphi,
             "after_steps": main_run["steps_done"],
         }
-        print(f"[bench] {other}: {oms:.3f} ms/step; max|dphi| fp16s vs fp32 {dphi:.2e}",
+        print(f"[bench] {other}: {oms:.4f} ms/step; max|dphi| fp16s vs fp32 {dphi:.2e}",
               file=sys.stderr, flush=True)
+        if args.workload == "rising_bubble":
+            cfg2 = pfinputs.droplet_impact()
+            n2 = 256 * 256 * 128
+            blk = {"workload": desc["droplet_impact"]}
+            for st in ("fp32", "fp16s"):
+                r2 = time_storage(cfg2, st, max(50, args.steps // 4), args.warmup)
+                blk[st] = {"mlups": round(n2 / (r2["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r2["kernel_ms"], 4),
+                           "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * n2 /
+                                                 (r2["kernel_ms"] * 1e-3) / 1e9, 1)}
+                print(f"[bench] droplet_impact {st}: {r2['kernel_ms']:.4f} ms/step",
+                      file=sys.stderr, flush=True)
+            out["droplet_impact"] = blk
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

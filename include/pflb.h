@@ -53,13 +53,14 @@ extern "C" {
 
 #define PFLB_STORE_FP32  0     /* populations stored as float32                     */
 #define PFLB_STORE_FP16S 1     /* per site a float32 reference level R ~ phi/4 per  */
-                               /* set; populations stored as fp16 deviations from  */
-                               /* r_i R (dyadic r_i ~ 4 w_i, sum r_i = 4), the rest */
-                               /* population as r_0 R; FP32 arithmetic throughout   */
+                               /* set; every population stored as an fp16 deviation */
+                               /* from r_i R (dyadic r_i ~ 4 w_i, sum r_i = 4);     */
+                               /* FP32 arithmetic throughout                        */
 
 /* buffer ids for pflb_required_bytes / pflb_bind.  A state buffer holds both
  * distribution sets interleaved per population (FP32: float2 (h_i, g_i) per slot;
- * FP16S: a float2 pair of reference levels per site, then half2 deviation pairs);
+ * FP16S: a float2 pair of reference levels per site, then a half2 deviation pair
+ * per population);
  * the step reads one state buffer and writes the other. */
 #define PFLB_BUF_STATE0  0
 #define PFLB_BUF_STATE1  1

@@ -127,10 +127,12 @@ struct Codec {                // FP16S: power-of-two scales of the fp16 deviatio
 // storage codecs.  One state buffer holds both sets, interleaved per population so
 // that one load brings h_i and g_i of a slot:
 //   FP32 : [Q][S] float2 (h_i, g_i)
-//   FP16S: [S] float2 (R_h, R_g), then [Q-1][S] half2 (dev_h_i, dev_g_i).  Slot (s, i)
-//          decodes to r_i R(s) + dev_i(s)/scale (i >= 1), the rest slot to r_0 R(s),
-//          with the dyadic r_i ~ 4 w_i of the lattice (sum r_i = 4): R ~ phi/4 is the
-//          site's zeroth-order equilibrium level and the fp16 words hold deviations.
+//   FP16S: [S] float2 (R_h, R_g), then [Q][S] half2 (dev_h_i, dev_g_i).  Slot (s, i)
+//          decodes to r_i R(s) + dev_i(s)/scale, with the dyadic r_i ~ 4 w_i of the
+//          lattice (sum r_i = 4): R ~ phi/4 is the site's zeroth-order equilibrium
+//          level and the fp16 words hold the deviations from it.  The rest word dev_0
+//          carries what the float32 R cannot: the site's stored values sum to the
+//          intended total to a few 1e-11, so sum(phi) is conserved.
 // ---------------------------------------------------------------------------
 struct StoreF32 {
     static constexpr bool HALF = false;
@@ -140,7 +142,7 @@ struct StoreF32 {
 struct StoreF16S {
     static constexpr bool HALF = true;
     __host__ __device__ static constexpr size_t bytes_per_site(int q) {
-        return 8 + (size_t)(q - 1) * 4;
+        return 8 + (size_t)q * 4;
     }
 };
 
@@ -159,9 +161,9 @@ __device__ __forceinline__ void encode_site(char* __restrict__ b, uint32_t site,
         __half2* dev = reinterpret_cast<__half2*>(b + (size_t)S * 8);
         const float Rh = h[0] / L::r(0), Rg = g[0] / L::r(0);
         reinterpret_cast<float2*>(b)[site] = make_float2(Rh, Rg);
-        static_for<1, L::Q>([&](auto I) {
+        static_for<0, L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            dev[(size_t)(i - 1) * S + site] =
+            dev[(size_t)i * S + site] =
                 __halves2half2(__float2half_rn((h[i] - L::r(i) * Rh) * cd.sh),
                                __float2half_rn((g[i] - L::r(i) * Rg) * cd.sg));
         });
@@ -210,13 +212,17 @@ struct SiteWriter<L, StoreF16S> {
     char* __restrict__ b;
     uint32_t site, S;
     const Codec& cd;
-    float th, th_lo;               // h total (phi, as hi + lo)
-    float Rh0, Rg0, dh, dg;
+    double th;                     // h total (the site's phi)
     double tg;                     // g total
+    double dh, dg;                 // sums of the decoded deviations (exact dyadic terms)
+    float Rh0, Rg0;
     __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site_, uint32_t S_,
                                           const Codec& cd_, float th_, float th_lo_)
-        : b(b_), site(site_), S(S_), cd(cd_), th(th_), th_lo(th_lo_), Rh0(0.f), Rg0(0.f),
-          dh(0.f), dg(0.f), tg(0.0) {}
+        : b(b_), site(site_), S(S_), cd(cd_), th((double)th_ + (double)th_lo_), tg(0.0),
+          dh(0.0), dg(0.0), Rh0(0.f), Rg0(0.f) {}
+    __device__ __forceinline__ char* dev_addr(int i) const {
+        return b + (size_t)S * 8 + (size_t)i * ((size_t)S * 4) + site * 4u;
+    }
     template <int I>
     __device__ __forceinline__ void put(float h, float g) {
         static_assert(dyadic_refs_sum_to_four<L>(), "reference coefficients must sum to 4");
@@ -227,16 +233,20 @@ struct SiteWriter<L, StoreF16S> {
         } else {
             const __half qh = __float2half_rn((h - L::r(I) * Rh0) * cd.sh);
             const __half qg = __float2half_rn((g - L::r(I) * Rg0) * cd.sg);
-            dh += __half2float(qh) * cd.ish;
-            dg += __half2float(qg) * cd.isg;
-            char* base = b + (size_t)S * 8 + (size_t)(I - 1) * ((size_t)S * 4);
-            store_nt(base + site * 4u, __halves2half2(qh, qg));
+            dh += (double)(__half2float(qh) * cd.ish);
+            dg += (double)(__half2float(qg) * cd.isg);
+            store_nt(dev_addr(I), __halves2half2(qh, qg));
         }
     }
+    // R from the float64 complement, and the rest word from what R's rounding left over
     __device__ __forceinline__ void finish() {
-        const float tg_hi = (float)tg;
-        const float tg_lo = (float)(tg - (double)tg_hi);
-        store_nt(b + site * 8u, 0.25f * ((th - dh) + th_lo), 0.25f * ((tg_hi - dg) + tg_lo));
+        const float Rh = (float)(0.25 * (th - dh));
+        const float Rg = (float)(0.25 * (tg - dg));
+        const double resh = (th - dh) - 4.0 * (double)Rh;
+        const double resg = (tg - dg) - 4.0 * (double)Rg;
+        store_nt(b + site * 8u, Rh, Rg);
+        store_nt(dev_addr(0), __halves2half2(__float2half_rn((float)resh * cd.sh),
+                                             __float2half_rn((float)resg * cd.sg)));
     }
 };
 
@@ -359,16 +369,11 @@ __device__ __forceinline__ float2 load_pair(const char* __restrict__ b, uint32_t
         return *reinterpret_cast<const float2*>(base + off);
     } else {
         const float2 R = *reinterpret_cast<const float2*>(b + slot_site * 8u);
-        if constexpr (I == 0) {
-            return make_float2(L::r(0) * R.x, L::r(0) * R.y);
-        } else {
-            uint32_t off;
-            // deviation arrays start after the R pairs; population i >= 1 is entry i - 1
-            const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8 - (size_t)S * 4, S,
-                                                         slot_site, flip, off);
-            const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
-            return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
-        }
+        uint32_t off;
+        // deviation arrays start after the R pairs, one per population
+        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
+        const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
+        return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
     }
 }
 
@@ -382,46 +387,105 @@ __device__ __forceinline__ float load_h(const char* __restrict__ b, uint32_t S,
         return *reinterpret_cast<const float*>(base + off);
     } else {
         const float R = *reinterpret_cast<const float*>(b + slot_site * 8u);
-        if constexpr (I == 0) {
-            return L::r(0) * R;
-        } else {
-            uint32_t off;
-            const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8 - (size_t)S * 4, S,
-                                                         slot_site, flip, off);
-            return fmaf(__half2float(*reinterpret_cast<const __half*>(base + off)), cd.ish,
-                        L::r(I) * R);
-        }
+        uint32_t off;
+        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
+        return fmaf(__half2float(*reinterpret_cast<const __half*>(base + off)), cd.ish,
+                    L::r(I) * R);
     }
 }
 
-// Gather the Q pre-collision populations of both sets of one site.
+// phi of a gathered site, summed in float64 from the stored values and used as hi + lo
+// floats.  The BGK update relaxes h towards phi w_i and the site keeps the mass phi: a
+// float32-rounded phi would add that rounding error to the site at every step (a random
+// walk of the phase field).  With FP32 storage
+// the terms are the (exact) float32 populations.  With FP16S storage they are
+// r_i R + dev_i / scale taken from the stored words, where r_i R is exact in float64:
+// the float32-rounded decoded populations would make phi, which becomes the total the
+// next writer stores, inherit rounding errors that are identical over uniform regions
+// and so drift sum(phi) systematically.
+struct PhiAcc {
+    double r = 0.0;   // FP32: sum of populations; FP16S: sum of r_i R
+    double d = 0.0;   // FP16S: sum of dev_i / scale (exact dyadic terms)
+    __device__ __forceinline__ double value() const { return r + d; }
+};
+
+template <class L, class ST, int I, int WALLS>
+__device__ __forceinline__ float2 load_pair_acc(const char* __restrict__ b, uint32_t S,
+                                                uint32_t slot_site, bool flip, const Codec& cd,
+                                                PhiAcc& acc) {
+    if constexpr (!ST::HALF) {
+        const float2 v = load_pair<L, ST, I, WALLS>(b, S, slot_site, flip, cd);
+        acc.r += (double)v.x;
+        return v;
+    } else {
+        const float2 R = *reinterpret_cast<const float2*>(b + slot_site * 8u);
+        acc.r = fma((double)R.x, (double)L::r(I), acc.r);
+        uint32_t off;
+        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
+        const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
+        acc.d += (double)(df.x * cd.ish);
+        return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
+    }
+}
+
+template <class L, class ST, int I, int WALLS>
+__device__ __forceinline__ float load_h_acc(const char* __restrict__ b, uint32_t S,
+                                            uint32_t slot_site, bool flip, const Codec& cd,
+                                            PhiAcc& acc) {
+    if constexpr (!ST::HALF) {
+        const float v = load_h<L, ST, I, WALLS>(b, S, slot_site, flip, cd);
+        acc.r += (double)v;
+        return v;
+    } else {
+        const float R = *reinterpret_cast<const float*>(b + slot_site * 8u);
+        acc.r = fma((double)R, (double)L::r(I), acc.r);
+        uint32_t off;
+        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
+        const float d = __half2float(*reinterpret_cast<const __half*>(base + off)) * cd.ish;
+        acc.d += (double)d;
+        return d + L::r(I) * R;
+    }
+}
+
+// Gather the Q pre-collision populations of both sets of one site and its phi.
 template <class L, class ST, int WALLS>
-__device__ __forceinline__ void pull_site(const char* __restrict__ b, const Geom& G,
-                                          const Col& c, const ZRow& r, const Codec& cd,
-                                          float (&h)[L::Q], float (&g)[L::Q]) {
+__device__ __forceinline__ double pull_site(const char* __restrict__ b, const Geom& G,
+                                            const Col& c, const ZRow& r, const Codec& cd,
+                                            float (&h)[L::Q], float (&g)[L::Q]) {
+    PhiAcc acc;
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         uint32_t s;
         bool flip;
         upstream<L, i, WALLS>(c, r, s, flip);
-        const float2 v = load_pair<L, ST, i, WALLS>(b, G.S, s, flip, cd);
+        const float2 v = load_pair_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
         h[i] = v.x;
         g[i] = v.y;
     });
+    return acc.value();
 }
 
-// Gather only the h populations of one site.
+// Gather only the h populations of one site and its phi.
 template <class L, class ST, int WALLS>
-__device__ __forceinline__ void pull_site_h(const char* __restrict__ b, const Geom& G,
-                                            const Col& c, const ZRow& r, const Codec& cd,
-                                            float (&h)[L::Q]) {
+__device__ __forceinline__ double pull_site_h(const char* __restrict__ b, const Geom& G,
+                                              const Col& c, const ZRow& r, const Codec& cd,
+                                              float (&h)[L::Q]) {
+    PhiAcc acc;
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         uint32_t s;
         bool flip;
         upstream<L, i, WALLS>(c, r, s, flip);
-        h[i] = load_h<L, ST, i, WALLS>(b, G.S, s, flip, cd);
+        h[i] = load_h_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
     });
+    return acc.value();
+}
+
+// float64 phi as hi + lo floats
+__device__ __forceinline__ float split_hi_lo(double s, float& lo) {
+    const float hi = (float)s;
+    lo = (float)(s - (double)hi);
+    return hi;
 }
 
 // ---------------------------------------------------------------------------
@@ -533,17 +597,6 @@ __device__ __forceinline__ void eq_dir(const Macro& a, const EqTerms& t, float& 
     geq = fmaf(w, fmaf(a.rho, e, t.P3) + cu * t.dcoef, -0.5f * K);
 }
 
-// phi = sum_i f_i accumulated in float64 and returned as hi + lo floats.  The BGK update
-// relaxes h towards phi w_i: with a float32 phi every site would gain or lose the
-// rounding error of its own sum at every step (a random walk of the phase field).
-template <class L>
-__device__ __forceinline__ float phi_sum(const float (&f)[L::Q], float& lo) {
-    double s = (double)f[0];
-    static_for<1, L::Q>([&](auto I) { s += (double)f[decltype(I)::value]; });
-    const float hi = (float)s;
-    lo = (float)(s - (double)hi);
-    return hi;
-}
 
 // Full collision of one site, h BGK (Eq. 1) and the filtered g update (Eq. 10), with
 // each post-collision pair handed to `out` as soon as it is formed.
@@ -555,7 +608,7 @@ __device__ __forceinline__ float phi_sum(const float (&f)[L::Q], float& lo) {
 //                       + (u_a F_b + u_b F_a) - 3 u_a u_b (u.F),
 // with d = grad(phi), A = rho_dif + 3 mu (T = 1/3); the delta f^eq term of Eq. 13 is odd
 // in c and has no second moment.  Opposite velocities are handled as pairs, sharing
-// c.u, c.d, c.F and c.n.  a.phi + phi_lo is the site's phi (see phi_sum).
+// c.u, c.d, c.F and c.n.  a.phi + phi_lo is the site's phi (see PhiAcc).
 template <class L, class Out>
 __device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, float phi_lo,
                                                const float (&h)[L::Q], const float (&g)[L::Q],

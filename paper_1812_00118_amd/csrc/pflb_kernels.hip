@@ -69,33 +69,28 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                               L::USES_Y ? map_coord(y0 - 1 + rhy, G.ny, G.wy) : 0);
 
     auto ring_phi = [&](const ZRow& r) {
-        float f[Q], lo;
-        pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f);
-        return phi_sum<L>(f, lo);
+        float f[Q];
+        return (float)pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f);
     };
 
     float hA[Q], gA[Q], loA, hB[Q], gB[Q], loB;
     {   // plane z0 - 1 (phi only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
-        float f[Q], lo;
-        pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f);
-        sphi[(z0 - 1) & 3][ty + OY][tx + 1] = phi_sum<L>(f, lo);
+        float f[Q];
+        sphi[(z0 - 1) & 3][ty + OY][tx + 1] = (float)pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f);
         if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm);
         const ZRow r0 = make_zrow(G, z0);
-        pull_site<L, ST, WALLS>(src, G, own, r0, cd, hA, gA);
-        sphi[z0 & 3][ty + OY][tx + 1] = phi_sum<L>(hA, loA);
+        sphi[z0 & 3][ty + OY][tx + 1] =
+            split_hi_lo(pull_site<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA);
         if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0);
     }
     // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc).
     auto plane = [&](int z, const float (&hc)[Q], const float (&gc)[Q], float lo_c,
                      float (&hn)[Q], float (&gn)[Q], float& lo_n) {
         const ZRow rn = make_zrow(G, map_coord(z + 1, G.nz, G.wz));
-        if (z + 1 < zend) {
-            pull_site<L, ST, WALLS>(src, G, own, rn, cd, hn, gn);
-        } else {
-            pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
-        }
-        sphi[(z + 1) & 3][ty + OY][tx + 1] = phi_sum<L>(hn, lo_n);
+        const double pn64 = (z + 1 < zend) ? pull_site<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
+                                           : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
+        sphi[(z + 1) & 3][ty + OY][tx + 1] = split_hi_lo(pn64, lo_n);
         if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
         __syncthreads();
         if (active) {
@@ -242,9 +237,8 @@ k_phi(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __restric
     if (s >= N) return;
     int x, y, z;
     site_coords(G, s, x, y, z);
-    float f[L::Q], lo;
-    pull_site_h<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, f);
-    phi[s] = phi_sum<L>(f, lo);
+    float f[L::Q];
+    phi[s] = (float)pull_site_h<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, f);
 }
 
 template <class L, class ST, int WALLS>
@@ -291,11 +285,10 @@ __device__ __forceinline__ double slot_sum(const char* b, uint32_t s, uint32_t S
     } else {
         const float2 R = reinterpret_cast<const float2*>(b)[s];
         bad |= !isfinite(R.x) || !isfinite(R.y);
-        acc = (double)L::r(0) * (double)R.x;
         const __half2* dev = reinterpret_cast<const __half2*>(b + (size_t)S * 8);
-        static_for<1, L::Q>([&](auto I) {
+        static_for<0, L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const float2 d = __half22float2(dev[(size_t)(i - 1) * S + s]);
+            const float2 d = __half22float2(dev[(size_t)i * S + s]);
             bad |= !isfinite(d.x) || !isfinite(d.y);
             acc += (double)L::r(i) * (double)R.x + (double)d.x * (double)cd.ish;
         });

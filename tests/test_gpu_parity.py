@@ -138,7 +138,8 @@ def test_static_droplet_1000_steps():
     assert not bad
     assert np.abs(r["phi"] - ro["phi"]).max() <= 1e-5
     assert _jerr(r["J"], ro["J"][:2], cfg["rho_H"]) <= 1e-4
-    assert abs(m1 - m0) / m0 <= 1e-6
+    print(f"\nstatic droplet mass drift {(m1 - m0) / m0:.2e}")
+    assert abs(m1 - m0) / m0 <= 1e-7
     assert abs(m1 - mo) / mo <= 1e-6
 
 
@@ -302,7 +303,7 @@ def test_fp16s_one_step_random_state(name, q, shape, bc):
                          ids=["static_droplet", "rising_bubble"])
 def test_fp16s_error_and_mass(make, steps):
     """FP16-shifted storage against the FP64 oracle: the error per result is reported
-    (phi, P, J) and bounded; sum(phi) is conserved like FP32 storage."""
+    (phi, P, J) and bounded; sum(phi) is conserved (to 1e-10 relative)."""
     cfg = make()
     r, ro, (m0, m1, bad), mo = _run_pair(cfg, steps, storage="fp16s")
     D = 3 if cfg["lattice"] == 19 else 2
@@ -314,4 +315,5 @@ def test_fp16s_error_and_mass(make, steps):
           f"mass drift {(m1 - m0) / m0:.2e}")
     assert not bad
     assert dphi <= 1e-3
-    assert abs(m1 - m0) / m0 <= 1e-6
+    # the rest word carries R's rounding: sum(phi) is conserved to float64 level
+    assert abs(m1 - m0) / m0 <= 1e-10
