@@ -70,7 +70,7 @@ extern "C" {
 /*
  * Model and domain parameters (Section 2; Section 4 gives values per case).
  *   lattice      9 (D2Q9) or 19 (D3Q19)
- *   nx, ny, nz   sites per axis (nz = 1 for D2Q9), each >= 1
+ *   nx, ny, nz   sites per axis (nz = 1 for D2Q9), each >= 1, at most 2^28 - 64 sites
  *   bc[3]        boundary per axis x, y, z: PFLB_BC_PERIODIC or PFLB_BC_WALL (both
  *                faces of an axis alike; walls: halfway bounce-back for h and g,
  *                phi outside a wall equals phi at the adjacent site)
@@ -140,6 +140,16 @@ int pflb_get_state(pflb_ctx* ctx, float* h, float* g, void* stream);
  * caller device memory) followed by pflb_set_state. */
 int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
                      float* work, void* stream);
+
+/* Replace the state by the equilibria of given macroscopic fields (a hand-over from
+ * another model of the same flow, e.g. a learned surrogate): u = J / rho' with rho' the
+ * density read-out divides by, then pflb_equilibrium and the state load of
+ * pflb_init_fields.  Reading back returns phi, P and J up to FP32 rounding.
+ *   phi [N], P [N] (NULL: zero), J [D][N]; work: (2*Q + D)*N floats of device memory.
+ * The step counter is kept and increased by `advance` (>= 0), the number of steps the
+ * given fields lie ahead of the current state. */
+int pflb_reconstruct(pflb_ctx* ctx, const float* phi, const float* P, const float* J,
+                     float* work, int advance, void* stream);
 
 /* Enqueue nsteps fused stream-and-collide steps of both sets (Eqs. 1 and 10 with
  * the central differences of Section 2).  Returns launch errors only. */

@@ -1,0 +1,150 @@
+/*
+ * pfsur.h -- C ABI of the learned 16-step surrogate that runs beside the phase-field
+ * lattice Boltzmann solver (libpflb), on AMD gfx950 with BF16 matrix cores.
+ *
+ * The surrogate is not part of the paper.  It maps the macroscopic state (phi, P, rho u)
+ * of a D2Q9 periodic domain at step n to the state at step n + 16 through a 4-level
+ * convolutional U-Net (17 circular-padded 3x3 convolutions with 32/64/128/256 channels
+ * and SiLU, 2x2 average pooling, nearest 2x upsampling with skip concatenation, and a
+ * 1x1 head predicting the normalised residual).  Convolutions are implicit GEMMs on
+ * BF16 MFMA with FP32 accumulation; weights are kept as FP32 masters with BF16 copies.
+ * The plain lattice Boltzmann step is the fallback and the judge of the surrogate's
+ * error (pflb_advance_guarded).
+ *
+ * Conventions (as in pflb.h): device pointers unless stated "host"; the caller owns
+ * activations, batches and workspaces; the library owns the weights and optimiser
+ * state of a context.  Tensors are NHWC: [B][H][W][C], C fastest.  Returns 0 or a
+ * negative PFLB_ERR_* code.
+ */
+#ifndef PFSUR_H
+#define PFSUR_H
+
+#include <stddef.h>
+
+#include "pflb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFSUR_IN_CH   8   /* input channels: phi, P, J_x, J_y, log10(rho_H/rho_L), 3 zero */
+#define PFSUR_OUT_CH  4   /* output channels: normalised residual of phi, P, J_x, J_y    */
+#define PFSUR_STEPS  16   /* lattice Boltzmann steps one surrogate application replaces  */
+
+/* Geometry and the normalisation of the fields.
+ *   H, W         grid (multiples of 8, >= 16)
+ *   max_batch    largest batch a workspace is sized for (>= 1)
+ *   in_shift[4], in_scale[4]   x_c = (field_c - shift_c) * scale_c for phi, P, J_x, J_y
+ *   out_scale[4] field_c(n+16) = field_c(n) + out_c * out_scale[c]
+ *   lrr_scale    channel 4 = log10(rho_H / rho_L) * lrr_scale */
+typedef struct pfsur_cfg {
+    int H, W;
+    int max_batch;
+    float in_shift[4];
+    float in_scale[4];
+    float out_scale[4];
+    float lrr_scale;
+} pfsur_cfg;
+
+typedef struct pfsur_ctx pfsur_ctx;
+
+/* Number of FP32 parameters: for every 3x3 layer in network order (e0a, e0b, e1a, e1b,
+ * e2a, e2b, b3a, b3b, u2, d2a, d2b, u1, d1a, d1b, u0, d0a, d0b) its weights
+ * [Cout][3][3][Cin] then its bias [Cout]; then the head's [4][32] and [4]. */
+size_t pfsur_num_params(void);
+
+/* Create a context on the current device: allocates the FP32 master weights, their
+ * BF16 copies and the Adam moments (zero weights until pfsur_set_params). */
+int pfsur_create(const pfsur_cfg* cfg, pfsur_ctx** out);
+void pfsur_destroy(pfsur_ctx* ctx);
+const char* pfsur_last_error(const pfsur_ctx* ctx);
+
+/* Parameters to / from a HOST float array of pfsur_num_params() values (layout above).
+ * Setting parameters also resets the Adam state. */
+int pfsur_set_params(pfsur_ctx* ctx, const float* host);
+int pfsur_get_params(pfsur_ctx* ctx, float* host);
+
+/* Bytes of the caller's device workspace for a batch (training = 1: forward
+ * activations plus the backward buffers). */
+size_t pfsur_workspace_bytes(const pfsur_cfg* cfg, int batch, int training);
+
+/* Pack a batch of solver fields into the network input x (BF16 NHWC, PFSUR_IN_CH):
+ *   phi, P [batch][H][W], J [batch][2][H][W] (the pflb_read layout per sample),
+ *   lrr[batch] host array of log10(rho_H/rho_L). */
+int pfsur_pack(pfsur_ctx* ctx, const float* phi, const float* P, const float* J,
+               const double* lrr, int batch, void* x, void* stream);
+
+/* Training target from two solver states of the same batch, 16 steps apart:
+ * y [batch][H][W][4] FP32, y_c = (field1_c - field0_c) / out_scale[c] (layouts as in
+ * pfsur_pack). */
+int pfsur_pack_target(pfsur_ctx* ctx, const float* phi0, const float* P0, const float* J0,
+                      const float* phi1, const float* P1, const float* J1, int batch, float* y,
+                      void* stream);
+
+/* out [batch][H][W][4] FP32 = network(x) (x: BF16 NHWC [batch][H][W][8]). */
+int pfsur_forward(pfsur_ctx* ctx, const void* x, float* out, int batch, void* workspace,
+                  void* stream);
+
+/* Apply a predicted residual: field_c += out_c * out_scale[c] in place, for
+ * phi, P [batch][H][W] and J [batch][2][H][W]. */
+int pfsur_apply(pfsur_ctx* ctx, const float* out, float* phi, float* P, float* J, int batch,
+                void* stream);
+
+/* One training step on (x, y): forward, MSE loss against y [batch][H][W][4] FP32,
+ * backward, Adam with learning rate lr (beta1 0.9, beta2 0.999, eps 1e-8).  *loss
+ * (host) receives the batch loss of the forward pass; synchronous. */
+int pfsur_train_step(pfsur_ctx* ctx, const void* x, const float* y, int batch, float lr,
+                     float* loss, void* workspace, void* stream);
+
+/* Gradients of the MSE loss with respect to all parameters, without an update, into a
+ * HOST array of pfsur_num_params() floats (for checking against a reference). */
+int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, float* host_grad,
+                    float* loss, void* workspace, void* stream);
+
+/* Guarded advance of a D2Q9 lattice Boltzmann context by `windows` x 16 steps.  For
+ * each window the surrogate predicts the state 16 steps ahead; it is accepted when
+ * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)| and, on every
+ * check_every-th window (0: never), when max|phi_out - phi_LB| <= phi_tol against 16
+ * plain steps taken from the same state.  An accepted prediction becomes the new state
+ * (pflb_reconstruct); otherwise the 16 plain steps are taken.  lrr is
+ * log10(rho_H/rho_L) of the context.  work must hold pfsur_guard_work_bytes().
+ * *n_fallback (host) counts the windows that fell back.  Synchronous. */
+size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg);
+int pflb_advance_guarded(pflb_ctx* lb, pfsur_ctx* sur, int windows, double lrr,
+                         double mass_tol, double phi_tol, int check_every, int* n_fallback,
+                         void* work, void* stream);
+
+/* The accept rule of pflb_advance_guarded, a pure host function (1 accept, 0 reject):
+ * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums) and,
+ * when checked != 0, phi_err <= phi_tol. */
+int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, int checked,
+                       double phi_err, double phi_tol);
+
+/* Building blocks, stateless (no context): one circular-padded 3x3 convolution as the
+ * network computes it, for testing and reuse.
+ *   mode 0: x is [batch][H][W][Cin]; mode 1: x is [batch][H/2][W/2][Cin], read through
+ *   2x nearest upsampling (H, W even); mode 2: x is [batch][2H][2W][Cin], read through
+ *   2x2 average pooling (each pooled value rounded to BF16).
+ *   x BF16 NHWC, Cin a multiple of 8; w BF16 [Cout][3][3][Cin]; b FP32 [Cout] or NULL.
+ * pfsur_conv_fwd writes y_pre FP32 [batch][H][W][Cout] = conv(x) + b and/or
+ * y_act BF16 = act ? silu(y_pre) : y_pre (either may be NULL).
+ * pfsur_conv_wgrad writes dw FP32 [Cout][3][3][Cin] = sum_p dy[p, o] x_mode[p + tap, c]
+ * and db FP32 [Cout] = sum_p dy[p, o] (NULL: skip) from dy BF16 [batch][H][W][Cout]
+ * (Cout a multiple of 8), using `work` of pfsur_conv_wgrad_work_bytes() bytes.
+ * Requires batch * H * W <= 2^26. */
+int pfsur_conv_fwd(const void* x, int batch, int H, int W, int Cin, int Cout, int mode,
+                   const void* w, const float* b, int act, float* y_pre, void* y_act,
+                   void* stream);
+size_t pfsur_conv_wgrad_work_bytes(int batch, int H, int W, int Cin, int Cout);
+int pfsur_conv_wgrad(const void* x, const void* dy, int batch, int H, int W, int Cin, int Cout,
+                     int mode, float* dw, float* db, void* work, void* stream);
+
+/* Checkpoint / restore the parameters and optimiser state (host file). */
+int pfsur_save(pfsur_ctx* ctx, const char* path);
+int pfsur_load(pfsur_ctx* ctx, const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFSUR_H */

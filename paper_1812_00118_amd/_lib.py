@@ -1,4 +1,4 @@
-"""ctypes declarations of the C ABI in include/pflb.h."""
+"""ctypes declarations of the C ABI in include/pflb.h and include/pfsur.h."""
 import ctypes
 import os
 
@@ -37,6 +37,12 @@ class Params(ctypes.Structure):
                 ("scale_log2", ctypes.c_int * 2)]
 
 
+class SurCfg(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
+                ("out_scale", ctypes.c_float * 4), ("lrr_scale", ctypes.c_float)]
+
+
 _vp = ctypes.c_void_p
 _SIGS = {
     "pflb_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(_vp)]),
@@ -48,6 +54,7 @@ _SIGS = {
     "pflb_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pflb_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pflb_init_fields": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pflb_reconstruct": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "pflb_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "pflb_read": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pflb_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
@@ -55,6 +62,38 @@ _SIGS = {
     "pflb_step_count": (ctypes.c_longlong, [_vp]),
     "pflb_save": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
     "pflb_load": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
+    # surrogate
+    "pfsur_num_params": (ctypes.c_size_t, []),
+    "pfsur_create": (ctypes.c_int, [ctypes.POINTER(SurCfg), ctypes.POINTER(_vp)]),
+    "pfsur_destroy": (None, [_vp]),
+    "pfsur_last_error": (ctypes.c_char_p, [_vp]),
+    "pfsur_set_params": (ctypes.c_int, [_vp, _vp]),
+    "pfsur_get_params": (ctypes.c_int, [_vp, _vp]),
+    "pfsur_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int, ctypes.c_int]),
+    "pfsur_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.c_int, _vp, _vp]),
+    "pfsur_pack_target": (ctypes.c_int, [_vp] * 7 + [ctypes.c_int, _vp, _vp]),
+    "pfsur_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
+    "pfsur_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "pfsur_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
+                                        ctypes.POINTER(ctypes.c_float), _vp, _vp]),
+    "pfsur_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp,
+                                       ctypes.POINTER(ctypes.c_float), _vp, _vp]),
+    "pfsur_guard_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg)]),
+    "pflb_advance_guarded": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int), _vp, _vp]),
+    "pfsur_guard_accept": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "pfsur_conv_fwd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
+                                      _vp, _vp]),
+    "pfsur_conv_wgrad_work_bytes": (ctypes.c_size_t, [ctypes.c_int] * 5),
+    "pfsur_conv_wgrad": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                        _vp]),
+    "pfsur_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "pfsur_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
 }
 
 _lib = None

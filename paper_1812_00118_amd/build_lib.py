@@ -1,4 +1,5 @@
-"""Compile the HIP sources of the package into libpflb.so (gfx950) in the package dir."""
+"""Compile the HIP sources of the package (lattice Boltzmann step and surrogate) into
+libpflb.so (gfx950) in the package dir."""
 import os
 import subprocess
 import sys
@@ -8,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpflb.so")
 
-SOURCES = ["pflb_kernels.hip", "pflb_api.hip"]
+SOURCES = ["pflb_kernels.hip", "pflb_api.hip", "sur_kernels.hip", "sur_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -39,7 +39,8 @@ std::string check_params(const pflb_params* p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "nx, ny, nz must be >= 1";
     if (p->lattice == 9 && p->nz != 1) return "D2Q9 needs nz = 1";
     const double n = (double)p->nx * p->ny * p->nz;
-    if (n > 2147483647.0 - 4096.0) return "domain larger than 2^31 sites";
+    // population addresses are 32-bit byte offsets from a per-direction base
+    if (n > 268435456.0 - 64.0) return "domain larger than 2^28 - 64 sites";
     for (int a = 0; a < 3; ++a)
         if (p->bc[a] != PFLB_BC_PERIODIC && p->bc[a] != PFLB_BC_WALL) return "bc must be 0 or 1";
     if (!(finite(p->rho_L) && p->rho_L > 0) || !(finite(p->rho_H) && p->rho_H > 0))
@@ -280,6 +281,24 @@ int pflb_init_fields(pflb_ctx* c, const float* phi, const float* u, const float*
     return pflb_set_state(c, h, g, stream);
 }
 
+int pflb_reconstruct(pflb_ctx* c, const float* phi, const float* P, const float* J, float* work,
+                     int advance, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!phi || !J || !work) return fail(c, PFLB_ERR_PARAM, "NULL field or work pointer");
+    if (advance < 0) return fail(c, PFLB_ERR_PARAM, "advance < 0");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    float* u = work + (size_t)2 * c->Q * c->N;
+    hipError_t e = launch_u_from_j(a, c->N, phi, J, u);
+    if (e != hipSuccess) return hip_fail(c, e, "u_from_j launch");
+    const long long steps = c->steps;
+    r = pflb_init_fields(c, phi, u, P, work, stream);
+    if (r) return r;
+    c->steps = steps + advance;
+    return PFLB_OK;
+}
+
 int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
     int r = need_bound(c);
     if (r) return r;
@@ -396,3 +415,13 @@ int pflb_load(pflb_ctx* c, const char* path, void* stream) {
 }
 
 }  // extern "C"
+
+int pflb_ctx_info(const pflb_ctx* c, CtxInfo* out) {
+    if (!c || !out) return PFLB_ERR_PARAM;
+    out->q = c->p.lattice;
+    out->nx = c->p.nx; out->ny = c->p.ny; out->nz = c->p.nz;
+    for (int a = 0; a < 3; ++a) out->bc[a] = c->p.bc[a];
+    out->N = c->N;
+    out->bound = c->bound;
+    return PFLB_OK;
+}

@@ -23,6 +23,8 @@ struct Launch {
 hipError_t launch_step(const Launch& a, const void* src, void* dst);
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
                               const float* P, float* h, float* g);
+hipError_t launch_u_from_j(const Launch& a, uint32_t N, const float* phi, const float* J,
+                          float* u);
 hipError_t launch_set_state(const Launch& a, uint32_t N, const float* h, const float* g,
                             void* b);
 hipError_t launch_get_state(const Launch& a, uint32_t N, const void* b, float* h, float* g);
@@ -30,8 +32,19 @@ hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, f
                        float* J, float* U);
 hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch);
 size_t state_bytes(int q, bool half, uint32_t S);
+
+// shape of a context as the user gave it (nx, ny, nz, bc), for the surrogate hand-over
+struct CtxInfo {
+    int q, nx, ny, nz;
+    int bc[3];
+    uint32_t N;
+    bool bound;
+};
 size_t mass_scratch_bytes();
 size_t mass_result_offset();
 size_t mass_flag_offset();
 
 }  // namespace pflb
+
+struct pflb_ctx;
+int pflb_ctx_info(const ::pflb_ctx* c, pflb::CtxInfo* out);

@@ -178,6 +178,28 @@ k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
     });
 }
 
+// velocity from momentum for a hand-over of macroscopic fields: u = J / rho' with
+// rho' = rho + beta rho_dif lap(phi) / 4, the density that read-out divides by
+template <class L>
+__global__ void __launch_bounds__(256)
+k_u_from_j(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
+           const float* __restrict__ J, float* __restrict__ u) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    int x, y, z;
+    site_coords(G, s, x, y, z);
+    float pn[L::Q];
+    phi_stencil<L>(G, phi, x, y, z, pn);
+    float ls = 0.f;
+    static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i & 1) ls = fmaf(L::w(i), (pn[i] - pn[0]) + (pn[i + 1] - pn[0]), ls);
+    });
+    const float rho = fmaf(pn[0], m.rho_dif, m.rho_L);
+    const float irp = 1.0f / fmaf(m.beta * 0.25f * m.rho_dif, 6.0f * ls, rho);
+    for (int c = 0; c < L::D; ++c) u[(size_t)c * N + s] = J[(size_t)c * N + s] * irp;
+}
+
 // ---------------------------------------------------------------------------
 // pre-collision distributions <-> pull storage
 // slot (y, j) is gathered by x = y + c_j as population j when x is a fluid site,
@@ -411,6 +433,17 @@ hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, con
                               const float* P, float* h, float* g) {
     return a.q == 19 ? equilibrium_t<LatD3Q19>(a, N, phi, u, P, h, g)
                      : equilibrium_t<LatD2Q9>(a, N, phi, u, P, h, g);
+}
+
+hipError_t launch_u_from_j(const Launch& a, uint32_t N, const float* phi, const float* J,
+                          float* u) {
+    if (a.q == 19)
+        hipLaunchKernelGGL((k_u_from_j<LatD3Q19>), grid1(N), dim3(256), 0, a.stream, a.G, a.m, N,
+                           phi, J, u);
+    else
+        hipLaunchKernelGGL((k_u_from_j<LatD2Q9>), grid1(N), dim3(256), 0, a.stream, a.G, a.m, N,
+                           phi, J, u);
+    return hipGetLastError();
 }
 
 template <class L, class ST>

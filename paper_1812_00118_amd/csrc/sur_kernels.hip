@@ -1,0 +1,575 @@
+// HIP kernels of the convolutional surrogate (gfx950, BF16 MFMA, FP32 accumulation).
+//
+// Activations are NHWC BF16; gradients FP32.  A 3x3 convolution with circular padding
+//   out[p, o] = b[o] + sum_{tap, c} in[p + off(tap), c] w[o, tap, c],  off(tap) = (tap/3 - 1,
+//   tap%3 - 1) in (y, x), is an implicit GEMM with M = pixels, N = Cout, K = 9 Cin; the
+// K index runs over (tap, channel group of 8).  The same kernel computes the input
+// gradient with the weights transposed and the taps mirrored.  The weight gradient is a
+// GEMM over pixels (K = B H W) with the tiles transposed through LDS.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sur_internal.hpp"
+
+namespace pfsur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// 8 consecutive input channels at output-resolution pixel (b, y, x), through the layer's
+// input mode (same resolution, 2x nearest upsampling, or 2x2 average pooling).
+__device__ __forceinline__ bf16x8 gather8(const GatherP& g, int b, int y, int x, int c) {
+    if (g.mode == MODE_UP) {
+        y >>= 1;
+        x >>= 1;
+    }
+    if (g.mode != MODE_POOL) {
+        const size_t idx = (((size_t)b * g.Hin + y) * g.Win + x) * g.cs + g.c0 + c;
+        return *reinterpret_cast<const bf16x8*>(g.p + idx);
+    }
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const size_t idx = (((size_t)b * g.Hin + 2 * y + i) * g.Win + 2 * x + j) * g.cs + g.c0 + c;
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(g.p + idx);
+            for (int k = 0; k < 8; ++k) acc[k] += (float)v[k];
+        }
+    bf16x8 r;
+    for (int k = 0; k < 8; ++k) r[k] = (__bf16)(0.25f * acc[k]);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM 3x3 convolution.  A workgroup of 4 waves covers 256 output pixels x 32
+// output channels; a wave covers 64 pixels (4 MFMA row blocks) x 32 channels (2 column
+// blocks) with v_mfma_f32_16x16x32_bf16, whose lane l holds A row l%16 / B column l%16
+// with K elements 8(l/16)..8(l/16)+7, and C rows 4(l/16)..+3 of column l%16.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_conv3x3(ConvP a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int P = a.B * a.H * a.W;
+    const int p0 = blockIdx.x * 256 + wave * 64;
+    const int co0 = blockIdx.y * 32;
+    const int cg_per_tap = a.g.C >> 3;               // channel groups of 8 per tap
+    const int nkg = 9 * cg_per_tap;
+    // this lane's pixel in each of the 4 row blocks
+    int pb[4], py[4], px[4];
+    bool pv[4];
+    for (int mb = 0; mb < 4; ++mb) {
+        const int p = p0 + mb * 16 + r16;
+        pv[mb] = p < P;
+        const int pp = pv[mb] ? p : 0;
+        px[mb] = pp % a.W;
+        py[mb] = (pp / a.W) % a.H;
+        pb[mb] = pp / (a.W * a.H);
+    }
+    f32x4 acc[4][2];
+    for (int mb = 0; mb < 4; ++mb)
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = 0; 4 * s < nkg; ++s) {
+        const int kg = 4 * s + q;
+        const bool kv = kg < nkg;
+        const int tap = kv ? kg / cg_per_tap : 0;
+        const int cg = kv ? kg - tap * cg_per_tap : 0;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        bf16x8 A[4], Bm[2];
+        for (int mb = 0; mb < 4; ++mb)
+            A[mb] = (kv && pv[mb]) ? gather8(a.g, pb[mb], wrap(py[mb] + dy, a.H), wrap(px[mb] + dx, a.W), cg * 8)
+                                   : zero8;
+        for (int nb = 0; nb < 2; ++nb) {
+            const int co = co0 + nb * 16 + r16;
+            Bm[nb] = (kv && co < a.Cout)
+                         ? *reinterpret_cast<const bf16x8*>(a.w + (size_t)co * 9 * a.g.C + (size_t)kg * 8)
+                         : zero8;
+        }
+        for (int mb = 0; mb < 4; ++mb)
+            for (int nb = 0; nb < 2; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mb], Bm[nb], acc[mb][nb], 0, 0, 0);
+    }
+    // epilogue
+    for (int nb = 0; nb < 2; ++nb) {
+        const int co = co0 + nb * 16 + r16;
+        if (co >= a.Cout) continue;
+        const float bias = a.bias ? a.bias[co] : 0.0f;
+        for (int mb = 0; mb < 4; ++mb)
+            for (int j = 0; j < 4; ++j) {
+                const int p = p0 + mb * 16 + 4 * q + j;
+                if (p >= P) continue;
+                const float v = acc[mb][nb][j] + bias;
+                if (a.zout) a.zout[(size_t)p * a.Cout + co] = (__bf16)v;
+                if (a.out)
+                    a.out[(size_t)p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
+                if (a.fout) {
+                    float* f = a.fout + (size_t)p * a.f_cs + a.f_c0 + co;
+                    *f = a.f_accum ? *f + v : v;
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient dW[o, tap, c] = sum_p dz[p, o] in[p + off(tap), c] over a pixel
+// range per workgroup (split K).  A workgroup covers 32 output channels x one tap x
+// 32 input channels; each wave takes every 4th step of 32 pixels, transposes its dz and
+// input tiles through its own LDS region so that the MFMA operands (8 consecutive
+// pixels of one channel) are contiguous, and the 4 wave results are summed in a fixed
+// order before the partial is written.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_wgrad(WgradP a) {
+    __shared__ __bf16 sA[4][32][40];   // [wave][out channel][pixel] (+8 pad)
+    __shared__ __bf16 sB[4][32][40];   // [wave][in channel][pixel]
+    __shared__ float sred[4][32][33];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, r16 = lane & 15;
+    const int co0 = blockIdx.x * 32;
+    const int cblocks = (a.g.C + 31) / 32;
+    const int tap = blockIdx.y / cblocks;
+    const int ci0 = (blockIdx.y % cblocks) * 32;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int P = a.B * a.H * a.W;
+    const int pbeg = blockIdx.z * a.px_per_split;
+    const int pend = min(P, pbeg + a.px_per_split);
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int nsteps = (pend - pbeg + 31) / 32;
+    const int my_steps = (nsteps + 3) / 4;            // uniform trip count for the barriers
+    for (int t = 0; t < my_steps; ++t) {
+        const int step = t * 4 + wave;
+        const int ps = pbeg + step * 32;
+        // each lane loads two (pixel, channel group) pairs of each tile
+        for (int rep = 0; rep < 2; ++rep) {
+            const int idx = rep * 64 + lane;          // 0..127: pixel = idx / 4, group = idx % 4
+            const int pl = idx >> 2, grp = idx & 3;
+            const int p = ps + pl;
+            const bool ok = step < nsteps && p < pend;
+            bf16x8 va = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0}, vb = va;
+            if (ok) {
+                const int co = co0 + grp * 8;
+                if (co < a.Cout) va = *reinterpret_cast<const bf16x8*>(a.dz + (size_t)p * a.Cout + co);
+                const int ci = ci0 + grp * 8;
+                if (ci < a.g.C) {
+                    const int x = p % a.W, y = (p / a.W) % a.H, b = p / (a.W * a.H);
+                    vb = gather8(a.g, b, wrap(y + dy, a.H), wrap(x + dx, a.W), ci);
+                }
+            }
+            for (int k = 0; k < 8; ++k) {
+                sA[wave][grp * 8 + k][pl] = va[k];
+                sB[wave][grp * 8 + k][pl] = vb[k];
+            }
+        }
+        __syncthreads();
+        bf16x8 A[2], Bm[2];
+        for (int i = 0; i < 2; ++i) {
+            A[i] = *reinterpret_cast<const bf16x8*>(&sA[wave][i * 16 + r16][8 * q]);
+            Bm[i] = *reinterpret_cast<const bf16x8*>(&sB[wave][i * 16 + r16][8 * q]);
+        }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], Bm[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // C: rows = out channels 16 i + 4 q + e, columns = in channels 16 j + r16
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) sred[wave][16 * i + 4 * q + e][16 * j + r16] = acc[i][j][e];
+    __syncthreads();
+    for (int k = threadIdx.x; k < 32 * 32; k += 256) {
+        const int o = k >> 5, c = k & 31;
+        const float v = sred[0][o][c] + sred[1][o][c] + sred[2][o][c] + sred[3][o][c];
+        const int co = co0 + o, ci = ci0 + c;
+        if (co < a.Cout && ci < a.g.C)
+            a.part[(size_t)blockIdx.z * a.Cout * 9 * a.g.C + ((size_t)co * 9 + tap) * a.g.C + ci] = v;
+    }
+}
+
+// out[i] = sum_s part[s][i] (fixed order) (+ out[i] if accumulate)
+__global__ void k_reduce_splits(const float* __restrict__ part, int nsplit, size_t n,
+                                float* __restrict__ out, int accumulate) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
+    out[i] = accumulate ? out[i] + s : s;
+}
+
+// column sums of a [P][C] BF16 matrix over a pixel range per block: part[blk][C]
+__global__ void __launch_bounds__(256) k_colsum(const __bf16* __restrict__ m, int P, int C,
+                                                int px_per_block, float* __restrict__ part) {
+    __shared__ float s[256];
+    const int c = threadIdx.x % 32 + 32 * blockIdx.y;
+    const int r = threadIdx.x / 32;                   // 8 row lanes
+    const int pb = blockIdx.x * px_per_block, pe = min(P, pb + px_per_block);
+    float acc = 0.f;
+    if (c < C)
+        for (int p = pb + r; p < pe; p += 8) acc += (float)m[(size_t)p * C + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (r == 0 && c < C) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += s[k * 32 + threadIdx.x % 32];
+        part[(size_t)blockIdx.x * C + c] = t;
+    }
+}
+
+// dz[p, c] = d_act[p, c0 + c] * silu'(z[p, c])
+__global__ void k_silu_bwd(const float* __restrict__ dact, int cs, int c0, const __bf16* __restrict__ z,
+                           size_t P, int C, __bf16* __restrict__ dz) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= P * C) return;
+    const size_t p = i / C;
+    const int c = (int)(i - p * C);
+    dz[i] = (__bf16)(dact[p * cs + c0 + c] * silu_grad((float)z[i]));
+}
+
+// grad_hi[b, 2y+i, 2x+j, c0 + c] += dx_lo[b, y, x, c] / 4   (average pooling adjoint)
+__global__ void k_unpool_add(const float* __restrict__ dlo, int B, int Hl, int Wl, int C,
+                             float* __restrict__ ghi, int cs, int c0) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t n = (size_t)B * 4 * Hl * Wl * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    size_t p = i / C;
+    const int x = (int)(p % (2 * Wl));
+    p /= 2 * Wl;
+    const int y = (int)(p % (2 * Hl));
+    const int b = (int)(p / (2 * Hl));
+    ghi[(((size_t)b * 2 * Hl + y) * 2 * Wl + x) * cs + c0 + c] +=
+        0.25f * dlo[(((size_t)b * Hl + y / 2) * Wl + x / 2) * C + c];
+}
+
+// grad_lo[b, y, x, c0 + c] (+)= sum_{i,j} dx_hi[b, 2y+i, 2x+j, c]   (upsampling adjoint)
+__global__ void k_sumpool(const float* __restrict__ dhi, int B, int Hl, int Wl, int C,
+                          float* __restrict__ glo, int cs, int c0, int acc) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t n = (size_t)B * Hl * Wl * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const size_t p = i / C;
+    const int x = (int)(p % Wl);
+    const int y = (int)((p / Wl) % Hl);
+    const int b = (int)(p / ((size_t)Wl * Hl));
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int bb = 0; bb < 2; ++bb)
+            s += dhi[(((size_t)b * 2 * Hl + 2 * y + a) * 2 * Wl + 2 * x + bb) * C + c];
+    float* g = glo + p * cs + c0 + c;
+    *g = acc ? *g + s : s;
+}
+
+// 1x1 head: out[p, o] = bh[o] + sum_c act[p, c] wh[o, c]   (32 -> 4)
+__global__ void k_head_fwd(const __bf16* __restrict__ act, int cs, int c0, const float* __restrict__ wh,
+                           const float* __restrict__ bh, size_t P, float* __restrict__ out) {
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    float o[4] = {bh[0], bh[1], bh[2], bh[3]};
+    for (int c = 0; c < 32; ++c) {
+        const float v = (float)act[p * cs + c0 + c];
+        for (int k = 0; k < 4; ++k) o[k] += v * wh[k * 32 + c];
+    }
+    for (int k = 0; k < 4; ++k) out[p * 4 + k] = o[k];
+}
+
+// head backward: dact[p, c] = sum_o dout[p, o] wh[o, c]; per-block partial sums
+// part[blk][o * 32 + c] of dwh[o, c] = sum_p dout[p, o] act[p, c] and part[blk][128 + o] of
+// dbh[o] = sum_p dout[p, o]
+__global__ void __launch_bounds__(256) k_head_bwd(const __bf16* __restrict__ act, int cs, int c0,
+                                                  const float* __restrict__ wh,
+                                                  const float* __restrict__ dout, size_t P,
+                                                  float* __restrict__ dact, int dcs, int dc0,
+                                                  float* __restrict__ part) {
+    __shared__ float s[4][256];
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    float d[4] = {0, 0, 0, 0};
+    if (p < P)
+        for (int k = 0; k < 4; ++k) d[k] = dout[p * 4 + k];
+    float* blk = part + (size_t)blockIdx.x * 132;
+    for (int c = 0; c < 33; ++c) {
+        const float v = (c < 32) ? (p < P ? (float)act[p * cs + c0 + c] : 0.f) : 1.0f;
+        if (c < 32 && p < P) {
+            float g = 0.f;
+            for (int k = 0; k < 4; ++k) g += d[k] * wh[k * 32 + c];
+            dact[p * dcs + dc0 + c] = g;
+        }
+        for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = d[k] * v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < (unsigned)w)
+                for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x < 4) blk[c < 32 ? threadIdx.x * 32 + c : 128 + threadIdx.x] = s[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// MSE: per-block partial sums of (out - y)^2 and dout = 2 (out - y) / n
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ out, const float* __restrict__ y,
+                                             size_t n, float* __restrict__ dout,
+                                             double* __restrict__ part) {
+    __shared__ double s[256];
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (i < n) {
+        const float d = out[i] - y[i];
+        e = (double)d * d;
+        if (dout) dout[i] = 2.0f * d / (float)n;
+    }
+    s[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_sum_f64(const double* __restrict__ part, int n, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        out[0] = s;
+    }
+}
+
+// Adam (Kingma & Ba) on FP32 masters
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float c1, float c2) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// BF16 copies of one layer's weights: wf [Cout][9][Cin] and, for the input gradient,
+// wt [Cin][9][Cout] with the taps mirrored (tap -> 8 - tap)
+__global__ void k_weights_bf16(const float* __restrict__ w, int Cout, int Cin, __bf16* __restrict__ wf,
+                               __bf16* __restrict__ wt) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t n = (size_t)Cout * 9 * Cin;
+    if (i >= n) return;
+    const int ci = (int)(i % Cin);
+    const int tap = (int)((i / Cin) % 9);
+    const int co = (int)(i / (9 * (size_t)Cin));
+    wf[i] = (__bf16)w[i];
+    if (wt) wt[((size_t)ci * 9 + (8 - tap)) * Cout + co] = (__bf16)w[i];
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// network input of one sample from solver fields: x[y, x, :] = ((phi - s0) k0,
+// (P - s1) k1, (Jx - s2) k2, (Jy - s3) k3, lrr lrr_scale, 0, 0, 0)
+__global__ void k_pack(const float* __restrict__ phi, const float* __restrict__ P,
+                       const float* __restrict__ J, float lrr, Norm nm, size_t HW,
+                       __bf16* __restrict__ x) {
+    const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= HW) return;
+    const float f[4] = {phi[s], P[s], J[s], J[HW + s]};
+    bf16x8 v;
+    for (int c = 0; c < 4; ++c) v[c] = (__bf16)((f[c] - nm.shift[c]) * nm.scale[c]);
+    v[4] = (__bf16)(lrr * nm.lrr_scale);
+    v[5] = v[6] = v[7] = (__bf16)0.0f;
+    *reinterpret_cast<bf16x8*>(x + s * 8) = v;
+}
+
+// training target of one sample: y[s, c] = (f1_c - f0_c) / out_scale[c]
+__global__ void k_pack_target(const float* __restrict__ phi0, const float* __restrict__ P0,
+                              const float* __restrict__ J0, const float* __restrict__ phi1,
+                              const float* __restrict__ P1, const float* __restrict__ J1, Norm nm,
+                              size_t HW, float* __restrict__ y) {
+    const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= HW) return;
+    float4 v;
+    v.x = (phi1[s] - phi0[s]) / nm.out_scale[0];
+    v.y = (P1[s] - P0[s]) / nm.out_scale[1];
+    v.z = (J1[s] - J0[s]) / nm.out_scale[2];
+    v.w = (J1[HW + s] - J0[HW + s]) / nm.out_scale[3];
+    reinterpret_cast<float4*>(y)[s] = v;
+}
+
+__global__ void k_apply(const float* __restrict__ out, Norm nm, int B, size_t HW,
+                        float* __restrict__ phi, float* __restrict__ P, float* __restrict__ J) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)B * HW) return;
+    const size_t b = i / HW, s = i - b * HW;
+    phi[i] += out[i * 4 + 0] * nm.out_scale[0];
+    P[i] += out[i * 4 + 1] * nm.out_scale[1];
+    J[(b * 2) * HW + s] += out[i * 4 + 2] * nm.out_scale[2];
+    J[(b * 2 + 1) * HW + s] += out[i * 4 + 3] * nm.out_scale[3];
+}
+
+// max |a - b| per block (for the surrogate-vs-solver check)
+__global__ void __launch_bounds__(256) k_maxdiff(const float* __restrict__ a, const float* __restrict__ b,
+                                                 size_t n, float* __restrict__ part) {
+    __shared__ float s[256];
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(a[i] - b[i]));
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// sum of a float field in float64, per block
+__global__ void __launch_bounds__(256) k_sum_field(const float* __restrict__ a, size_t n,
+                                                   double* __restrict__ part) {
+    __shared__ double s[256];
+    double m = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        m += (double)a[i];
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t conv3x3(const ConvP& a, hipStream_t st) {
+    const int P = a.B * a.H * a.W;
+    hipLaunchKernelGGL(k_conv3x3, dim3((P + 255) / 256, (a.Cout + 31) / 32), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t wgrad(const WgradP& a, hipStream_t st) {
+    const int cb = (a.g.C + 31) / 32;
+    const int P = a.B * a.H * a.W;
+    const int nsplit = (P + a.px_per_split - 1) / a.px_per_split;
+    hipLaunchKernelGGL(k_wgrad, dim3((a.Cout + 31) / 32, 9 * cb, nsplit), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t reduce_splits(const float* part, int nsplit, size_t n, float* out, int acc,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_splits, dim3(blocks(n)), dim3(256), 0, st, part, nsplit, n, out, acc);
+    return hipGetLastError();
+}
+
+hipError_t colsum(const __bf16* m, int P, int C, int px_per_block, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum, dim3((P + px_per_block - 1) / px_per_block, (C + 31) / 32),
+                       dim3(256), 0, st, m, P, C, px_per_block, part);
+    return hipGetLastError();
+}
+
+hipError_t silu_bwd(const float* dact, int cs, int c0, const __bf16* z, size_t P, int C,
+                    __bf16* dz, hipStream_t st) {
+    hipLaunchKernelGGL(k_silu_bwd, dim3(blocks(P * C)), dim3(256), 0, st, dact, cs, c0, z, P, C, dz);
+    return hipGetLastError();
+}
+
+hipError_t unpool_add(const float* dlo, int B, int Hl, int Wl, int C, float* ghi, int cs, int c0,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_unpool_add, dim3(blocks((size_t)B * 4 * Hl * Wl * C)), dim3(256), 0, st,
+                       dlo, B, Hl, Wl, C, ghi, cs, c0);
+    return hipGetLastError();
+}
+
+hipError_t sumpool(const float* dhi, int B, int Hl, int Wl, int C, float* glo, int cs, int c0,
+                   int acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_sumpool, dim3(blocks((size_t)B * Hl * Wl * C)), dim3(256), 0, st, dhi, B,
+                       Hl, Wl, C, glo, cs, c0, acc);
+    return hipGetLastError();
+}
+
+hipError_t head_fwd(const __bf16* act, int cs, int c0, const float* wh, const float* bh, size_t P,
+                    float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_head_fwd, dim3(blocks(P)), dim3(256), 0, st, act, cs, c0, wh, bh, P, out);
+    return hipGetLastError();
+}
+
+hipError_t head_bwd(const __bf16* act, int cs, int c0, const float* wh, const float* dout, size_t P,
+                    float* dact, int dcs, int dc0, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_head_bwd, dim3(blocks(P)), dim3(256), 0, st, act, cs, c0, wh, dout, P, dact,
+                       dcs, dc0, part);
+    return hipGetLastError();
+}
+
+unsigned head_blocks(size_t P) { return blocks(P); }
+
+hipError_t mse(const float* out, const float* y, size_t n, float* dout, double* part, double* res,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_mse, dim3(blocks(n)), dim3(256), 0, st, out, y, n, dout, part);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, st, part, (int)blocks(n), res);
+    return hipGetLastError();
+}
+
+unsigned mse_blocks(size_t n) { return blocks(n); }
+
+hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr, int t,
+                hipStream_t st) {
+    const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, st, w, g, m, v, n, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* wt, hipStream_t st) {
+    hipLaunchKernelGGL(k_weights_bf16, dim3(blocks((size_t)Cout * 9 * Cin)), dim3(256), 0, st, w,
+                       Cout, Cin, wf, wt);
+    return hipGetLastError();
+}
+
+hipError_t fill(float* p, size_t n, float v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks(n)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t pack(const float* phi, const float* P, const float* J, float lrr, const Norm& nm,
+                size_t HW, __bf16* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3(blocks(HW)), dim3(256), 0, st, phi, P, J, lrr, nm, HW, x);
+    return hipGetLastError();
+}
+
+hipError_t pack_target(const float* phi0, const float* P0, const float* J0, const float* phi1,
+                       const float* P1, const float* J1, const Norm& nm, size_t HW, float* y,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_target, dim3(blocks(HW)), dim3(256), 0, st, phi0, P0, J0, phi1, P1,
+                       J1, nm, HW, y);
+    return hipGetLastError();
+}
+
+hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi, float* P, float* J,
+                 hipStream_t st) {
+    hipLaunchKernelGGL(k_apply, dim3(blocks((size_t)B * HW)), dim3(256), 0, st, out, nm, B, HW, phi,
+                       P, J);
+    return hipGetLastError();
+}
+
+hipError_t maxdiff(const float* a, const float* b, size_t n, float* part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_maxdiff, dim3(nblk), dim3(256), 0, st, a, b, n, part);
+    return hipGetLastError();
+}
+
+hipError_t sum_field(const float* a, size_t n, double* part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_field, dim3(nblk), dim3(256), 0, st, a, n, part);
+    return hipGetLastError();
+}
+
+}  // namespace pfsur

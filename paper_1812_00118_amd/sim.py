@@ -111,6 +111,17 @@ class Sim:
         self._check(self.L.pflb_init_fields(self.ctx, _ptr(phi_t), _ptr(u_t), _ptr(P_t),
                                             _ptr(self._work), self._stream()))
 
+    def reconstruct(self, phi, J, P=None, advance=0):
+        """Replace the state by the equilibria of (phi, P, J); the step counter grows by
+        `advance`."""
+        phi_t = self._dev(phi, self.shape)
+        J_t = self._dev(J, (self.D,) + self.shape)
+        P_t = self._dev(P, self.shape) if P is not None else None
+        work = torch.empty((2 * self.Q + self.D) * self.N, device=self.device)
+        self._check(self.L.pflb_reconstruct(self.ctx, _ptr(phi_t), _ptr(P_t), _ptr(J_t),
+                                            _ptr(work), int(advance), self._stream()))
+        torch.cuda.current_stream(self.device).synchronize()
+
     def release_work(self):
         self._work = None
 

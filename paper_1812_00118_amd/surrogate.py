@@ -1,0 +1,207 @@
+"""Python handle of the convolutional surrogate in libpflb (include/pfsur.h).
+
+Argument marshalling only: the network's forward and backward passes, the loss, Adam,
+the packing of solver fields and the guarded hand-over run in the library's kernels;
+PyTorch provides device memory and the current stream.  Layouts are NHWC: the network
+input x is BF16 (batch, H, W, 8), outputs and targets are FP32 (batch, H, W, 4).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import PflbError, SurCfg, lib
+
+IN_CH, OUT_CH, STEPS = 8, 4, 16
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Surrogate:
+    """H, W: grid; norm: dict with in_shift[4], in_scale[4], out_scale[4], lrr_scale
+    (channels phi, P, J_x, J_y)."""
+
+    def __init__(self, H, W, max_batch, norm, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpflb needs a HIP GPU; none is visible")
+        self.L = lib()
+        self.device = torch.device(device or "cuda")
+        c = SurCfg()
+        c.H, c.W, c.max_batch = int(H), int(W), int(max_batch)
+        for k in range(4):
+            c.in_shift[k] = float(norm["in_shift"][k])
+            c.in_scale[k] = float(norm["in_scale"][k])
+            c.out_scale[k] = float(norm["out_scale"][k])
+        c.lrr_scale = float(norm["lrr_scale"])
+        self.cfg = c
+        self.H, self.W, self.max_batch = c.H, c.W, c.max_batch
+        self.norm = {k: (list(v) if not np.isscalar(v) else float(v)) for k, v in norm.items()}
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.L.pfsur_create(ctypes.byref(c), ctypes.byref(ctx))
+        if rc != 0:
+            raise PflbError(rc, "pfsur_create failed")
+        self.ctx = ctx
+        self.nparams = int(self.L.pfsur_num_params())
+        self._ws = {}
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PflbError(rc, self.L.pfsur_last_error(self.ctx).decode())
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                torch.cuda.synchronize(self.device)
+                self.L.pfsur_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def workspace(self, batch, training):
+        key = (int(batch), bool(training))
+        if key not in self._ws:
+            n = int(self.L.pfsur_workspace_bytes(ctypes.byref(self.cfg), key[0], int(key[1])))
+            if n == 0:
+                raise PflbError(-1, f"no workspace for batch {batch}")
+            self._ws[key] = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        t = self._ws[key]
+        off = (-t.data_ptr()) % 256
+        return ctypes.c_void_p(t.data_ptr() + off)
+
+    def release_workspaces(self):
+        self._ws = {}
+
+    # ------------------------------------------------------------------ parameters
+    def set_params(self, flat):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        if a.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {a.size}")
+        self._check(self.L.pfsur_set_params(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        a = np.empty(self.nparams, dtype=np.float32)
+        self._check(self.L.pfsur_get_params(self.ctx, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def save(self, path):
+        self._check(self.L.pfsur_save(self.ctx, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.L.pfsur_load(self.ctx, str(path).encode()))
+
+    # ------------------------------------------------------------------ data
+    def _f32(self, t, shape):
+        t = torch.as_tensor(t).to(device=self.device, dtype=torch.float32).contiguous()
+        return t.reshape(shape)
+
+    def pack(self, phi, P, J, lrr):
+        """phi, P (B, H, W); J (B, 2, H, W); lrr: B values of log10(rho_H/rho_L)."""
+        B = len(lrr)
+        phi = self._f32(phi, (B, self.H, self.W))
+        P = self._f32(P, (B, self.H, self.W))
+        J = self._f32(J, (B, 2, self.H, self.W))
+        x = torch.empty((B, self.H, self.W, IN_CH), dtype=torch.bfloat16, device=self.device)
+        arr = (ctypes.c_double * B)(*[float(v) for v in lrr])
+        self._check(self.L.pfsur_pack(self.ctx, _ptr(phi), _ptr(P), _ptr(J), arr, B, _ptr(x),
+                                      _stream(self.device)))
+        return x
+
+    def pack_target(self, f0, f1):
+        """f0, f1: (phi, P, J) of the same batch 16 steps apart -> y FP32 (B, H, W, 4)."""
+        B = f0[0].shape[0]
+        a = [self._f32(f0[0], (B, self.H, self.W)), self._f32(f0[1], (B, self.H, self.W)),
+             self._f32(f0[2], (B, 2, self.H, self.W)), self._f32(f1[0], (B, self.H, self.W)),
+             self._f32(f1[1], (B, self.H, self.W)), self._f32(f1[2], (B, 2, self.H, self.W))]
+        y = torch.empty((B, self.H, self.W, OUT_CH), dtype=torch.float32, device=self.device)
+        self._check(self.L.pfsur_pack_target(self.ctx, *[_ptr(t) for t in a], B, _ptr(y),
+                                             _stream(self.device)))
+        return y
+
+    def forward(self, x):
+        B = x.shape[0]
+        out = torch.empty((B, self.H, self.W, OUT_CH), dtype=torch.float32, device=self.device)
+        self._check(self.L.pfsur_forward(self.ctx, _ptr(x), _ptr(out), B,
+                                         self.workspace(B, False), _stream(self.device)))
+        return out
+
+    def apply(self, out, phi, P, J):
+        """In place: field += out * out_scale (phi, P, J: contiguous float32 device
+        tensors (B, H, W), (B, H, W), (B, 2, H, W))."""
+        B = out.shape[0]
+        for t in (phi, P, J):
+            assert t.is_contiguous() and t.dtype == torch.float32
+        self._check(self.L.pfsur_apply(self.ctx, _ptr(out), _ptr(phi), _ptr(P), _ptr(J), B,
+                                       _stream(self.device)))
+
+    def train_step(self, x, y, lr):
+        B = x.shape[0]
+        loss = ctypes.c_float()
+        self._check(self.L.pfsur_train_step(self.ctx, _ptr(x), _ptr(y), B, float(lr),
+                                            ctypes.byref(loss), self.workspace(B, True),
+                                            _stream(self.device)))
+        return float(loss.value)
+
+    def gradients(self, x, y):
+        B = x.shape[0]
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = ctypes.c_float()
+        self._check(self.L.pfsur_gradients(self.ctx, _ptr(x), _ptr(y), B,
+                                           g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+                                           self.workspace(B, True), _stream(self.device)))
+        return g, float(loss.value)
+
+    # ------------------------------------------------------------------ hand-over
+    def advance_guarded(self, sim, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0):
+        """Advance a D2Q9 periodic Sim by windows x 16 steps; returns the number of
+        windows that fell back to the plain steps."""
+        n = int(self.L.pfsur_guard_work_bytes(ctypes.byref(self.cfg)))
+        work = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        nf = ctypes.c_int()
+        self._check(self.L.pflb_advance_guarded(sim.ctx, self.ctx, int(windows), float(lrr),
+                                                float(mass_tol), float(phi_tol),
+                                                int(check_every), ctypes.byref(nf), wp,
+                                                _stream(self.device)))
+        return int(nf.value)
+
+
+# ---------------------------------------------------------------------- building blocks
+
+def conv_fwd(x, w, b=None, mode=0, act=True):
+    """One 3x3 layer: x BF16 NHWC, w BF16 (Cout, 3, 3, Cin), b FP32 (Cout,) or None.
+    Returns (y_pre FP32, y_act BF16) of shape (B, H, W, Cout)."""
+    L = lib()
+    B, Hin, Win, Cin = x.shape
+    H, W = {0: (Hin, Win), 1: (2 * Hin, 2 * Win), 2: (Hin // 2, Win // 2)}[mode]
+    Cout = w.shape[0]
+    y_pre = torch.empty((B, H, W, Cout), dtype=torch.float32, device=x.device)
+    y_act = torch.empty((B, H, W, Cout), dtype=torch.bfloat16, device=x.device)
+    rc = L.pfsur_conv_fwd(_ptr(x.contiguous()), B, H, W, Cin, Cout, mode, _ptr(w.contiguous()),
+                          _ptr(b), int(bool(act)), _ptr(y_pre), _ptr(y_act), _stream(x.device))
+    if rc != 0:
+        raise PflbError(rc, "pfsur_conv_fwd")
+    return y_pre, y_act
+
+
+def conv_wgrad(x, dy, mode=0):
+    """Weight and bias gradients of one 3x3 layer from its input x (BF16 NHWC) and the
+    gradient dy (BF16, (B, H, W, Cout)).  Returns (dw (Cout, 3, 3, Cin), db (Cout,))."""
+    L = lib()
+    B, H, W, Cout = dy.shape
+    Cin = x.shape[3]
+    n = int(L.pfsur_conv_wgrad_work_bytes(B, H, W, Cin, Cout))
+    work = torch.empty(max(n, 4) // 4 + 64, dtype=torch.float32, device=x.device)
+    dw = torch.empty((Cout, 3, 3, Cin), dtype=torch.float32, device=x.device)
+    db = torch.empty((Cout,), dtype=torch.float32, device=x.device)
+    rc = L.pfsur_conv_wgrad(_ptr(x.contiguous()), _ptr(dy.contiguous()), B, H, W, Cin, Cout, mode,
+                            _ptr(dw), _ptr(db), _ptr(work), _stream(x.device))
+    if rc != 0:
+        raise PflbError(rc, "pfsur_conv_wgrad")
+    return dw, db

@@ -19,6 +19,11 @@ Workloads (lattice units, rho_L = 1):
   droplet_impact   D3Q19 256x256x128, x,y periodic, z walls, rho_H=1000, R=32, film
                    depth 16, impact velocity 0.05, Re=UD/nu_H=500, We=rho_H U^2 D/sigma
                    =8000, mu_H/mu_L=100, W=4, M=0.1, g=0.
+  drops            D2Q9 256x256 periodic, the surrogate's training and test family:
+                   per seed 2-8 droplets, R ~ U[8, 32], rho_H ~ logU[10, 1000], centres
+                   uniform on the torus at least W apart (edge to edge), each drop moving
+                   with a random velocity |u| <= 0.02; nu_H = nu_L = 0.01, M = 0.1, W = 4,
+                   sigma = 1e-2.  Seeds: train 0-255, validation 1000-1031, test 2000-2031.
 """
 import math
 
@@ -75,6 +80,37 @@ def droplet_impact(nx=256, ny=256, nz=128, R=32.0, film=16.0, U=0.05):
                 bc=(PERIODIC, PERIODIC, WALL), rho_L=1.0, rho_H=rho_H, nu_L=10.0 * nu_H,
                 nu_H=nu_H, M=0.1, W=4.0, sigma=sigma, g=(0.0, 0.0, 0.0), eps=1e-10,
                 hoc=1, dtheta_C=0.0, R=R, film=film, U=U, steps=5000)
+
+
+def drops(seed, n=256):
+    """Parameters and droplet layout of one seed of the surrogate family (see above);
+    numpy's PCG64 generator seeded with `seed` draws every random number."""
+    rng = np.random.default_rng(int(seed))
+    rho_H = float(10.0 ** rng.uniform(1.0, 3.0))
+    W = 4.0
+    n_drop = int(rng.integers(2, 9))
+    placed = []
+    tries = 0
+    while len(placed) < n_drop and tries < 2000:
+        tries += 1
+        R = float(rng.uniform(8.0, 32.0))
+        c = rng.uniform(0.0, n, size=2)
+        ok = True
+        for (c2, R2, _) in placed:
+            d = np.abs(c - c2)
+            d = np.minimum(d, n - d)
+            if math.hypot(d[0], d[1]) < R + R2 + W:
+                ok = False
+                break
+        if ok:
+            ang = rng.uniform(0.0, 2.0 * math.pi)
+            speed = rng.uniform(0.0, 0.02)
+            placed.append((c, R, (speed * math.cos(ang), speed * math.sin(ang))))
+    return dict(name="drops", lattice=9, shape=(n, n, 1),
+                bc=(PERIODIC, PERIODIC, PERIODIC), rho_L=1.0, rho_H=rho_H, nu_L=0.01,
+                nu_H=0.01, M=0.1, W=W, sigma=1e-2, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1,
+                dtheta_C=0.0, seed=int(seed),
+                drops=[(float(c[0]), float(c[1]), R, v[0], v[1]) for c, R, v in placed])
 
 
 def model_params(cfg):
@@ -160,7 +196,27 @@ def fields_droplet_impact(cfg):
     return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
 
 
+def fields_drops(cfg):
+    """phi = the largest of the periodic drop profiles; u = each drop's velocity
+    weighted by its profile; P = 0."""
+    nx, ny, _ = cfg["shape"]
+    z, y, x = _grid(cfg["shape"])
+    phi = np.zeros((1, ny, nx))
+    u = np.zeros((3, 1, ny, nx))
+    for cx, cy, R, vx, vy in cfg["drops"]:
+        dx = np.abs(x - cx)
+        dx = np.minimum(dx, nx - dx)
+        dy = np.abs(y - cy)
+        dy = np.minimum(dy, ny - dy)
+        p = 0.5 - 0.5 * np.tanh(2.0 * (np.sqrt(dx * dx + dy * dy) - R) / cfg["W"])
+        phi = np.maximum(phi, p)
+        u[0] += p * vx
+        u[1] += p * vy
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
 FIELDS = {"static_droplet": fields_static_droplet,
+          "drops": fields_drops,
           "rayleigh_taylor": fields_rayleigh_taylor,
           "rising_bubble": fields_rising_bubble,
           "droplet_impact": fields_droplet_impact}

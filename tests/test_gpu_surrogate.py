@@ -1,0 +1,333 @@
+"""GPU parity of the surrogate's kernels against the FP64 reference network.
+
+Layer-level cases give the kernels BF16-representable operands, so that the GPU and
+the reference compute the same mathematical sums and differ only by FP32 accumulation,
+bounded by (K - 1) u sum|terms| with u = 2^-24 and K the number of terms.  Network-level
+cases round every activation to BF16 on the GPU only, so their bar is a relative error
+derived from BF16's unit roundoff (2^-9) accumulated over the layers."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def bf16(a):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a32 = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def grid_values(rng, shape, step=1.0 / 64, kmax=255):
+    """Random multiples of `step` with |k| <= kmax: BF16-exact, and sums of four of them
+    are exact in FP32 (so 2x2 averages round identically on both sides)."""
+    k = np.clip(np.round(rng.standard_normal(shape) * 48), -kmax, kmax)
+    return k * step
+
+
+def dev_bf16(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+@pytest.fixture(scope="module")
+def sur_mod():
+    from paper_1812_00118_amd import surrogate
+    return surrogate
+
+
+def _mode_input(x, mode):
+    if mode == 1:
+        return U.upsample2(x)
+    if mode == 2:
+        return bf16(U.avgpool2(x))
+    return x
+
+
+CASES = [(8, 32, 0), (32, 48, 0), (64, 32, 1), (32, 64, 2), (16, 32, 2), (128, 32, 0)]
+
+
+@pytest.mark.parametrize("cin,cout,mode", CASES)
+def test_conv_forward_matches_reference(sur_mod, cin, cout, mode):
+    rng = np.random.default_rng(cin * 7 + cout + mode)
+    B, H, W = 2, 24, 24                                   # 1152 pixels: 4.5 tiles of 256
+    Hin, Win = {0: (H, W), 1: (H // 2, W // 2), 2: (2 * H, 2 * W)}[mode]
+    x = grid_values(rng, (B, Hin, Win, cin))
+    w = bf16(rng.standard_normal((cout, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin)))
+    b = bf16(rng.standard_normal(cout) * 0.1)
+    y_pre, y_act = sur_mod.conv_fwd(dev_bf16(x), dev_bf16(w), torch.tensor(b, dtype=torch.float32).cuda(),
+                                    mode=mode, act=True)
+    torch.cuda.synchronize()
+    xin = _mode_input(x, mode)
+    ref = U.conv3x3(xin, w, b)
+    bound = (9 * cin) * U32 * (U.conv3x3(np.abs(xin), np.abs(w), np.abs(b))) + 1e-30
+    err = np.abs(y_pre.cpu().numpy() - ref)
+    assert np.all(err <= bound), (err.max(), (err / bound).max())
+    act = y_act.float().cpu().numpy()
+    sref = U.silu(ref)
+    assert np.all(np.abs(act - sref) <= 2.0 ** -8 * np.abs(sref) + 1e-6)
+
+
+@pytest.mark.parametrize("cin,cout,mode", CASES)
+def test_conv_weight_gradient_matches_reference(sur_mod, cin, cout, mode):
+    if cout % 8:
+        cout = 48
+    rng = np.random.default_rng(100 + cin + cout + mode)
+    B, H, W = 2, 24, 24
+    Hin, Win = {0: (H, W), 1: (H // 2, W // 2), 2: (2 * H, 2 * W)}[mode]
+    x = grid_values(rng, (B, Hin, Win, cin))
+    dy = bf16(rng.standard_normal((B, H, W, cout)))
+    dw, db = sur_mod.conv_wgrad(dev_bf16(x), dev_bf16(dy), mode=mode)
+    torch.cuda.synchronize()
+    xin = _mode_input(x, mode)
+    w0 = np.zeros((cout, 3, 3, cin))
+    _, ref_dw, ref_db = U.conv3x3_backward(xin, w0, dy)
+    _, abs_dw, abs_db = U.conv3x3_backward(np.abs(xin), w0, np.abs(dy))
+    P = B * H * W
+    err = np.abs(dw.cpu().numpy() - ref_dw)
+    assert np.all(err <= P * U32 * abs_dw + 1e-30), err.max()
+    assert np.all(np.abs(db.cpu().numpy() - ref_db) <= P * U32 * abs_db + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (64, 128), (256, 128)])
+def test_input_gradient_is_forward_with_mirrored_transposed_weights(sur_mod, cin, cout):
+    """dx of a layer = the forward kernel applied to dy with weights w_t[c, tap, o] =
+    w[o, 8 - tap, c] (the identity the backward pass uses)."""
+    rng = np.random.default_rng(cin + 3 * cout)
+    B, H, W = 2, 16, 24
+    w = bf16(rng.standard_normal((cout, 3, 3, cin)) * 0.05)
+    dy = grid_values(rng, (B, H, W, cout))
+    wt = w.reshape(cout, 9, cin)[:, ::-1, :].transpose(2, 1, 0).reshape(cin, 3, 3, cout)
+    dx, _ = sur_mod.conv_fwd(dev_bf16(dy), dev_bf16(np.ascontiguousarray(wt)), None, mode=0,
+                             act=False)
+    torch.cuda.synchronize()
+    x0 = np.zeros((B, H, W, cin))
+    ref_dx, _, _ = U.conv3x3_backward(x0, w, dy)
+    abs_dx, _, _ = U.conv3x3_backward(x0, np.abs(w), np.abs(dy))
+    err = np.abs(dx.cpu().numpy() - ref_dx)
+    assert np.all(err <= 9 * cout * U32 * abs_dx + 1e-30), err.max()
+
+
+# ---------------------------------------------------------------------------- network
+
+def flat_params(params):
+    """Flatten {name: (w, b)} in the library's order (3x3 layers, then the head)."""
+    parts = []
+    for name, *_ in U.LAYERS:
+        w, b = params[name]
+        parts += [w.reshape(-1), b.reshape(-1)]
+    wh, bh = params["head"]
+    parts += [wh.reshape(-1), bh.reshape(-1)]
+    return np.concatenate(parts)
+
+
+def unflat(flat, like):
+    out, o = {}, 0
+    for name in [n for n, *_ in U.LAYERS] + ["head"]:
+        w, b = like[name]
+        out[name] = (flat[o:o + w.size].reshape(w.shape), flat[o + w.size:o + w.size + b.size])
+        o += w.size + b.size
+    assert o == flat.size
+    return out
+
+
+NORM = dict(in_shift=[0.0] * 4, in_scale=[1.0] * 4, out_scale=[1.0] * 4, lrr_scale=1.0)
+
+
+@pytest.fixture(scope="module")
+def net_case(sur_mod):
+    rng = np.random.default_rng(7)
+    params = {k: (bf16(w), bf16(b)) for k, (w, b) in U.init_weights(11).items()}
+    B, H, W = 2, 32, 32
+    x = np.zeros((B, H, W, U.IN_CH))
+    x[..., :5] = bf16(rng.standard_normal((B, H, W, 5)))
+    y = rng.standard_normal((B, H, W, U.OUT_CH)) * 0.5
+    s = sur_mod.Surrogate(H, W, 4, NORM)
+    s.set_params(flat_params(params))
+    return s, params, x, y
+
+
+def test_parameters_round_trip(net_case):
+    s, params, _, _ = net_case
+    assert np.array_equal(s.get_params(), flat_params(params).astype(np.float32))
+
+
+def test_network_forward_matches_reference(net_case):
+    s, params, x, _ = net_case
+    out = s.forward(dev_bf16(x)).cpu().numpy()
+    ref, _ = U.forward(params, x)
+    rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    # 17 layers, each rounding its activations (and pooled inputs) to BF16 (u = 2^-9):
+    # a random walk of ~sqrt(17 * 2) relative errors of order u
+    assert rel <= 2e-2, rel
+    assert np.abs(out - ref).max() <= 0.1 * np.abs(ref).max()
+
+
+def test_network_gradients_match_reference(net_case):
+    s, params, x, y = net_case
+    g, loss = s.gradients(dev_bf16(x), torch.tensor(y, dtype=torch.float32).cuda())
+    out, cache = U.forward(params, x)
+    ref_loss, dout = U.mse(out, y)
+    ref = U.backward(params, cache, dout)
+    assert abs(loss - ref_loss) <= 2e-2 * ref_loss
+    gp = unflat(g.astype(np.float64), params)
+    worst = {}
+    for name in ref:
+        for k in (0, 1):
+            a, r = gp[name][k], ref[name][k]
+            worst[(name, k)] = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+    # forward and backward each round to BF16 once per layer: twice the forward bar
+    bad = {k: v for k, v in worst.items() if v > 5e-2}
+    assert not bad, bad
+
+
+def test_adam_step_matches_reference(net_case, sur_mod):
+    s, params, x, y = net_case
+    p0 = s.get_params().astype(np.float64)
+    xd, yd = dev_bf16(x), torch.tensor(y, dtype=torch.float32).cuda()
+    g, _ = s.gradients(xd, yd)
+    lr = 1e-3
+    s.train_step(xd, yd, lr)
+    p1 = s.get_params().astype(np.float64)
+    exp, _, _ = U.adam(p0, g.astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), 1, lr)
+    assert np.allclose(p1, exp, rtol=1e-6, atol=1e-9), np.abs(p1 - exp).max()
+    s.set_params(flat_params(params))                      # restore for other tests
+
+
+def test_training_overfits_one_batch(sur_mod):
+    rng = np.random.default_rng(3)
+    params = U.init_weights(5)
+    s = sur_mod.Surrogate(32, 32, 2, NORM)
+    s.set_params(flat_params(params))
+    x = dev_bf16(np.concatenate([bf16(rng.standard_normal((2, 32, 32, 5))),
+                                 np.zeros((2, 32, 32, 3))], axis=3))
+    y = torch.tensor(rng.standard_normal((2, 32, 32, 4)) * 0.3, dtype=torch.float32).cuda()
+    losses = [s.train_step(x, y, 2e-3) for _ in range(80)]
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
+
+
+def test_checkpoint_round_trip(sur_mod, tmp_path):
+    rng = np.random.default_rng(4)
+    s = sur_mod.Surrogate(16, 16, 1, NORM)
+    s.set_params(flat_params(U.init_weights(2)))
+    x = dev_bf16(np.concatenate([bf16(rng.standard_normal((1, 16, 16, 5))),
+                                 np.zeros((1, 16, 16, 3))], axis=3))
+    y = torch.zeros((1, 16, 16, 4), device="cuda")
+    s.train_step(x, y, 1e-3)
+    s.save(tmp_path / "s.ck")
+    a = [s.train_step(x, y, 1e-3) for _ in range(3)]
+    pa = s.get_params()
+    s2 = sur_mod.Surrogate(16, 16, 1, NORM)
+    s2.load(tmp_path / "s.ck")
+    b = [s2.train_step(x, y, 1e-3) for _ in range(3)]
+    assert a == b and np.array_equal(pa, s2.get_params())
+
+
+def test_pack_and_apply(sur_mod):
+    rng = np.random.default_rng(5)
+    norm = dict(in_shift=[0.5, 0.01, 0.0, 0.0], in_scale=[2.0, 30.0, 50.0, 50.0],
+                out_scale=[0.05, 0.01, 0.02, 0.02], lrr_scale=0.5)
+    s = sur_mod.Surrogate(16, 24, 3, norm)
+    B = 3
+    phi = rng.uniform(0, 1, (B, 16, 24)).astype(np.float32)
+    P = (rng.standard_normal((B, 16, 24)) * 0.01).astype(np.float32)
+    J = (rng.standard_normal((B, 2, 16, 24)) * 0.02).astype(np.float32)
+    lrr = [1.0, 2.5, 3.0]
+    x = s.pack(phi, P, J, lrr).float().cpu().numpy()
+    f32 = np.float32
+    for c, f in enumerate([phi, P, J[:, 0], J[:, 1]]):
+        v = (f - f32(norm["in_shift"][c])) * f32(norm["in_scale"][c])
+        assert np.array_equal(x[..., c], bf16(v).astype(np.float32)), c
+    for b in range(B):
+        assert np.all(x[b, ..., 4] == bf16(f32(lrr[b]) * f32(0.5)))
+    assert np.all(x[..., 5:] == 0)
+    out = torch.tensor(rng.standard_normal((B, 16, 24, 4)), dtype=torch.float32).cuda()
+    ph, Pd, Jd = (torch.tensor(a).cuda() for a in (phi, P, J))
+    s.apply(out, ph, Pd, Jd)
+    o = out.cpu().numpy().astype(np.float64)
+    exp = [phi + o[..., 0] * 0.05, P + o[..., 1] * 0.01, J[:, 0] + o[..., 2] * 0.02,
+           J[:, 1] + o[..., 3] * 0.02]
+    got = [ph.cpu().numpy(), Pd.cpu().numpy(), Jd[:, 0].cpu().numpy(), Jd[:, 1].cpu().numpy()]
+    for a, e in zip(got, exp):
+        assert np.allclose(a, e, rtol=2e-7, atol=1e-9)
+    # the target of a pair inverts apply: y = (f1 - f0) / out_scale
+    y = s.pack_target((phi, P, J), (got[0], got[1], np.stack(got[2:], axis=1)))
+    assert np.allclose(y.cpu().numpy(), o, rtol=1e-4, atol=1e-4)
+
+
+# ---------------------------------------------------------------------------- hand-over
+
+def _drops_sim(n=64, seed=3):
+    import pfinputs as I
+    from paper_1812_00118_amd import Sim
+    cfg = I.drops(seed, n=n)
+    sim = Sim(I.model_params(cfg))
+    phi, u, P = I.fields(cfg)
+    sim.init_fields(phi, u, P)
+    return sim, cfg
+
+
+def test_reconstruct_reads_back_the_fields():
+    a, cfg = _drops_sim()
+    a.step(40)
+    f = a.read(("phi", "P", "J"))
+    b, _ = _drops_sim()
+    b.reconstruct(f["phi"], f["J"], f["P"], advance=5)
+    g = b.read(("phi", "P", "J"))
+    assert b.steps == 5
+    assert (g["phi"] - f["phi"]).abs().max().item() <= 2e-6
+    assert (g["P"] - f["P"]).abs().max().item() <= 1e-5 * f["P"].abs().max().item() + 1e-9
+    assert (g["J"] - f["J"]).abs().max().item() <= 1e-4 * f["J"].abs().max().item()
+
+
+def _net(sur_mod, n, seed=1, out_scale=1e-3):
+    norm = dict(in_shift=[0.5, 0.0, 0.0, 0.0], in_scale=[2.0, 100.0, 100.0, 100.0],
+                out_scale=[out_scale] * 4, lrr_scale=0.5)
+    s = sur_mod.Surrogate(n, n, 1, norm)
+    s.set_params(flat_params(U.init_weights(seed, scale=0.1)))
+    return s
+
+
+def test_guard_forced_fallback_equals_plain_steps(sur_mod):
+    """mass_tol = 0 rejects every window: the result is exactly 3 x 16 plain steps."""
+    s = _net(sur_mod, 64)
+    a, cfg = _drops_sim()
+    b, _ = _drops_sim()
+    lrr = np.log10(cfg["rho_H"])
+    nf = s.advance_guarded(a, 3, lrr, mass_tol=0.0, phi_tol=1.0, check_every=0)
+    b.step(48)
+    assert nf == 3 and a.steps == 48
+    assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+    # a checked window with phi_tol = 0 also falls back to the plain steps it took
+    nf = s.advance_guarded(a, 2, lrr, mass_tol=1e30, phi_tol=0.0, check_every=1)
+    b.step(32)
+    assert nf == 2 and a.steps == 80
+    assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+
+
+def test_guard_accepts_and_hands_over_the_prediction(sur_mod):
+    s = _net(sur_mod, 64)
+    a, cfg = _drops_sim()
+    b, _ = _drops_sim()
+    lrr = float(np.log10(cfg["rho_H"]))
+    nf = s.advance_guarded(a, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0)
+    assert nf == 0 and a.steps == 16
+    f = b.read(("phi", "P", "J"))
+    phi, P, J = f["phi"].reshape(1, 64, 64), f["P"].reshape(1, 64, 64), f["J"].reshape(1, 2, 64, 64)
+    out = s.forward(s.pack(phi, P, J, [lrr]))
+    s.apply(out, phi, P, J)
+    b.reconstruct(phi, J, P, advance=16)
+    assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+    # with a check every window the accepted state is the same prediction
+    c, _ = _drops_sim()
+    nf = s.advance_guarded(c, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=1)
+    assert nf == 0 and c.steps == 16
+    assert torch.equal(a.read(("phi",))["phi"], c.read(("phi",))["phi"])

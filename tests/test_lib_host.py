@@ -1,5 +1,5 @@
 """Host-only checks of the C-ABI library: it loads, exports every function declared in
-include/pflb.h, and validates parameters without touching a GPU."""
+include/pflb.h and include/pfsur.h, and validates parameters without touching a GPU."""
 import ctypes
 import os
 import re
@@ -22,11 +22,79 @@ def L():
     return _lib.load_library()
 
 
-def test_exports_every_declared_symbol(L):
-    names = _declared("pflb.h")
-    assert "pflb_step" in names and "pflb_create" in names
+@pytest.mark.parametrize("header", ["pflb.h", "pfsur.h"])
+def test_exports_every_declared_symbol(L, header):
+    names = _declared(header)
+    assert len(names) >= 10
     for n in names:
         assert hasattr(L, n), n
+        assert n in _lib.exported_symbols(), n
+
+
+def test_surrogate_parameter_count_matches_reference_network(L):
+    from oracle import unet as U
+    n = sum(co * 9 * ci + co for _, _, ci, co, _, _ in U.LAYERS) + U.OUT_CH * 32 + U.OUT_CH
+    assert L.pfsur_num_params() == n
+
+
+def _sur_cfg(**kw):
+    c = _lib.SurCfg()
+    c.H, c.W, c.max_batch = 256, 256, 4
+    for k in range(4):
+        c.in_scale[k] = 1.0
+        c.out_scale[k] = 1.0
+    c.lrr_scale = 1.0
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_surrogate_workspace_planning(L):
+    c = _sur_cfg()
+    inf1 = L.pfsur_workspace_bytes(ctypes.byref(c), 1, 0)
+    tr1 = L.pfsur_workspace_bytes(ctypes.byref(c), 1, 1)
+    tr4 = L.pfsur_workspace_bytes(ctypes.byref(c), 4, 1)
+    # inference holds at least the level-0 activations (32 + 64 + 32 + 32 BF16 channels)
+    assert inf1 >= 256 * 256 * 160 * 2
+    assert tr1 > 2 * inf1 and tr4 > 3.5 * tr1
+    assert L.pfsur_workspace_bytes(ctypes.byref(c), 5, 1) == 0       # above max_batch
+    assert L.pfsur_workspace_bytes(ctypes.byref(c), 0, 0) == 0
+    for bad in (dict(H=20), dict(W=8), dict(max_batch=0), dict(max_batch=2000)):
+        assert L.pfsur_workspace_bytes(ctypes.byref(_sur_cfg(**bad)), 1, 0) == 0, bad
+    assert L.pfsur_guard_work_bytes(ctypes.byref(c)) > inf1
+
+
+def test_guard_accept_rule(L):
+    """The fallback decision is a pure host function of two sums, the relative mass
+    tolerance and an optional phi error: forced from the host with synthetic values."""
+    acc = L.pfsur_guard_accept
+    s = 4096.0
+    assert acc(s, s * (1 + 0.9e-3), 1e-3, 0, 0.0, 0.0) == 1
+    assert acc(s, s * (1 + 1e-2), 1e-3, 0, 0.0, 0.0) == 0           # injected +1e-2 sum(phi)
+    assert acc(s, s * (1 - 1e-2), 1e-3, 0, 0.0, 0.0) == 0
+    assert acc(s, float("nan"), 1e-3, 0, 0.0, 0.0) == 0
+    assert acc(s, float("inf"), 1e-3, 0, 0.0, 0.0) == 0
+    assert acc(s, s, 1e-3, 1, 0.02, 0.05) == 1
+    assert acc(s, s, 1e-3, 1, 0.06, 0.05) == 0                      # checked window, phi off
+    assert acc(s, s, 1e-3, 1, float("nan"), 0.05) == 0
+    assert acc(s, s, 1e-3, 0, float("nan"), 0.05) == 1              # unchecked: error unused
+    assert acc(s, s + 1e-9, 0.0, 0, 0.0, 0.0) == 0                  # zero tolerance
+
+
+def test_conv_primitives_reject_bad_shapes(L):
+    """Shape checks come before any device work: NULL pointers, channel counts that are
+    not multiples of 8, odd sizes for the upsampling mode and unknown modes."""
+    dummy = ctypes.c_void_p(4096)
+    f = L.pfsur_conv_fwd
+    assert f(None, 1, 16, 16, 8, 32, 0, dummy, None, 1, None, None, None) == -1
+    assert f(dummy, 1, 16, 16, 12, 32, 0, dummy, None, 1, None, None, None) == -1
+    assert f(dummy, 1, 15, 16, 8, 32, 1, dummy, None, 1, None, None, None) == -1
+    assert f(dummy, 1, 16, 16, 8, 32, 3, dummy, None, 1, None, None, None) == -1
+    assert f(dummy, 0, 16, 16, 8, 32, 0, dummy, None, 1, None, None, None) == -1
+    assert f(ctypes.c_void_p(4098), 1, 16, 16, 8, 32, 0, dummy, None, 1, None, None, None) == -2
+    g = L.pfsur_conv_wgrad
+    assert g(dummy, dummy, 1, 16, 16, 8, 12, 0, dummy, None, dummy, None) == -1   # Cout % 8
+    assert L.pfsur_conv_wgrad_work_bytes(1, 16, 16, 8, 32) >= 32 * 9 * 8 * 4
 
 
 def _params(**kw):
@@ -48,10 +116,11 @@ def _params(**kw):
                                  dict(M=0.0), dict(W=-1.0), dict(rho_L=0.0),
                                  dict(nx=0), dict(lattice=9), dict(sigma=float("nan")),
                                  dict(storage=3), dict(storage=1, scale=(30, 0)),
-                                 dict(hoc=2), dict(eps=0.0)])
+                                 dict(hoc=2), dict(eps=0.0),
+                                 dict(nx=1024, ny=1024, nz=256)])
 def test_create_rejects_bad_params(L, bad):
-    """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums and D2Q9 with nz != 1
-    return PFLB_ERR_PARAM and leave *out NULL."""
+    """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1
+    and domains beyond 2^28 - 64 sites return PFLB_ERR_PARAM and leave *out NULL."""
     p = _params(**bad)
     ctx = ctypes.c_void_p(1)
     rc = L.pflb_create(ctypes.byref(p), ctypes.byref(ctx))
