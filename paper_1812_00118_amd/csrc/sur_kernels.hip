@@ -524,7 +524,9 @@ unsigned mse_blocks(size_t n) { return blocks(n); }
 
 hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr, int t,
                 hipStream_t st) {
-    const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+    // bias corrections from the exact betas, so that at t = 1 they equal the FP32 (1 - beta)
+    // factors of the moment updates and m / c1 = g
+    const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
     hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, st, w, g, m, v, n, lr, c1, c2);
     return hipGetLastError();
 }

@@ -6,6 +6,7 @@ PyTorch provides device memory and the current stream.  Layouts are NHWC: the ne
 input x is BF16 (batch, H, W, 8), outputs and targets are FP32 (batch, H, W, 4).
 """
 import ctypes
+import math
 
 import numpy as np
 import torch
@@ -13,6 +14,26 @@ import torch
 from ._lib import PflbError, SurCfg, lib
 
 IN_CH, OUT_CH, STEPS = 8, 4, 16
+
+# (name, Cin, Cout) of the 3x3 layers in parameter order (include/pfsur.h), then the head
+LAYERS = [("e0a", 8, 32), ("e0b", 32, 32), ("e1a", 32, 64), ("e1b", 64, 64),
+          ("e2a", 64, 128), ("e2b", 128, 128), ("b3a", 128, 256), ("b3b", 256, 256),
+          ("u2", 256, 128), ("d2a", 256, 128), ("d2b", 128, 128), ("u1", 128, 64),
+          ("d1a", 128, 64), ("d1b", 64, 64), ("u0", 64, 32), ("d0a", 64, 32), ("d0b", 32, 32)]
+HEAD = (32, OUT_CH)
+
+
+def init_params(seed, head_scale=0.1):
+    """He-normal 3x3 weights, zero biases, a small head (the first predictions stay
+    near persistence); flat float32 array in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, cin, cout in LAYERS:
+        parts.append(rng.standard_normal(cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
+        parts.append(np.zeros(cout))
+    parts.append(rng.standard_normal(HEAD[0] * HEAD[1]) * head_scale / math.sqrt(HEAD[0]))
+    parts.append(np.zeros(HEAD[1]))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def _ptr(t):
