@@ -4,7 +4,10 @@ Workload: D3Q19 rising bubble, 128^3 sites, periodic in x and y, walls in z,
 rho_H/rho_L = 1000, mu_H/mu_L = 100, R = 16, W = 4, Eotvos number 10, hydrostatic
 start; distributions stored in FP32 (the value), with FP16-shifted storage timed beside
 it (speed-up and the phi difference between the two after the same steps).  The D3Q19
-droplet impact on a film (256x256x128, both storages) is timed as a second block.
+droplet impact on a film (256x256x128, both storages) is timed as a second block, and
+the learned 16-step surrogate (D2Q9 256^2 droplets) as a third: trained here on solver
+trajectories, then its held-out error, its forward/training rate against the BF16 MFMA
+peak, and its speed-up over 16 plain steps with the guard.
 
 A step is one fused stream-and-collide pass over both distribution sets (every site,
 every population); the sum(phi)/non-finite guard runs once at the end of the timed
@@ -53,6 +56,8 @@ def parse_args():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other storage mode and the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--sur-train-steps", type=int, default=300)
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -140,6 +145,102 @@ def cpu_baseline(seconds):
                       f"whole-domain FP64 steps in {el:.1f} s, numpy single thread"}
 
 
+def _events_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def surrogate_block(train_steps):
+    """Train the surrogate on solver trajectories (D2Q9 256^2 droplets), then measure
+    its held-out error and its speed against the plain solver."""
+    import math
+    import numpy as np
+    import torch
+    import pfinputs
+    from paper_1812_00118_amd import Sim, surrogate as S, sur_train as T
+
+    H = W = 256
+    t0 = time.time()
+    tr = T.Dataset(range(32), pfinputs.drops, t0=64, n_states=9)
+    te = T.Dataset(range(2000, 2004), pfinputs.drops, t0=64, n_states=9)
+    gen_s = time.time() - t0
+    norm = T.normalisation(tr)
+    sur = S.Surrogate(H, W, 32, norm)
+    sur.set_params(S.init_params(0))
+    t0 = time.time()
+    losses = T.train(sur, tr, train_steps, 8, 1e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    ev = T.evaluate(sur, te)
+    print(f"[bench] surrogate: trained {train_steps} steps in {train_s:.1f} s; test mse "
+          f"{ev['mse']:.4f} (persistence {ev['mse_persistence']:.4f}), phi err "
+          f"{ev['phi_err']:.4f} (persistence {ev['phi_err_persistence']:.4f})",
+          file=sys.stderr, flush=True)
+    flops = sum(2 * H * W // 4 ** lvl * cout * 9 * cin for (_, cin, cout), lvl in
+                zip(S.LAYERS, [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0]))
+    flops += 2 * H * W * S.HEAD[0] * S.HEAD[1]
+    fwd = {}
+    for B in (1, 32):
+        x = torch.zeros((B, H, W, S.IN_CH), dtype=torch.bfloat16, device="cuda")
+        fwd[B] = _events_ms(lambda: sur.forward(x), 10 if B == 1 else 4)
+    xb = torch.zeros((8, H, W, S.IN_CH), dtype=torch.bfloat16, device="cuda")
+    yb = torch.zeros((8, H, W, S.OUT_CH), device="cuda")
+    train_ms = _events_ms(lambda: sur.train_step(xb, yb, 0.0), 4)
+    # plain solver: 16 steps of one 256^2 domain
+    cfg = pfinputs.drops(2000)
+    sim = Sim(pfinputs.model_params(cfg))
+    sim.init_fields(*pfinputs.fields(cfg))
+    sim.release_work()
+    lb16 = _events_ms(lambda: sim.step(16), 20)
+    # guarded advance vs plain steps from the same state: 8 windows, every 4th checked
+    lrr = math.log10(cfg["rho_H"])
+    a = Sim(pfinputs.model_params(cfg))
+    a.init_fields(*pfinputs.fields(cfg))
+    a.step(64)
+    b = Sim(pfinputs.model_params(cfg))
+    b.init_fields(*pfinputs.fields(cfg))
+    b.step(64)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    nf = sur.advance_guarded(a, 8, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=4)
+    torch.cuda.synchronize()
+    guard_ms = (time.time() - t0) * 1e3
+    t0 = time.time()
+    b.step(128)
+    torch.cuda.synchronize()
+    plain_ms = (time.time() - t0) * 1e3
+    dphi = (a.read(("phi",))["phi"] - b.read(("phi",))["phi"]).abs().max().item()
+    ach = flops * 32 / (fwd[32] * 1e-3) / 1e12
+    return {
+        "workload": "drops D2Q9 256^2 periodic, 2-8 droplets, R U[8,32], rho_H logU[10,1000]",
+        "params": int(sur.nparams),
+        "gflop_per_sample_forward": round(flops / 1e9, 3),
+        "train": {"pairs": len(tr), "trajectories": 32, "steps": train_steps, "batch": 8,
+                  "seconds": round(train_s, 2), "data_seconds": round(gen_s, 2),
+                  "final_loss": round(float(np.mean(losses[-20:])), 5)},
+        "test": {k: round(v, 5) for k, v in ev.items()},
+        "forward_ms": {"batch1": round(fwd[1], 4), "batch32": round(fwd[32], 4)},
+        "train_step_ms_batch8": round(train_ms, 4),
+        "lb16_ms_per_domain": round(lb16, 4),
+        "speedup_vs_lb16": {"batch1": round(lb16 / fwd[1], 4),
+                            "batch32": round(32 * lb16 / fwd[32], 4)},
+        "roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(ach / 2500.0, 5),
+                     "kernel": "forward, batch 32 (17 conv + head)"},
+        "guarded": {"windows": 8, "check_every": 4, "fallbacks": nf,
+                    "wall_ms": round(guard_ms, 3), "plain_lb_ms": round(plain_ms, 3),
+                    "max_abs_dphi_vs_lb": dphi, "mass_tol": 1e-3, "phi_tol": 0.05},
+    }
+
+
 def main():
     args = parse_args()
     if args.copy_probe:
@@ -220,6 +321,8 @@ def main():
                 print(f"[bench] droplet_impact {st}: {r2['kernel_ms']:.4f} ms/step",
                       file=sys.stderr, flush=True)
             out["droplet_impact"] = blk
+        if not args.no_surrogate:
+            out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -15,6 +15,7 @@ namespace pfsur {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_grad(float z) {
@@ -111,6 +112,160 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvP a) {
                     a.out[(size_t)p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
                 if (a.fout) {
                     float* f = a.fout + (size_t)p * a.f_cs + a.f_c0 + co;
+                    *f = a.f_accum ? *f + v : v;
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM 3x3 convolution staged through LDS, for C and Cout multiples of 32.
+// A workgroup (4 waves) computes a 16x16 patch of output pixels of one image x NT
+// output channels.  The input channels are processed in chunks of 32: the chunk's
+// 18x18 halo patch (wrap, pooling or upsampling applied while loading) and its
+// NT x 9 x 32 weights are staged in LDS, and the loads of the next chunk are issued
+// into registers before the current chunk is computed.  Wave w owns patch rows
+// 4w..4w+3 as two 32-pixel MFMA row blocks; v_mfma_f32_32x32x16_bf16 (lane l: A row
+// l%32 = pixel, B column l%32 = channel, K elements 8(l/32)..+7; D column l%32, rows
+// 8(j/4) + 4(l/32) + j%4).  Row strides are padded (40 and 296 BF16) so that 16
+// consecutive lanes reading 16 bytes hit distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int TP = 16;                 // output patch edge
+constexpr int HP = TP + 2;             // halo patch edge
+constexpr int APAD = 40;               // BF16 per staged pixel (32 channels + pad)
+constexpr int BPAD = 9 * 32 + 8;       // BF16 per staged output channel
+constexpr int A_ITEMS = HP * HP * 4;   // 16-byte items of the halo patch
+constexpr int A_PER_T = (A_ITEMS + 255) / 256;
+
+template <int NT, int MODE>
+__global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
+    constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
+    constexpr int B_PER_T = (B_ITEMS + 255) / 256;
+    constexpr int NB = NT / 32;
+    __shared__ __bf16 sA[HP * HP * APAD];
+    __shared__ __bf16 sB[NT * BPAD];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
+    int blk = blockIdx.x;
+    const int tx = blk % tx_n;
+    blk /= tx_n;
+    const int ty = blk % ty_n;
+    const int b = blk / ty_n;
+    const int x0 = tx * TP, y0 = ty * TP;
+    const int co0 = blockIdx.y * NT;
+    const int C = a.g.C;
+    const int nchunk = C / 32;
+    const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
+
+    bf16x8 ra[A_PER_T], rb[B_PER_T];
+    auto load_a = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < A_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it < A_ITEMS) {
+                const int pi = it >> 2, grp = it & 3;
+                const int py = pi / HP, px = pi - py * HP;
+                ra[k] = gather8(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W),
+                                c0 + 8 * grp);
+            }
+        }
+    };
+    auto store_a = [&]() {
+#pragma unroll
+        for (int k = 0; k < A_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it < A_ITEMS)
+                *reinterpret_cast<bf16x8*>(&sA[(it >> 2) * APAD + 8 * (it & 3)]) = ra[k];
+        }
+    };
+    auto load_b = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < B_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            const int col = it / 36, rem = it - col * 36;
+            const int tap = rem >> 2, grp = rem & 3;
+            const int co = co0 + col;
+            rb[k] = (it < B_ITEMS && co < a.Cout)
+                        ? *reinterpret_cast<const bf16x8*>(a.w + ((size_t)co * 9 + tap) * C +
+                                                           c0 + 8 * grp)
+                        : zero8;
+        }
+    };
+    auto store_b = [&]() {
+#pragma unroll
+        for (int k = 0; k < B_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            const int col = it / 36, rem = it - col * 36;
+            if (it < B_ITEMS) *reinterpret_cast<bf16x8*>(&sB[col * BPAD + rem * 8]) = rb[k];
+        }
+    };
+
+    f32x16 acc[2][NB];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.0f;
+
+    // this lane's pixel in each row block: patch row 4w + 2mb + l32/16, column l32%16
+    const int prow = 4 * wave + (l32 >> 4), pcol = l32 & 15;
+
+    load_b(0);
+    if (MODE != MODE_POOL) load_a(0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        __syncthreads();                         // the previous chunk is consumed
+        if (MODE == MODE_POOL) load_a(ch * 32);  // pooled gathers average at once
+        store_a();
+        store_b();
+        __syncthreads();
+        if (ch + 1 < nchunk) {
+            load_b((ch + 1) * 32);
+            if (MODE != MODE_POOL) load_a((ch + 1) * 32);
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;   // halo coordinates: +1 offset folded in
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                bf16x8 A[2], Bm[NB];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    A[mb] = *reinterpret_cast<const bf16x8*>(
+                        &sA[((prow + 2 * mb + dy) * HP + pcol + dx) * APAD + 16 * h + 8 * g]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    Bm[nb] = *reinterpret_cast<const bf16x8*>(
+                        &sB[(nb * 32 + l32) * BPAD + tap * 32 + 16 * h + 8 * g]);
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[mb], Bm[nb],
+                                                                             acc[mb][nb], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds channel co0 + 32 nb + l32 of 16 pixels per row block
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = co0 + nb * 32 + l32;
+        if (co >= a.Cout) continue;
+        const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int idx = 8 * (j >> 2) + 4 * g + (j & 3);   // pixel in the row block
+                const int y = y0 + 4 * wave + 2 * mb + (idx >> 4), x = x0 + (idx & 15);
+                if (y >= a.H || x >= a.W) continue;
+                const size_t p = ((size_t)b * a.H + y) * a.W + x;
+                const float v = acc[mb][nb][j] + bias;
+                if (a.zout) a.zout[p * a.Cout + co] = (__bf16)v;
+                if (a.out) a.out[p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
+                if (a.fout) {
+                    float* f = a.fout + p * a.f_cs + a.f_c0 + co;
                     *f = a.f_accum ? *f + v : v;
                 }
             }
@@ -452,7 +607,25 @@ __global__ void __launch_bounds__(256) k_sum_field(const float* __restrict__ a, 
 // ---------------------------------------------------------------------------
 static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
+template <int NT>
+static void launch_tiled(const ConvP& a, hipStream_t st) {
+    const dim3 grid(a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP), (a.Cout + NT - 1) / NT);
+    if (a.g.mode == MODE_POOL)
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL>), grid, dim3(256), 0, st, a);
+    else if (a.g.mode == MODE_UP)
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME>), grid, dim3(256), 0, st, a);
+}
+
 hipError_t conv3x3(const ConvP& a, hipStream_t st) {
+    if (a.g.C % 32 == 0 && a.Cout % 32 == 0) {
+        if (a.Cout % 64 == 0)
+            launch_tiled<64>(a, st);
+        else
+            launch_tiled<32>(a, st);
+        return hipGetLastError();
+    }
     const int P = a.B * a.H * a.W;
     hipLaunchKernelGGL(k_conv3x3, dim3((P + 255) / 256, (a.Cout + 31) / 32), dim3(256), 0, st, a);
     return hipGetLastError();
