@@ -73,27 +73,18 @@ const ParamLayout PL;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// split of the pixel (K) dimension of a weight gradient: about 1024 workgroups
-int wgrad_split(int P, int Cout, int Cin, int* px_per_split) {
-    const int wgs = ((Cout + 31) / 32) * 9 * ((Cin + 31) / 32);
-    int nsplit = (1024 + wgs - 1) / wgs;
-    const int maxsplit = (P + 127) / 128;
-    if (nsplit > maxsplit) nsplit = maxsplit;
-    if (nsplit < 1) nsplit = 1;
-    int pps = (P + nsplit - 1) / nsplit;
-    pps = (pps + 127) / 128 * 128;
-    *px_per_split = pps;
-    return (P + pps - 1) / pps;
-}
+constexpr int COLSUM_PX = 1024;   // pixels per block of the primitive's bias sums
+constexpr int SILU_PX = 256;      // pixels per block of the fused SiLU backward
 
-constexpr int COLSUM_PX = 1024;
-
-size_t wgrad_part_floats(int P, int Cout, int Cin) {
-    int pps;
-    const int ns = wgrad_split(P, Cout, Cin, &pps);
+// floats of the partial-sum buffer for one layer's weight and bias gradients
+size_t wgrad_part_floats(int B, int H, int W, int Cout, int Cin) {
+    int per;
+    const int ns = wgrad_nsplit(B, H, W, Cout, Cin, &per);
+    const size_t P = (size_t)B * H * W;
     const size_t a = (size_t)ns * Cout * 9 * Cin;
-    const size_t b = (size_t)((P + COLSUM_PX - 1) / COLSUM_PX) * Cout;
-    return a > b ? a : b;
+    const size_t b = (P + SILU_PX - 1) / SILU_PX * Cout;
+    const size_t c = (P + COLSUM_PX - 1) / COLSUM_PX * Cout;
+    return std::max(a, std::max(b, c));
 }
 
 // byte offsets into the caller's workspace
@@ -125,7 +116,7 @@ Plan make_plan(int H, int W, int B, bool training) {
             const size_t P = pix(L.level);
             dz = std::max(dz, P * L.Cout);
             if (L.mode != MODE_SAME) dx = std::max(dx, P * L.Cin);
-            part = std::max(part, wgrad_part_floats((int)P, L.Cout, L.Cin));
+            part = std::max(part, wgrad_part_floats(B, H >> L.level, W >> L.level, L.Cout, L.Cin));
         }
         p.dz = take(dz * 2);
         p.dx = take(dx * 4);
@@ -257,9 +248,13 @@ int run_backward(pfsur_ctx* c, const void* x, const float* y, int B, char* ws, h
         const LayerDef& L = LAYERS[l];
         const int Hl = H >> L.level, Wl = W >> L.level;
         const int P = B * Hl * Wl;
+        // dz and the bias gradient's partial sums, then the weight gradient (both use part)
         SUR_TRY(silu_bwd(dact(L.out_buf), BUFS[L.out_buf].C, L.out_c0,
-                         reinterpret_cast<const __bf16*>(ws + p.z[l]), (size_t)P, L.Cout, dz, st),
+                         reinterpret_cast<const __bf16*>(ws + p.z[l]), P, L.Cout, SILU_PX, dz,
+                         part, st),
                 "silu backward");
+        SUR_TRY(reduce_splits(part, (P + SILU_PX - 1) / SILU_PX, L.Cout, c->grad + PL.b[l], 0, st),
+                "bias reduce");
         WgradP wg;
         wg.g = gather_of(L, ws, p, x, H, W);
         wg.B = B;
@@ -267,15 +262,12 @@ int run_backward(pfsur_ctx* c, const void* x, const float* y, int B, char* ws, h
         wg.W = Wl;
         wg.dz = dz;
         wg.Cout = L.Cout;
-        const int ns = wgrad_split(P, L.Cout, L.Cin, &wg.px_per_split);
+        int per;
+        const int ns = wgrad_nsplit(B, Hl, Wl, L.Cout, L.Cin, &per);
         wg.part = part;
         SUR_TRY(wgrad(wg, st), "wgrad");
         SUR_TRY(reduce_splits(part, ns, (size_t)L.Cout * 9 * L.Cin, c->grad + PL.w[l], 0, st),
                 "wgrad reduce");
-        SUR_TRY(colsum(dz, P, L.Cout, COLSUM_PX, part, st), "bias grad");
-        SUR_TRY(reduce_splits(part, (P + COLSUM_PX - 1) / COLSUM_PX, L.Cout, c->grad + PL.b[l], 0,
-                              st),
-                "bias reduce");
         if (l == 0) continue;
         ConvP d;
         memset(&d, 0, sizeof(d));
@@ -745,7 +737,7 @@ int pfsur_conv_fwd(const void* x, int batch, int H, int W, int Cin, int Cout, in
 
 size_t pfsur_conv_wgrad_work_bytes(int batch, int H, int W, int Cin, int Cout) {
     if (!conv_shape_ok(batch, H, W, Cin, Cout, MODE_SAME)) return 0;
-    return wgrad_part_floats(batch * H * W, Cout, Cin) * 4;
+    return wgrad_part_floats(batch, H, W, Cout, Cin) * 4;
 }
 
 int pfsur_conv_wgrad(const void* x, const void* dy, int batch, int H, int W, int Cin, int Cout,
@@ -762,7 +754,8 @@ int pfsur_conv_wgrad(const void* x, const void* dy, int batch, int H, int W, int
     a.W = W;
     a.dz = static_cast<const __bf16*>(dy);
     a.Cout = Cout;
-    const int ns = wgrad_split(P, Cout, Cin, &a.px_per_split);
+    int per;
+    const int ns = wgrad_nsplit(batch, H, W, Cout, Cin, &per);
     a.part = static_cast<float*>(work);
     if (wgrad(a, st) != hipSuccess) return PFLB_ERR_DEVICE;
     if (reduce_splits(a.part, ns, (size_t)Cout * 9 * Cin, dw, 0, st) != hipSuccess)

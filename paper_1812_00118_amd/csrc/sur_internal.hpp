@@ -36,12 +36,12 @@ struct ConvP {
 };
 
 // part[split][Cout][9][C] = sum over the split's pixels of dz[p, co] in[p + off(tap), ci]
+// (splits: wgrad_nsplit)
 struct WgradP {
     GatherP g;
     int B, H, W;
     const __bf16* dz;
     int Cout;
-    int px_per_split;
     float* part;
 };
 
@@ -51,11 +51,12 @@ struct Norm {
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st);
 hipError_t wgrad(const WgradP& a, hipStream_t st);
+int wgrad_nsplit(int B, int H, int W, int Cout, int Cin, int* per_split);
 hipError_t reduce_splits(const float* part, int nsplit, size_t n, float* out, int acc,
                          hipStream_t st);
 hipError_t colsum(const __bf16* m, int P, int C, int px_per_block, float* part, hipStream_t st);
-hipError_t silu_bwd(const float* dact, int cs, int c0, const __bf16* z, size_t P, int C,
-                    __bf16* dz, hipStream_t st);
+hipError_t silu_bwd(const float* dact, int cs, int c0, const __bf16* z, int P, int C, int ppb,
+                    __bf16* dz, float* part, hipStream_t st);
 hipError_t unpool_add(const float* dlo, int B, int Hl, int Wl, int C, float* ghi, int cs, int c0,
                       hipStream_t st);
 hipError_t sumpool(const float* dhi, int B, int Hl, int Wl, int C, float* glo, int cs, int c0,

@@ -137,6 +137,35 @@ constexpr int BPAD = 9 * 32 + 8;       // BF16 per staged output channel
 constexpr int A_ITEMS = HP * HP * 4;   // 16-byte items of the halo patch
 constexpr int A_PER_T = (A_ITEMS + 255) / 256;
 
+// Epilogue of a 16x16-pixel tile: the lane holds channel co0 + 32 nb + l32 of 16 pixels
+// per 32-pixel row block (D rows 8(j/4) + 4g + j%4).
+template <int NB>
+__device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc)[2][NB], int b,
+                                              int y0, int x0, int co0, int wave, int l32, int g) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int co = co0 + nb * 32 + l32;
+        if (co >= a.Cout) continue;
+        const float bias = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int idx = 8 * (j >> 2) + 4 * g + (j & 3);   // pixel in the row block
+                const int y = y0 + 4 * wave + 2 * mb + (idx >> 4), x = x0 + (idx & 15);
+                if (y >= a.H || x >= a.W) continue;
+                const size_t p = ((size_t)b * a.H + y) * a.W + x;
+                const float v = acc[mb][nb][j] + bias;
+                if (a.zout) a.zout[p * a.Cout + co] = (__bf16)v;
+                if (a.out) a.out[p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
+                if (a.fout) {
+                    float* f = a.fout + p * a.f_cs + a.f_c0 + co;
+                    *f = a.f_accum ? *f + v : v;
+                }
+            }
+    }
+}
+
 template <int NT, int MODE>
 __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
@@ -247,115 +276,213 @@ __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
             }
         }
     }
-    // epilogue: lane holds channel co0 + 32 nb + l32 of 16 pixels per row block
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int co = co0 + nb * 32 + l32;
-        if (co >= a.Cout) continue;
-        const float bias = a.bias ? a.bias[co] : 0.0f;
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int idx = 8 * (j >> 2) + 4 * g + (j & 3);   // pixel in the row block
-                const int y = y0 + 4 * wave + 2 * mb + (idx >> 4), x = x0 + (idx & 15);
-                if (y >= a.H || x >= a.W) continue;
-                const size_t p = ((size_t)b * a.H + y) * a.W + x;
-                const float v = acc[mb][nb][j] + bias;
-                if (a.zout) a.zout[p * a.Cout + co] = (__bf16)v;
-                if (a.out) a.out[p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
-                if (a.fout) {
-                    float* f = a.fout + p * a.f_cs + a.f_c0 + co;
-                    *f = a.f_accum ? *f + v : v;
-                }
-            }
-    }
+    tile_epilogue<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient dW[o, tap, c] = sum_p dz[p, o] in[p + off(tap), c] over a pixel
-// range per workgroup (split K).  A workgroup covers 32 output channels x one tap x
-// 32 input channels; each wave takes every 4th step of 32 pixels, transposes its dz and
-// input tiles through its own LDS region so that the MFMA operands (8 consecutive
-// pixels of one channel) are contiguous, and the 4 wave results are summed in a fixed
-// order before the partial is written.
+// First layer (8 input channels, same resolution): the whole K = 9 taps x 8 channels
+// fits one stage.  K is ordered (tap, channel) and padded to 10 taps, so each 16-wide
+// MFMA K step covers taps 2k (lanes 0-31) and 2k+1 (lanes 32-63).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_wgrad(WgradP a) {
-    __shared__ __bf16 sA[4][32][40];   // [wave][out channel][pixel] (+8 pad)
-    __shared__ __bf16 sB[4][32][40];   // [wave][in channel][pixel]
-    __shared__ float sred[4][32][33];
+constexpr int BPAD1 = 88;   // 10 taps x 8 channels + pad: conflict-free 16-byte reads
+
+__global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
+    __shared__ __bf16 sA[HP * HP * 8];
+    __shared__ __bf16 sB[32 * BPAD1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = lane >> 4, r16 = lane & 15;
-    const int co0 = blockIdx.x * 32;
-    const int cblocks = (a.g.C + 31) / 32;
-    const int tap = blockIdx.y / cblocks;
-    const int ci0 = (blockIdx.y % cblocks) * 32;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int P = a.B * a.H * a.W;
-    const int pbeg = blockIdx.z * a.px_per_split;
-    const int pend = min(P, pbeg + a.px_per_split);
-    f32x4 acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const int nsteps = (pend - pbeg + 31) / 32;
-    const int my_steps = (nsteps + 3) / 4;            // uniform trip count for the barriers
-    for (int t = 0; t < my_steps; ++t) {
-        const int step = t * 4 + wave;
-        const int ps = pbeg + step * 32;
-        // each lane loads two (pixel, channel group) pairs of each tile
-        for (int rep = 0; rep < 2; ++rep) {
-            const int idx = rep * 64 + lane;          // 0..127: pixel = idx / 4, group = idx % 4
-            const int pl = idx >> 2, grp = idx & 3;
-            const int p = ps + pl;
-            const bool ok = step < nsteps && p < pend;
-            bf16x8 va = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0}, vb = va;
-            if (ok) {
-                const int co = co0 + grp * 8;
-                if (co < a.Cout) va = *reinterpret_cast<const bf16x8*>(a.dz + (size_t)p * a.Cout + co);
-                const int ci = ci0 + grp * 8;
-                if (ci < a.g.C) {
-                    const int x = p % a.W, y = (p / a.W) % a.H, b = p / (a.W * a.H);
-                    vb = gather8(a.g, b, wrap(y + dy, a.H), wrap(x + dx, a.W), ci);
+    const int l32 = lane & 31, g = lane >> 5;
+    const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
+    int blk = blockIdx.x;
+    const int tx = blk % tx_n;
+    blk /= tx_n;
+    const int ty = blk % ty_n;
+    const int b = blk / ty_n;
+    const int x0 = tx * TP, y0 = ty * TP;
+    const int co0 = blockIdx.y * 32;
+    const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
+    for (int it = threadIdx.x; it < HP * HP; it += 256) {
+        const int py = it / HP, px = it - py * HP;
+        *reinterpret_cast<bf16x8*>(&sA[it * 8]) =
+            gather8(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W), 0);
+    }
+    for (int it = threadIdx.x; it < 32 * 10; it += 256) {
+        const int col = it / 10, tap = it - col * 10;
+        const int co = co0 + col;
+        *reinterpret_cast<bf16x8*>(&sB[col * BPAD1 + tap * 8]) =
+            (tap < 9 && co < a.Cout)
+                ? *reinterpret_cast<const bf16x8*>(a.w + ((size_t)co * 9 + tap) * 8)
+                : zero8;
+    }
+    __syncthreads();
+    f32x16 acc[2][1];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[mb][0][j] = 0.0f;
+    const int prow = 4 * wave + (l32 >> 4), pcol = l32 & 15;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int tap = 2 * k + g;
+        const int dy = tap / 3, dx = tap % 3;
+        const bf16x8 Bm = *reinterpret_cast<const bf16x8*>(&sB[l32 * BPAD1 + tap * 8]);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const bf16x8 A =
+                tap < 9 ? *reinterpret_cast<const bf16x8*>(
+                              &sA[((prow + 2 * mb + dy) * HP + pcol + dx) * 8])
+                        : zero8;
+            acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bm, acc[mb][0], 0, 0, 0);
+        }
+    }
+    tile_epilogue<1>(a, acc, b, y0, x0, co0, wave, l32, g);
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient staged through LDS: dW[o, tap, c] = sum_p dz[p, o] in[p + off(tap), c].
+// A workgroup owns 32 output x 32 input channels and all 9 taps, and a contiguous range
+// of 16x16 pixel patches (split K).  Per patch, dz is staged transposed ([o][pixel]) and
+// the input halo as three copies shifted by dx ([dx][c][halo row][16 pixels]), so every
+// MFMA operand (8 consecutive pixels of one channel) is an aligned 16-byte LDS read.
+// Wave w reduces over patch rows 4w..4w+3 for all taps; the 4 wave sums are added in a
+// fixed order and the workgroup's partial sums go to part[split].
+// ---------------------------------------------------------------------------
+constexpr int DZ_STRIDE = 264;                 // 256 pixels + pad per output channel
+constexpr int XC_STRIDE = HP * 16 + 8;         // 18 halo rows x 16 pixels + pad per channel
+constexpr int X_COPY = 32 * XC_STRIDE;         // one dx-shifted copy
+
+template <int MODE>
+__global__ void __launch_bounds__(256, 2) k_wgrad_tiled(WgradP a, int patches_per_split,
+                                                        int npatch) {
+    __shared__ __bf16 sD[32 * DZ_STRIDE];
+    __shared__ __bf16 sX[3 * X_COPY];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int o0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+    const int C = a.g.C;
+    const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
+    const int pbeg = blockIdx.z * patches_per_split;
+    const int pend = min(npatch, pbeg + patches_per_split);
+    const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
+
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[t][j] = 0.0f;
+
+    bf16x8 rd[4], rx[A_PER_T];
+    auto load = [&](int patch) {
+        int q = patch;
+        const int tx = q % tx_n;
+        q /= tx_n;
+        const int ty = q % ty_n;
+        const int b = q / ty_n;
+        const int x0 = tx * TP, y0 = ty * TP;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int it = threadIdx.x + 256 * k;     // 256 pixels x 4 groups of 8 channels
+            const int pi = it >> 2, og = it & 3;
+            const int y = y0 + (pi >> 4), x = x0 + (pi & 15), o = o0 + 8 * og;
+            rd[k] = (y < a.H && x < a.W && o < a.Cout)
+                        ? *reinterpret_cast<const bf16x8*>(
+                              a.dz + (((size_t)b * a.H + y) * a.W + x) * a.Cout + o)
+                        : zero8;
+        }
+#pragma unroll
+        for (int k = 0; k < A_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;     // 18x18 halo pixels x 4 groups
+            if (it < A_ITEMS) {
+                const int pi = it >> 2, cg = it & 3;
+                const int hy = pi / HP, hx = pi - hy * HP;
+                const int c = c0 + 8 * cg;
+                rx[k] = c < C ? gather8(a.g, b, wrap(y0 - 1 + hy, a.H), wrap(x0 - 1 + hx, a.W), c)
+                              : zero8;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            const int pi = it >> 2, og = it & 3;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sD[(8 * og + e) * DZ_STRIDE + pi] = rd[k][e];
+        }
+#pragma unroll
+        for (int k = 0; k < A_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it < A_ITEMS) {
+                const int pi = it >> 2, cg = it & 3;
+                const int hy = pi / HP, hx = pi - hy * HP;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int px = hx - dx;
+                    if (px >= 0 && px < TP)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            sX[dx * X_COPY + (8 * cg + e) * XC_STRIDE + hy * 16 + px] = rx[k][e];
                 }
             }
-            for (int k = 0; k < 8; ++k) {
-                sA[wave][grp * 8 + k][pl] = va[k];
-                sB[wave][grp * 8 + k][pl] = vb[k];
+        }
+    };
+
+    if (pbeg < pend) load(pbeg);
+    for (int patch = pbeg; patch < pend; ++patch) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (patch + 1 < pend) load(patch + 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int py = 4 * wave + r;
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(&sD[l32 * DZ_STRIDE + py * 16 + 8 * g]);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                const bf16x8 Bv = *reinterpret_cast<const bf16x8*>(
+                    &sX[dx * X_COPY + l32 * XC_STRIDE + (py + dy) * 16 + 8 * g]);
+                acc[tap] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc[tap], 0, 0, 0);
             }
         }
-        __syncthreads();
-        bf16x8 A[2], Bm[2];
-        for (int i = 0; i < 2; ++i) {
-            A[i] = *reinterpret_cast<const bf16x8*>(&sA[wave][i * 16 + r16][8 * q]);
-            Bm[i] = *reinterpret_cast<const bf16x8*>(&sB[wave][i * 16 + r16][8 * q]);
-        }
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], Bm[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
     }
-    // C: rows = out channels 16 i + 4 q + e, columns = in channels 16 j + r16
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            for (int e = 0; e < 4; ++e) sred[wave][16 * i + 4 * q + e][16 * j + r16] = acc[i][j][e];
-    __syncthreads();
-    for (int k = threadIdx.x; k < 32 * 32; k += 256) {
-        const int o = k >> 5, c = k & 31;
-        const float v = sred[0][o][c] + sred[1][o][c] + sred[2][o][c] + sred[3][o][c];
-        const int co = co0 + o, ci = ci0 + c;
-        if (co < a.Cout && ci < a.g.C)
-            a.part[(size_t)blockIdx.z * a.Cout * 9 * a.g.C + ((size_t)co * 9 + tap) * a.g.C + ci] = v;
+    // fixed-order sum of the 4 waves, one tap at a time, through the (now free) sX region
+    float* red = reinterpret_cast<float*>(sX);       // [4 waves][32 o][33]
+    for (int tap = 0; tap < 9; ++tap) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int o = 8 * (j >> 2) + 4 * g + (j & 3);
+            red[(wave * 32 + o) * 33 + l32] = acc[tap][j];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < 1024; k += 256) {
+            const int o = k >> 5, c = k & 31;
+            const float v = ((red[o * 33 + c] + red[(32 + o) * 33 + c]) + red[(64 + o) * 33 + c]) +
+                            red[(96 + o) * 33 + c];
+            if (o0 + o < a.Cout && c0 + c < C)
+                a.part[(size_t)blockIdx.z * a.Cout * 9 * C + ((size_t)(o0 + o) * 9 + tap) * C + c0 + c] = v;
+        }
     }
 }
 
-// out[i] = sum_s part[s][i] (fixed order) (+ out[i] if accumulate)
-__global__ void k_reduce_splits(const float* __restrict__ part, int nsplit, size_t n,
-                                float* __restrict__ out, int accumulate) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
-    out[i] = accumulate ? out[i] + s : s;
+// out[i] = sum_s part[s][i] (+ out[i] if accumulate).  A block takes 32 consecutive i;
+// its 8 rows of lanes take every 8th split, then the 8 row sums are added in order.
+__global__ void __launch_bounds__(256) k_reduce_splits(const float* __restrict__ part, int nsplit,
+                                                       size_t n, float* __restrict__ out,
+                                                       int accumulate) {
+    __shared__ float sred[8][33];
+    const int ci = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const size_t i = (size_t)blockIdx.x * 32 + ci;
+    float acc = 0.f;
+    if (i < n)
+        for (int k = sl; k < nsplit; k += 8) acc += part[(size_t)k * n + i];
+    sred[sl][ci] = acc;
+    __syncthreads();
+    if (sl == 0 && i < n) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += sred[k][ci];
+        out[i] = accumulate ? out[i] + t : t;
+    }
 }
 
 // column sums of a [P][C] BF16 matrix over a pixel range per block: part[blk][C]
@@ -377,14 +504,31 @@ __global__ void __launch_bounds__(256) k_colsum(const __bf16* __restrict__ m, in
     }
 }
 
-// dz[p, c] = d_act[p, c0 + c] * silu'(z[p, c])
-__global__ void k_silu_bwd(const float* __restrict__ dact, int cs, int c0, const __bf16* __restrict__ z,
-                           size_t P, int C, __bf16* __restrict__ dz) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= P * C) return;
-    const size_t p = i / C;
-    const int c = (int)(i - p * C);
-    dz[i] = (__bf16)(dact[p * cs + c0 + c] * silu_grad((float)z[i]));
+// dz[p, c] = d_act[p, c0 + c] * silu'(z[p, c]) (BF16), and per block of ppb pixels the
+// column sums of dz: part[block][c] (the bias gradient's partial sums)
+__global__ void __launch_bounds__(256) k_silu_bwd(const float* __restrict__ dact, int cs, int c0,
+                                                  const __bf16* __restrict__ z, int P, int C,
+                                                  int ppb, __bf16* __restrict__ dz,
+                                                  float* __restrict__ part) {
+    __shared__ float sred[8][33];
+    const int cl = threadIdx.x & 31, r = threadIdx.x >> 5;
+    const int c = blockIdx.y * 32 + cl;
+    const int pb = blockIdx.x * ppb, pe = min(P, pb + ppb);
+    float acc = 0.f;
+    if (c < C)
+        for (int p = pb + r; p < pe; p += 8) {
+            const size_t i = (size_t)p * C + c;
+            const __bf16 d = (__bf16)(dact[(size_t)p * cs + c0 + c] * silu_grad((float)z[i]));
+            dz[i] = d;
+            acc += (float)d;
+        }
+    sred[r][cl] = acc;
+    __syncthreads();
+    if (r == 0 && c < C) {
+        float t = 0.f;
+        for (int k = 0; k < 8; ++k) t += sred[k][cl];
+        part[(size_t)blockIdx.x * C + c] = t;
+    }
 }
 
 // grad_hi[b, 2y+i, 2x+j, c0 + c] += dx_lo[b, y, x, c] / 4   (average pooling adjoint)
@@ -435,37 +579,57 @@ __global__ void k_head_fwd(const __bf16* __restrict__ act, int cs, int c0, const
     for (int k = 0; k < 4; ++k) out[p * 4 + k] = o[k];
 }
 
-// head backward: dact[p, c] = sum_o dout[p, o] wh[o, c]; per-block partial sums
-// part[blk][o * 32 + c] of dwh[o, c] = sum_p dout[p, o] act[p, c] and part[blk][128 + o] of
-// dbh[o] = sum_p dout[p, o]
+// head backward: dact[p, c] = sum_o dout[p, o] wh[o, c]; per block of HEAD_PPB pixels the
+// partial sums part[blk][o * 32 + c] of dwh[o, c] = sum_p dout[p, o] act[p, c] and
+// part[blk][128 + o] of dbh[o] = sum_p dout[p, o].  Each thread accumulates its pixels in
+// registers; waves reduce by butterfly shuffles, then the 4 wave sums are added in order.
+constexpr int HEAD_PPB = 2048;
 __global__ void __launch_bounds__(256) k_head_bwd(const __bf16* __restrict__ act, int cs, int c0,
                                                   const float* __restrict__ wh,
                                                   const float* __restrict__ dout, size_t P,
                                                   float* __restrict__ dact, int dcs, int dc0,
                                                   float* __restrict__ part) {
-    __shared__ float s[4][256];
-    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-    float d[4] = {0, 0, 0, 0};
-    if (p < P)
-        for (int k = 0; k < 4; ++k) d[k] = dout[p * 4 + k];
-    float* blk = part + (size_t)blockIdx.x * 132;
-    for (int c = 0; c < 33; ++c) {
-        const float v = (c < 32) ? (p < P ? (float)act[p * cs + c0 + c] : 0.f) : 1.0f;
-        if (c < 32 && p < P) {
-            float g = 0.f;
-            for (int k = 0; k < 4; ++k) g += d[k] * wh[k * 32 + c];
-            dact[p * dcs + dc0 + c] = g;
+    __shared__ float sred[4][132];
+    float acc[132];
+#pragma unroll
+    for (int k = 0; k < 132; ++k) acc[k] = 0.f;
+    const size_t pb = (size_t)blockIdx.x * HEAD_PPB;
+    const size_t pe = pb + HEAD_PPB < P ? pb + HEAD_PPB : P;
+    for (size_t p = pb + threadIdx.x; p < pe; p += 256) {
+        const float4 d4 = reinterpret_cast<const float4*>(dout)[p];
+        const float d[4] = {d4.x, d4.y, d4.z, d4.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8*>(act + p * cs + c0 + 8 * q);
+            float g[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int c = 8 * q + e;
+                const float av = (float)v[e];
+                g[e] = d[0] * wh[c] + d[1] * wh[32 + c] + d[2] * wh[64 + c] + d[3] * wh[96 + c];
+#pragma unroll
+                for (int o = 0; o < 4; ++o) acc[o * 32 + c] += d[o] * av;
+            }
+            float4* dst = reinterpret_cast<float4*>(dact + p * dcs + dc0 + 8 * q);
+            dst[0] = make_float4(g[0], g[1], g[2], g[3]);
+            dst[1] = make_float4(g[4], g[5], g[6], g[7]);
         }
-        for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = d[k] * v;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < (unsigned)w)
-                for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x < 4) blk[c < 32 ? threadIdx.x * 32 + c : 128 + threadIdx.x] = s[threadIdx.x][0];
-        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[128 + o] += d[o];
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 132; ++k) {
+        float v = acc[k];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) sred[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 132)
+        part[(size_t)blockIdx.x * 132 + threadIdx.x] =
+            ((sred[0][threadIdx.x] + sred[1][threadIdx.x]) + sred[2][threadIdx.x]) +
+            sred[3][threadIdx.x];
 }
 
 // MSE: per-block partial sums of (out - y)^2 and dout = 2 (out - y) / n
@@ -489,12 +653,18 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ out, cons
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-__global__ void k_sum_f64(const double* __restrict__ part, int n, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        out[0] = s;
+__global__ void __launch_bounds__(256) k_sum_f64(const double* __restrict__ part, int n,
+                                                 double* __restrict__ out) {
+    __shared__ double sred[256];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+    sred[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) sred[threadIdx.x] += sred[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[0] = sred[0];
 }
 
 // Adam (Kingma & Ba) on FP32 masters
@@ -619,6 +789,11 @@ static void launch_tiled(const ConvP& a, hipStream_t st) {
 }
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st) {
+    if (a.g.C == 8 && a.g.mode == MODE_SAME && a.Cout % 32 == 0) {
+        const dim3 grid(a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP), a.Cout / 32);
+        hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     if (a.g.C % 32 == 0 && a.Cout % 32 == 0) {
         if (a.Cout % 64 == 0)
             launch_tiled<64>(a, st);
@@ -631,17 +806,38 @@ hipError_t conv3x3(const ConvP& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+int wgrad_patches(int B, int H, int W) { return B * ((H + TP - 1) / TP) * ((W + TP - 1) / TP); }
+
+// splits of the patch range: about 512 workgroups in all (2 per CU)
+int wgrad_nsplit(int B, int H, int W, int Cout, int Cin, int* per_split) {
+    const int np = wgrad_patches(B, H, W);
+    const int blocks = ((Cout + 31) / 32) * ((Cin + 31) / 32);
+    int ns = (512 + blocks - 1) / blocks;
+    if (ns > np) ns = np;
+    if (ns < 1) ns = 1;
+    const int per = (np + ns - 1) / ns;
+    *per_split = per;
+    return (np + per - 1) / per;
+}
+
 hipError_t wgrad(const WgradP& a, hipStream_t st) {
-    const int cb = (a.g.C + 31) / 32;
-    const int P = a.B * a.H * a.W;
-    const int nsplit = (P + a.px_per_split - 1) / a.px_per_split;
-    hipLaunchKernelGGL(k_wgrad, dim3((a.Cout + 31) / 32, 9 * cb, nsplit), dim3(256), 0, st, a);
+    int per;
+    const int ns = wgrad_nsplit(a.B, a.H, a.W, a.Cout, a.g.C, &per);
+    const int np = wgrad_patches(a.B, a.H, a.W);
+    const dim3 grid((a.Cout + 31) / 32, (a.g.C + 31) / 32, ns);
+    if (a.g.mode == MODE_POOL)
+        hipLaunchKernelGGL((k_wgrad_tiled<MODE_POOL>), grid, dim3(256), 0, st, a, per, np);
+    else if (a.g.mode == MODE_UP)
+        hipLaunchKernelGGL((k_wgrad_tiled<MODE_UP>), grid, dim3(256), 0, st, a, per, np);
+    else
+        hipLaunchKernelGGL((k_wgrad_tiled<MODE_SAME>), grid, dim3(256), 0, st, a, per, np);
     return hipGetLastError();
 }
 
 hipError_t reduce_splits(const float* part, int nsplit, size_t n, float* out, int acc,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_splits, dim3(blocks(n)), dim3(256), 0, st, part, nsplit, n, out, acc);
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, st, part,
+                       nsplit, n, out, acc);
     return hipGetLastError();
 }
 
@@ -651,9 +847,10 @@ hipError_t colsum(const __bf16* m, int P, int C, int px_per_block, float* part, 
     return hipGetLastError();
 }
 
-hipError_t silu_bwd(const float* dact, int cs, int c0, const __bf16* z, size_t P, int C,
-                    __bf16* dz, hipStream_t st) {
-    hipLaunchKernelGGL(k_silu_bwd, dim3(blocks(P * C)), dim3(256), 0, st, dact, cs, c0, z, P, C, dz);
+hipError_t silu_bwd(const float* dact, int cs, int c0, const __bf16* z, int P, int C, int ppb,
+                    __bf16* dz, float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_silu_bwd, dim3((P + ppb - 1) / ppb, (C + 31) / 32), dim3(256), 0, st, dact,
+                       cs, c0, z, P, C, ppb, dz, part);
     return hipGetLastError();
 }
 
@@ -679,17 +876,17 @@ hipError_t head_fwd(const __bf16* act, int cs, int c0, const float* wh, const fl
 
 hipError_t head_bwd(const __bf16* act, int cs, int c0, const float* wh, const float* dout, size_t P,
                     float* dact, int dcs, int dc0, float* part, hipStream_t st) {
-    hipLaunchKernelGGL(k_head_bwd, dim3(blocks(P)), dim3(256), 0, st, act, cs, c0, wh, dout, P, dact,
+    hipLaunchKernelGGL(k_head_bwd, dim3(head_blocks(P)), dim3(256), 0, st, act, cs, c0, wh, dout, P, dact,
                        dcs, dc0, part);
     return hipGetLastError();
 }
 
-unsigned head_blocks(size_t P) { return blocks(P); }
+unsigned head_blocks(size_t P) { return (unsigned)((P + HEAD_PPB - 1) / HEAD_PPB); }
 
 hipError_t mse(const float* out, const float* y, size_t n, float* dout, double* part, double* res,
                hipStream_t st) {
     hipLaunchKernelGGL(k_mse, dim3(blocks(n)), dim3(256), 0, st, out, y, n, dout, part);
-    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, st, part, (int)blocks(n), res);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, st, part, (int)blocks(n), res);
     return hipGetLastError();
 }
 
