@@ -101,18 +101,22 @@ int pfsur_train_step(pfsur_ctx* ctx, const void* x, const float* y, int batch, f
 int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, float* host_grad,
                     float* loss, void* workspace, void* stream);
 
-/* Guarded advance of a D2Q9 lattice Boltzmann context by `windows` x 16 steps.  For
- * each window the surrogate predicts the state 16 steps ahead; it is accepted when
+/* Guarded advance of a batch of D2Q9 lattice Boltzmann contexts by `windows` x 16 steps.
+ * For each window the surrogate predicts, in one batched forward pass, the state 16
+ * steps ahead of every context; the prediction for context k is accepted when
  * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)| and, on every
  * check_every-th window (0: never), when max|phi_out - phi_LB| <= phi_tol against 16
- * plain steps taken from the same state.  An accepted prediction becomes the new state
- * (pflb_reconstruct); otherwise the 16 plain steps are taken.  lrr is
- * log10(rho_H/rho_L) of the context.  work must hold pfsur_guard_work_bytes().
- * *n_fallback (host) counts the windows that fell back.  Synchronous. */
-size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg);
-int pflb_advance_guarded(pflb_ctx* lb, pfsur_ctx* sur, int windows, double lrr,
-                         double mass_tol, double phi_tol, int check_every, int* n_fallback,
-                         void* work, void* stream);
+ * plain steps taken from the same state.  An accepted prediction becomes the context's
+ * new state (pflb_reconstruct); otherwise the 16 plain steps are taken.
+ *   lbs[batch]  contexts (periodic, nx = W, ny = H), batch <= max_batch
+ *   lrr[batch]  host array of log10(rho_H/rho_L) per context
+ *   work        pfsur_guard_work_bytes(cfg, batch) bytes of device memory, 256-aligned
+ *   *n_fallback (host) number of (window, context) pairs that fell back.
+ * Synchronous. */
+size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch);
+int pflb_advance_guarded(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int windows,
+                         const double* lrr, double mass_tol, double phi_tol, int check_every,
+                         int* n_fallback, void* work, void* stream);
 
 /* The accept rule of pflb_advance_guarded, a pure host function (1 accept, 0 reject):
  * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums) and,

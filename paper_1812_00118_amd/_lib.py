@@ -79,9 +79,10 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_float), _vp, _vp]),
     "pfsur_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp,
                                        ctypes.POINTER(ctypes.c_float), _vp, _vp]),
-    "pfsur_guard_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg)]),
-    "pflb_advance_guarded": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double,
-                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+    "pfsur_guard_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int]),
+    "pflb_advance_guarded": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int), _vp, _vp]),
     "pfsur_guard_accept": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int, ctypes.c_double, ctypes.c_double]),

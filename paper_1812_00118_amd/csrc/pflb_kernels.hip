@@ -19,6 +19,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
     return xcd < rem ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
 }
 
+// Workgroup barrier over LDS traffic only.  Inside the step no thread reads global
+// memory that another thread writes (src is read-only, dst write-only), so the global
+// stores of a finished plane may stay in flight across it; __syncthreads() would wait
+// for them (vmcnt(0)) at every plane.  The memory clobber keeps the compiler from
+// moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Fused step.  A workgroup owns a TX x TY column tile (D2Q9: TX x 1) and marches
 // along z over BZ planes.  phi of plane z+1 on the tile plus a one-site ring is
@@ -92,7 +101,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                                            : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
         sphi[(z + 1) & 3][ty + OY][tx + 1] = split_hi_lo(pn64, lo_n);
         if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
-        __syncthreads();
+        lds_barrier();
         if (active) {
             const ZRow r = make_zrow(G, z);
             float pn[Q];

@@ -532,7 +532,7 @@ struct GuardPlan {
     size_t phi, P, J, phi_lb, x, out, ws, recon, dpart, fpart, total;
 };
 
-GuardPlan guard_plan(const pfsur_cfg* cfg) {
+GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     GuardPlan g;
     const size_t HW = (size_t)cfg->H * cfg->W;
     size_t o = 0;
@@ -541,29 +541,34 @@ GuardPlan guard_plan(const pfsur_cfg* cfg) {
         o += align256(bytes);
         return r;
     };
-    g.phi = take(HW * 4);
-    g.P = take(HW * 4);
-    g.J = take(2 * HW * 4);
+    g.phi = take(n * HW * 4);
+    g.P = take(n * HW * 4);
+    g.J = take(n * 2 * HW * 4);
     g.phi_lb = take(HW * 4);
-    g.x = take(HW * PFSUR_IN_CH * 2);
-    g.out = take(HW * PFSUR_OUT_CH * 4);
-    g.ws = take(make_plan(cfg->H, cfg->W, 1, false).total);
+    g.x = take(n * HW * PFSUR_IN_CH * 2);
+    g.out = take(n * HW * PFSUR_OUT_CH * 4);
+    g.ws = take(make_plan(cfg->H, cfg->W, n, false).total);
     g.recon = take((2 * 9 + 2) * HW * 4);
-    g.dpart = take(GUARD_BLOCKS * 8);
+    g.dpart = take((size_t)n * GUARD_BLOCKS * 8);
     g.fpart = take(GUARD_BLOCKS * 4);
     g.total = o;
     return g;
 }
 
-// fixed-order host sum of per-block partial sums (deterministic)
-int field_sum(pfsur_ctx* c, const float* a, size_t n, double* dpart, hipStream_t st, double* res) {
-    SUR_TRY(sum_field(a, n, dpart, GUARD_BLOCKS, st), "field sum");
-    double h[GUARD_BLOCKS];
-    SUR_TRY(hipMemcpyAsync(h, dpart, sizeof(h), hipMemcpyDeviceToHost, st), "field sum read-back");
+// per-sample sums of n fields of HW values, each a fixed-order host sum of per-block
+// partial sums (deterministic)
+int field_sums(pfsur_ctx* c, const float* a, int n, size_t HW, double* dpart, hipStream_t st,
+               std::vector<double>& res) {
+    for (int k = 0; k < n; ++k)
+        SUR_TRY(sum_field(a + k * HW, HW, dpart + (size_t)k * GUARD_BLOCKS, GUARD_BLOCKS, st),
+                "field sum");
+    std::vector<double> h((size_t)n * GUARD_BLOCKS);
+    SUR_TRY(hipMemcpyAsync(h.data(), dpart, h.size() * 8, hipMemcpyDeviceToHost, st),
+            "field sum read-back");
     SUR_TRY(hipStreamSynchronize(st), "field sum read-back");
-    double s = 0.0;
-    for (int k = 0; k < GUARD_BLOCKS; ++k) s += h[k];
-    *res = s;
+    res.assign(n, 0.0);
+    for (int k = 0; k < n; ++k)
+        for (int b = 0; b < GUARD_BLOCKS; ++b) res[k] += h[(size_t)k * GUARD_BLOCKS + b];
     return PFLB_OK;
 }
 
@@ -571,27 +576,31 @@ int field_sum(pfsur_ctx* c, const float* a, size_t n, double* dpart, hipStream_t
 
 extern "C" {
 
-size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg) {
-    if (!check_cfg(cfg).empty()) return 0;
-    return guard_plan(cfg).total;
+size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch) {
+    if (!check_cfg(cfg).empty() || batch < 1 || batch > cfg->max_batch) return 0;
+    return guard_plan(cfg, batch).total;
 }
 
-int pflb_advance_guarded(pflb_ctx* lb, pfsur_ctx* c, int windows, double lrr, double mass_tol,
-                         double phi_tol, int check_every, int* n_fallback, void* work,
-                         void* stream) {
+int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
+                         const double* lrr, double mass_tol, double phi_tol, int check_every,
+                         int* n_fallback, void* work, void* stream) {
     if (!c) return PFLB_ERR_PARAM;
-    if (!lb || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
+    if (!lbs || !lrr || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
+    if (n < 1 || n > c->cfg.max_batch) return fail(c, PFLB_ERR_PARAM, "batch must be in [1, max_batch]");
     if (((uintptr_t)work & 255u)) return fail(c, PFLB_ERR_ALIGN, "work must be 256-byte aligned");
     if (windows < 0 || check_every < 0) return fail(c, PFLB_ERR_PARAM, "negative count");
-    pflb::CtxInfo info;
-    if (pflb_ctx_info(lb, &info) != PFLB_OK || !info.bound)
-        return fail(c, PFLB_ERR_UNBOUND, "lattice context not bound");
-    if (info.q != 9 || info.nx != c->cfg.W || info.ny != c->cfg.H || info.bc[0] != PFLB_BC_PERIODIC ||
-        info.bc[1] != PFLB_BC_PERIODIC)
-        return fail(c, PFLB_ERR_PARAM, "lattice must be D2Q9, periodic, nx = W, ny = H");
+    for (int k = 0; k < n; ++k) {
+        pflb::CtxInfo info;
+        if (!lbs[k] || pflb_ctx_info(lbs[k], &info) != PFLB_OK || !info.bound)
+            return fail(c, PFLB_ERR_UNBOUND, "lattice context missing or not bound");
+        if (info.q != 9 || info.nx != c->cfg.W || info.ny != c->cfg.H ||
+            info.bc[0] != PFLB_BC_PERIODIC || info.bc[1] != PFLB_BC_PERIODIC)
+            return fail(c, PFLB_ERR_PARAM, "lattices must be D2Q9, periodic, nx = W, ny = H");
+    }
     hipStream_t st = (hipStream_t)stream;
-    const GuardPlan g = guard_plan(&c->cfg);
+    const GuardPlan g = guard_plan(&c->cfg, n);
     char* w = static_cast<char*>(work);
+    const size_t HW = (size_t)c->cfg.H * c->cfg.W;
     float* phi = reinterpret_cast<float*>(w + g.phi);
     float* P = reinterpret_cast<float*>(w + g.P);
     float* J = reinterpret_cast<float*>(w + g.J);
@@ -599,41 +608,43 @@ int pflb_advance_guarded(pflb_ctx* lb, pfsur_ctx* c, int windows, double lrr, do
     float* out = reinterpret_cast<float*>(w + g.out);
     double* dpart = reinterpret_cast<double*>(w + g.dpart);
     float* fpart = reinterpret_cast<float*>(w + g.fpart);
-    const size_t HW = (size_t)c->cfg.H * c->cfg.W;
     *n_fallback = 0;
+    std::vector<double> s_in, s_out;
     for (int win = 0; win < windows; ++win) {
-        int r = pflb_read(lb, phi, P, J, nullptr, st);
-        if (r) return fail(c, r, std::string("lattice read: ") + pflb_last_error(lb));
-        double s_in = 0.0, s_out = 0.0;
-        if ((r = field_sum(c, phi, HW, dpart, st, &s_in))) return r;
-        if ((r = pfsur_pack(c, phi, P, J, &lrr, 1, w + g.x, st))) return r;
-        if ((r = run_forward(c, w + g.x, out, 1, w + g.ws, false, st))) return r;
-        if ((r = pfsur_apply(c, out, phi, P, J, 1, st))) return r;
-        if ((r = field_sum(c, phi, HW, dpart, st, &s_out))) return r;
+        int r;
+        for (int k = 0; k < n; ++k)
+            if ((r = pflb_read(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW, nullptr, st)))
+                return fail(c, r, std::string("lattice read: ") + pflb_last_error(lbs[k]));
+        if ((r = field_sums(c, phi, n, HW, dpart, st, s_in))) return r;
+        if ((r = pfsur_pack(c, phi, P, J, lrr, n, w + g.x, st))) return r;
+        if ((r = run_forward(c, w + g.x, out, n, w + g.ws, false, st))) return r;
+        if ((r = pfsur_apply(c, out, phi, P, J, n, st))) return r;
+        if ((r = field_sums(c, phi, n, HW, dpart, st, s_out))) return r;
         const bool checked = check_every > 0 && (win + 1) % check_every == 0;
-        double err = 0.0;
-        if (checked) {
-            // the plain steps from the same state are the reference; if the prediction is
-            // rejected they are the fallback already taken
-            r = pflb_step(lb, PFSUR_STEPS, st);
-            if (!r) r = pflb_read(lb, phi_lb, nullptr, nullptr, nullptr, st);
-            if (r) return fail(c, r, std::string("lattice steps: ") + pflb_last_error(lb));
-            SUR_TRY(maxdiff(phi, phi_lb, HW, fpart, GUARD_BLOCKS, st), "phi check");
-            float h[GUARD_BLOCKS];
-            SUR_TRY(hipMemcpyAsync(h, fpart, sizeof(h), hipMemcpyDeviceToHost, st), "phi check");
-            SUR_TRY(hipStreamSynchronize(st), "phi check");
-            for (int k = 0; k < GUARD_BLOCKS; ++k) err = h[k] > err || h[k] != h[k] ? h[k] : err;
-            if (err != err) err = INFINITY;
-        }
-        if (pfsur_guard_accept(s_in, s_out, mass_tol, checked, err, phi_tol)) {
-            r = pflb_reconstruct(lb, phi, P, J, reinterpret_cast<float*>(w + g.recon),
-                                 checked ? 0 : PFSUR_STEPS, st);
-            if (r) return fail(c, r, std::string("hand-over: ") + pflb_last_error(lb));
-        } else {
-            *n_fallback += 1;
-            if (!checked) {
-                r = pflb_step(lb, PFSUR_STEPS, st);
-                if (r) return fail(c, r, std::string("fallback steps: ") + pflb_last_error(lb));
+        for (int k = 0; k < n; ++k) {
+            double err = 0.0;
+            if (checked) {
+                // the plain steps from the same state are the reference; if the
+                // prediction is rejected they are the fallback already taken
+                r = pflb_step(lbs[k], PFSUR_STEPS, st);
+                if (!r) r = pflb_read(lbs[k], phi_lb, nullptr, nullptr, nullptr, st);
+                if (r) return fail(c, r, std::string("lattice steps: ") + pflb_last_error(lbs[k]));
+                SUR_TRY(maxdiff(phi + k * HW, phi_lb, HW, fpart, GUARD_BLOCKS, st), "phi check");
+                float h[GUARD_BLOCKS];
+                SUR_TRY(hipMemcpyAsync(h, fpart, sizeof(h), hipMemcpyDeviceToHost, st), "phi check");
+                SUR_TRY(hipStreamSynchronize(st), "phi check");
+                for (int b = 0; b < GUARD_BLOCKS; ++b) err = h[b] > err || h[b] != h[b] ? h[b] : err;
+                if (err != err) err = INFINITY;
+            }
+            if (pfsur_guard_accept(s_in[k], s_out[k], mass_tol, checked, err, phi_tol)) {
+                r = pflb_reconstruct(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW,
+                                     reinterpret_cast<float*>(w + g.recon), checked ? 0 : PFSUR_STEPS,
+                                     st);
+                if (r) return fail(c, r, std::string("hand-over: ") + pflb_last_error(lbs[k]));
+            } else {
+                *n_fallback += 1;
+                if (!checked && (r = pflb_step(lbs[k], PFSUR_STEPS, st)))
+                    return fail(c, r, std::string("fallback steps: ") + pflb_last_error(lbs[k]));
             }
         }
     }

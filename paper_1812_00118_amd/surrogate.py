@@ -179,14 +179,22 @@ class Surrogate:
         return g, float(loss.value)
 
     # ------------------------------------------------------------------ hand-over
-    def advance_guarded(self, sim, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0):
-        """Advance a D2Q9 periodic Sim by windows x 16 steps; returns the number of
-        windows that fell back to the plain steps."""
-        n = int(self.L.pfsur_guard_work_bytes(ctypes.byref(self.cfg)))
-        work = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+    def advance_guarded(self, sims, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0):
+        """Advance D2Q9 periodic Sims (one, or a list of at most max_batch) by windows x 16
+        steps with one batched forward pass per window; returns the number of (window,
+        sim) pairs that fell back to the plain steps."""
+        if not isinstance(sims, (list, tuple)):
+            sims, lrr = [sims], [lrr]
+        n = len(sims)
+        nb = int(self.L.pfsur_guard_work_bytes(ctypes.byref(self.cfg), n))
+        if nb == 0:
+            raise PflbError(-1, f"no guard workspace for {n} contexts")
+        work = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in sims])
+        lr = (ctypes.c_double * n)(*[float(v) for v in lrr])
         nf = ctypes.c_int()
-        self._check(self.L.pflb_advance_guarded(sim.ctx, self.ctx, int(windows), float(lrr),
+        self._check(self.L.pflb_advance_guarded(ctxs, n, self.ctx, int(windows), lr,
                                                 float(mass_tol), float(phi_tol),
                                                 int(check_every), ctypes.byref(nf), wp,
                                                 _stream(self.device)))

@@ -314,7 +314,7 @@ def test_reconstruct_reads_back_the_fields():
 def _net(sur_mod, n, seed=1, out_scale=1e-3):
     norm = dict(in_shift=[0.5, 0.0, 0.0, 0.0], in_scale=[2.0, 100.0, 100.0, 100.0],
                 out_scale=[out_scale] * 4, lrr_scale=0.5)
-    s = sur_mod.Surrogate(n, n, 1, norm)
+    s = sur_mod.Surrogate(n, n, 4, norm)
     s.set_params(flat_params(U.init_weights(seed, scale=0.1)))
     return s
 
@@ -354,3 +354,32 @@ def test_guard_accepts_and_hands_over_the_prediction(sur_mod):
     nf = s.advance_guarded(c, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=1)
     assert nf == 0 and c.steps == 16
     assert torch.equal(a.read(("phi",))["phi"], c.read(("phi",))["phi"])
+
+
+def test_batched_guard_matches_single_context_guard(sur_mod):
+    """One batched window over three contexts hands over the same states as three
+    single-context windows, and a forced fallback equals plain stepping for all."""
+    s = _net(sur_mod, 64)
+    seeds = (3, 4, 5)
+    cfgs = [pfinputs_drops(k) for k in seeds]
+    lrr = [float(np.log10(c["rho_H"])) for c in cfgs]
+    batch = [_drops_sim(seed=k)[0] for k in seeds]
+    nf = s.advance_guarded(batch, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0)
+    assert nf == 0
+    for k, seed in enumerate(seeds):
+        one, _ = _drops_sim(seed=seed)
+        assert s.advance_guarded(one, 1, lrr[k], mass_tol=1e30, phi_tol=1e30) == 0
+        assert torch.equal(batch[k].read(("phi",))["phi"], one.read(("phi",))["phi"])
+    plain = [_drops_sim(seed=k)[0] for k in seeds]
+    fb = [_drops_sim(seed=k)[0] for k in seeds]
+    nf = s.advance_guarded(fb, 2, lrr, mass_tol=0.0, phi_tol=1.0, check_every=0)
+    assert nf == 6
+    for a, b in zip(fb, plain):
+        b.step(32)
+        assert a.steps == 32
+        assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+
+
+def pfinputs_drops(seed, n=64):
+    import pfinputs as I
+    return I.drops(seed, n=n)

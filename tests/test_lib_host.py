@@ -61,7 +61,9 @@ def test_surrogate_workspace_planning(L):
     assert L.pfsur_workspace_bytes(ctypes.byref(c), 0, 0) == 0
     for bad in (dict(H=20), dict(W=8), dict(max_batch=0), dict(max_batch=2000)):
         assert L.pfsur_workspace_bytes(ctypes.byref(_sur_cfg(**bad)), 1, 0) == 0, bad
-    assert L.pfsur_guard_work_bytes(ctypes.byref(c)) > inf1
+    assert L.pfsur_guard_work_bytes(ctypes.byref(c), 1) > inf1
+    assert L.pfsur_guard_work_bytes(ctypes.byref(c), 4) > 3 * L.pfsur_guard_work_bytes(ctypes.byref(c), 1)
+    assert L.pfsur_guard_work_bytes(ctypes.byref(c), 5) == 0
 
 
 def test_guard_accept_rule(L):
