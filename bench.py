@@ -36,12 +36,15 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rising_bubble_traffic.t
 CSRC = os.path.join(ROOT, "paper_1812_00118_amd", "csrc")
 
 
+STEP_SOURCES = ("pflb_device.hpp", "pflb_internal.hpp", "pflb_kernels.hip")
+
+
 def kernel_source_sha1():
-    """Hash of the HIP sources: counter figures taken for another build are not used."""
+    """Hash of the step kernel's sources: counter figures taken for another build of it
+    are not used."""
     h = hashlib.sha1()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(CSRC, f), "rb").read())
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sur_internal.hpp"
 
 namespace pfsur {
@@ -167,7 +169,7 @@ __device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc
 }
 
 template <int NT, int MODE>
-__global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
+__global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a, int tiles_per_wg) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
     constexpr int NB = NT / 32;
@@ -176,24 +178,36 @@ __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l32 = lane & 31, g = lane >> 5;
     const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
-    int blk = blockIdx.x;
-    const int tx = blk % tx_n;
-    blk /= tx_n;
-    const int ty = blk % ty_n;
-    const int b = blk / ty_n;
-    const int x0 = tx * TP, y0 = ty * TP;
+    const int ntile = a.B * tx_n * ty_n;
+    const int t_beg = blockIdx.x * tiles_per_wg;
+    const int t_end = min(ntile, t_beg + tiles_per_wg);
     const int co0 = blockIdx.y * NT;
     const int C = a.g.C;
     const int nchunk = C / 32;
+    // the (tile, chunk) pairs of this workgroup, in order; with one chunk the weights
+    // are staged once
+    const int niter = (t_end - t_beg) * nchunk;
     const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
 
+    auto tile_xy = [&](int t, int& b, int& y0, int& x0) {
+        const int tx = t % tx_n;
+        t /= tx_n;
+        const int ty = t % ty_n;
+        b = t / ty_n;
+        x0 = tx * TP;
+        y0 = ty * TP;
+    };
+
     bf16x8 ra[A_PER_T], rb[B_PER_T];
-    auto load_a = [&](int c0) {
+    auto load_a = [&](int it) {
+        int b, y0, x0;
+        tile_xy(t_beg + it / nchunk, b, y0, x0);
+        const int c0 = (it % nchunk) * 32;
 #pragma unroll
         for (int k = 0; k < A_PER_T; ++k) {
-            const int it = threadIdx.x + 256 * k;
-            if (it < A_ITEMS) {
-                const int pi = it >> 2, grp = it & 3;
+            const int i = threadIdx.x + 256 * k;
+            if (i < A_ITEMS) {
+                const int pi = i >> 2, grp = i & 3;
                 const int py = pi / HP, px = pi - py * HP;
                 ra[k] = gather8(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W),
                                 c0 + 8 * grp);
@@ -203,19 +217,20 @@ __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
     auto store_a = [&]() {
 #pragma unroll
         for (int k = 0; k < A_PER_T; ++k) {
-            const int it = threadIdx.x + 256 * k;
-            if (it < A_ITEMS)
-                *reinterpret_cast<bf16x8*>(&sA[(it >> 2) * APAD + 8 * (it & 3)]) = ra[k];
+            const int i = threadIdx.x + 256 * k;
+            if (i < A_ITEMS)
+                *reinterpret_cast<bf16x8*>(&sA[(i >> 2) * APAD + 8 * (i & 3)]) = ra[k];
         }
     };
-    auto load_b = [&](int c0) {
+    auto load_b = [&](int it) {
+        const int c0 = (it % nchunk) * 32;
 #pragma unroll
         for (int k = 0; k < B_PER_T; ++k) {
-            const int it = threadIdx.x + 256 * k;
-            const int col = it / 36, rem = it - col * 36;
+            const int i = threadIdx.x + 256 * k;
+            const int col = i / 36, rem = i - col * 36;
             const int tap = rem >> 2, grp = rem & 3;
             const int co = co0 + col;
-            rb[k] = (it < B_ITEMS && co < a.Cout)
+            rb[k] = (i < B_ITEMS && co < a.Cout)
                         ? *reinterpret_cast<const bf16x8*>(a.w + ((size_t)co * 9 + tap) * C +
                                                            c0 + 8 * grp)
                         : zero8;
@@ -224,34 +239,38 @@ __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
     auto store_b = [&]() {
 #pragma unroll
         for (int k = 0; k < B_PER_T; ++k) {
-            const int it = threadIdx.x + 256 * k;
-            const int col = it / 36, rem = it - col * 36;
-            if (it < B_ITEMS) *reinterpret_cast<bf16x8*>(&sB[col * BPAD + rem * 8]) = rb[k];
+            const int i = threadIdx.x + 256 * k;
+            const int col = i / 36, rem = i - col * 36;
+            if (i < B_ITEMS) *reinterpret_cast<bf16x8*>(&sB[col * BPAD + rem * 8]) = rb[k];
         }
     };
 
     f32x16 acc[2][NB];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.0f;
-
     // this lane's pixel in each row block: patch row 4w + 2mb + l32/16, column l32%16
     const int prow = 4 * wave + (l32 >> 4), pcol = l32 & 15;
 
-    load_b(0);
-    if (MODE != MODE_POOL) load_a(0);
-    for (int ch = 0; ch < nchunk; ++ch) {
+    if (niter > 0) {
+        load_b(0);
+        if (MODE != MODE_POOL) load_a(0);
+    }
+    for (int it = 0; it < niter; ++it) {
+        const int ch = it % nchunk;
+        if (ch == 0) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.0f;
+        }
         __syncthreads();                         // the previous chunk is consumed
-        if (MODE == MODE_POOL) load_a(ch * 32);  // pooled gathers average at once
+        if (MODE == MODE_POOL) load_a(it);       // pooled gathers average at once
         store_a();
-        store_b();
+        if (nchunk > 1 || it == 0) store_b();
         __syncthreads();
-        if (ch + 1 < nchunk) {
-            load_b((ch + 1) * 32);
-            if (MODE != MODE_POOL) load_a((ch + 1) * 32);
+        if (it + 1 < niter) {
+            if (nchunk > 1) load_b(it + 1);
+            if (MODE != MODE_POOL) load_a(it + 1);
         }
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
@@ -275,8 +294,12 @@ __global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a) {
                                                                              acc[mb][nb], 0, 0, 0);
             }
         }
+        if (ch == nchunk - 1) {
+            int b, y0, x0;
+            tile_xy(t_beg + it / nchunk, b, y0, x0);
+            tile_epilogue<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
+        }
     }
-    tile_epilogue<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,13 +802,18 @@ static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int NT>
 static void launch_tiled(const ConvP& a, hipStream_t st) {
-    const dim3 grid(a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP), (a.Cout + NT - 1) / NT);
+    // about 512 workgroups (2 per CU) in all; each walks a contiguous run of tiles so
+    // that the loads of its next tile overlap the MFMAs of the current one
+    const int ntile = a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP);
+    const int nblk_n = (a.Cout + NT - 1) / NT;
+    const int per = std::max(1, (ntile * nblk_n + 511) / 512);
+    const dim3 grid((ntile + per - 1) / per, nblk_n);
     if (a.g.mode == MODE_POOL)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL>), grid, dim3(256), 0, st, a, per);
     else if (a.g.mode == MODE_UP)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP>), grid, dim3(256), 0, st, a, per);
     else
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME>), grid, dim3(256), 0, st, a, per);
 }
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st) {

@@ -51,6 +51,10 @@ ONE_STEP_CASES = [
     ("d3q19-walls-z", 19, (70, 9, 13), (P_, P_, W_)),
     ("d3q19-walls-all", 19, (17, 11, 6), (W_, W_, W_)),
     ("d3q19-tiny", 19, (2, 3, 1), (W_, P_, P_)),
+    # degenerate: one site (every neighbour is the site itself, or a wall on each side)
+    ("d3q19-single", 19, (1, 1, 1), (P_, P_, P_)),
+    ("d2q9-single-walls", 9, (1, 1, 1), (W_, W_, P_)),
+    ("d3q19-single-walls", 19, (1, 1, 1), (W_, W_, W_)),
 ]
 
 
