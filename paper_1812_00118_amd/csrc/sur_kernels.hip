@@ -488,22 +488,31 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_tiled(WgradP a, int patches_pe
     }
 }
 
-// out[i] = sum_s part[s][i] (+ out[i] if accumulate).  A block takes 32 consecutive i;
-// its 8 rows of lanes take every 8th split, then the 8 row sums are added in order.
+// out[i] = sum_s part[s][i] (+ out[i] if accumulate).  A block takes 64 consecutive i;
+// its 4 rows of lanes take every 4th split, each with four independent partial sums
+// (splits k, k+4, k+8, k+12 of a stride of 16) so that several loads are in flight;
+// every combination is in a fixed order, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(256) k_reduce_splits(const float* __restrict__ part, int nsplit,
                                                        size_t n, float* __restrict__ out,
                                                        int accumulate) {
-    __shared__ float sred[8][33];
-    const int ci = threadIdx.x & 31, sl = threadIdx.x >> 5;
-    const size_t i = (size_t)blockIdx.x * 32 + ci;
-    float acc = 0.f;
-    if (i < n)
-        for (int k = sl; k < nsplit; k += 8) acc += part[(size_t)k * n + i];
-    sred[sl][ci] = acc;
+    __shared__ float sred[4][65];
+    const int ci = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const size_t i = (size_t)blockIdx.x * 64 + ci;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (i < n) {
+        int k = sl;
+        for (; k + 12 < nsplit; k += 16) {
+            a0 += part[(size_t)k * n + i];
+            a1 += part[(size_t)(k + 4) * n + i];
+            a2 += part[(size_t)(k + 8) * n + i];
+            a3 += part[(size_t)(k + 12) * n + i];
+        }
+        for (; k < nsplit; k += 4) a0 += part[(size_t)k * n + i];
+    }
+    sred[sl][ci] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (sl == 0 && i < n) {
-        float t = 0.f;
-        for (int k = 0; k < 8; ++k) t += sred[k][ci];
+        const float t = ((sred[0][ci] + sred[1][ci]) + sred[2][ci]) + sred[3][ci];
         out[i] = accumulate ? out[i] + t : t;
     }
 }
@@ -864,7 +873,7 @@ hipError_t wgrad(const WgradP& a, hipStream_t st) {
 
 hipError_t reduce_splits(const float* part, int nsplit, size_t n, float* out, int acc,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, st, part,
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, part,
                        nsplit, n, out, acc);
     return hipGetLastError();
 }
