@@ -61,6 +61,9 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sur-train-steps", type=int, default=2000)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-profile", action="store_true",
+                    help="only run 3 surrogate forward passes at batch 32 and 2 training steps "
+                         "at batch 8 (random weights; for a kernel trace)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (counter calibration)")
     return ap.parse_args()
@@ -259,10 +262,28 @@ def surrogate_block(train_steps):
     }
 
 
+def sur_profile():
+    import torch
+    from paper_1812_00118_amd import surrogate as S
+    norm = dict(in_shift=[0.0] * 4, in_scale=[1.0] * 4, out_scale=[1.0] * 4, lrr_scale=1.0)
+    sur = S.Surrogate(256, 256, 32, norm)
+    sur.set_params(S.init_params(0))
+    x = torch.zeros((32, 256, 256, S.IN_CH), dtype=torch.bfloat16, device="cuda")
+    fwd = [_events_ms(lambda: sur.forward(x), 1) for _ in range(3)]
+    xb = torch.zeros((8, 256, 256, S.IN_CH), dtype=torch.bfloat16, device="cuda")
+    yb = torch.zeros((8, 256, 256, S.OUT_CH), device="cuda")
+    trn = _events_ms(lambda: sur.train_step(xb, yb, 0.0), 2)
+    print(json.dumps({"forward_ms_batch32": round(min(fwd), 4),
+                      "train_step_ms_batch8": round(trn, 4)}), flush=True)
+
+
 def main():
     args = parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.sur_profile:
+        sur_profile()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
