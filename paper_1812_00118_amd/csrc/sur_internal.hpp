@@ -72,7 +72,6 @@ unsigned mse_blocks(size_t n);
 hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr, int t,
                 hipStream_t st);
 hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* wt, hipStream_t st);
-hipError_t fill(float* p, size_t n, float v, hipStream_t st);
 hipError_t pack(const float* phi, const float* P, const float* J, float lrr, const Norm& nm,
                 size_t HW, __bf16* x, hipStream_t st);
 hipError_t pack_target(const float* phi0, const float* P0, const float* J0, const float* phi1,

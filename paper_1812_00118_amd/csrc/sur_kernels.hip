@@ -726,11 +726,6 @@ __global__ void k_weights_bf16(const float* __restrict__ w, int Cout, int Cin, _
     if (wt) wt[((size_t)ci * 9 + (8 - tap)) * Cout + co] = (__bf16)w[i];
 }
 
-__global__ void k_fill(float* __restrict__ p, size_t n, float v) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // network input of one sample from solver fields: x[y, x, :] = ((phi - s0) k0,
 // (P - s1) k1, (Jx - s2) k2, (Jy - s3) k3, lrr lrr_scale, 0, 0, 0)
 __global__ void k_pack(const float* __restrict__ phi, const float* __restrict__ P,
@@ -941,12 +936,6 @@ hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr
 hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* wt, hipStream_t st) {
     hipLaunchKernelGGL(k_weights_bf16, dim3(blocks((size_t)Cout * 9 * Cin)), dim3(256), 0, st, w,
                        Cout, Cin, wf, wt);
-    return hipGetLastError();
-}
-
-hipError_t fill(float* p, size_t n, float v, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(blocks(n)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 
