@@ -168,8 +168,10 @@ __device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc
     }
 }
 
+// 32-channel tiles use 45 KB of LDS, so three workgroups fit a CU when the registers
+// allow it; 64-channel tiles (64 KB) fit two.
 template <int NT, int MODE>
-__global__ void __launch_bounds__(256, 2) k_conv_tiled(ConvP a, int tiles_per_wg) {
+__global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, int tiles_per_wg) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
     constexpr int NB = NT / 32;
@@ -806,11 +808,13 @@ static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int NT>
 static void launch_tiled(const ConvP& a, hipStream_t st) {
-    // about 512 workgroups (2 per CU) in all; each walks a contiguous run of tiles so
-    // that the loads of its next tile overlap the MFMAs of the current one
+    // as many workgroups as are resident at once (3 or 2 per CU); each walks a
+    // contiguous run of tiles so that the loads of its next tile overlap the MFMAs of
+    // the current one
+    constexpr int resident = NT == 32 ? 768 : 512;
     const int ntile = a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP);
     const int nblk_n = (a.Cout + NT - 1) / NT;
-    const int per = std::max(1, (ntile * nblk_n + 511) / 512);
+    const int per = std::max(1, (ntile * nblk_n + resident - 1) / resident);
     const dim3 grid((ntile + per - 1) / per, nblk_n);
     if (a.g.mode == MODE_POOL)
         hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL>), grid, dim3(256), 0, st, a, per);
