@@ -127,9 +127,10 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvP a) {
 // 18x18 halo patch (wrap, pooling or upsampling applied while loading) and its
 // NT x 9 x 32 weights are staged in LDS, and the loads of the next chunk are issued
 // into registers before the current chunk is computed.  Wave w owns patch rows
-// 4w..4w+3 as two 32-pixel MFMA row blocks; v_mfma_f32_32x32x16_bf16 (lane l: A row
-// l%32 = pixel, B column l%32 = channel, K elements 8(l/32)..+7; D column l%32, rows
-// 8(j/4) + 4(l/32) + j%4).  Row strides are padded (40 and 296 BF16) so that 16
+// 4w..4w+3 as two 32-pixel blocks; v_mfma_f32_32x32x16_bf16 takes the weights as A
+// (lane l: row l%32 = output channel, K elements 8(l/32)..+7) and the pixels as B
+// (column l%32 = pixel, same K), so D[channel][pixel] has lane l on pixel l%32 with
+// channels 8(j/4) + 4(l/32) + j%4.  Row strides are padded (40 and 296 BF16) so that 16
 // consecutive lanes reading 16 bytes hit distinct banks.
 // ---------------------------------------------------------------------------
 constexpr int TP = 16;                 // output patch edge
@@ -139,30 +140,49 @@ constexpr int BPAD = 9 * 32 + 8;       // BF16 per staged output channel
 constexpr int A_ITEMS = HP * HP * 4;   // 16-byte items of the halo patch
 constexpr int A_PER_T = (A_ITEMS + 255) / 256;
 
-// Epilogue of a 16x16-pixel tile: the lane holds channel co0 + 32 nb + l32 of 16 pixels
-// per 32-pixel row block (D rows 8(j/4) + 4g + j%4).
+// Epilogue of a 16x16-pixel tile.  The MFMAs compute D[channel][pixel] (weights as the
+// A operand), so lane l holds pixel l%32 of its 32-pixel row block and, for j = 0..15,
+// channel 8(j/4) + 4(l/32) + j%4 of the 32-channel block: runs of 4 consecutive channels,
+// written as one 8-byte (BF16) or 16-byte (FP32) store each.
 template <int NB>
 __device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc)[2][NB], int b,
                                               int y0, int x0, int co0, int wave, int l32, int g) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int co = co0 + nb * 32 + l32;
-        if (co >= a.Cout) continue;
-        const float bias = a.bias ? a.bias[co] : 0.0f;
+    for (int mb = 0; mb < 2; ++mb) {
+        const int y = y0 + 4 * wave + 2 * mb + (l32 >> 4), x = x0 + (l32 & 15);
+        if (y >= a.H || x >= a.W) continue;
+        const size_t p = ((size_t)b * a.H + y) * a.W + x;
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int idx = 8 * (j >> 2) + 4 * g + (j & 3);   // pixel in the row block
-                const int y = y0 + 4 * wave + 2 * mb + (idx >> 4), x = x0 + (idx & 15);
-                if (y >= a.H || x >= a.W) continue;
-                const size_t p = ((size_t)b * a.H + y) * a.W + x;
-                const float v = acc[mb][nb][j] + bias;
-                if (a.zout) a.zout[p * a.Cout + co] = (__bf16)v;
-                if (a.out) a.out[p * a.out_cs + a.out_c0 + co] = (__bf16)(a.act ? silu(v) : v);
+            for (int q = 0; q < 4; ++q) {
+                const int co = co0 + nb * 32 + 8 * q + 4 * g;   // first of 4 channels
+                if (co >= a.Cout) continue;
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = acc[mb][nb][4 * q + e] + (a.bias ? a.bias[co + e] : 0.0f);
+                if (a.zout) {
+                    bf16x4 z;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) z[e] = (__bf16)v[e];
+                    *reinterpret_cast<bf16x4*>(a.zout + p * a.Cout + co) = z;
+                }
+                if (a.out) {
+                    bf16x4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[e] = (__bf16)(a.act ? silu(v[e]) : v[e]);
+                    *reinterpret_cast<bf16x4*>(a.out + p * a.out_cs + a.out_c0 + co) = o;
+                }
                 if (a.fout) {
-                    float* f = a.fout + p * a.f_cs + a.f_c0 + co;
-                    *f = a.f_accum ? *f + v : v;
+                    float4* f = reinterpret_cast<float4*>(a.fout + p * a.f_cs + a.f_c0 + co);
+                    float4 w = make_float4(v[0], v[1], v[2], v[3]);
+                    if (a.f_accum) {
+                        const float4 o = *f;
+                        w.x += o.x; w.y += o.y; w.z += o.z; w.w += o.w;
+                    }
+                    *f = w;
                 }
             }
     }
@@ -292,7 +312,7 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
                 for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[mb], Bm[nb],
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm[nb], A[mb],
                                                                              acc[mb][nb], 0, 0, 0);
             }
         }
@@ -356,7 +376,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
                 tap < 9 ? *reinterpret_cast<const bf16x8*>(
                               &sA[((prow + 2 * mb + dy) * HP + pcol + dx) * 8])
                         : zero8;
-            acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bm, acc[mb][0], 0, 0, 0);
+            acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm, A, acc[mb][0], 0, 0, 0);
         }
     }
     tile_epilogue<1>(a, acc, b, y0, x0, co0, wave, l32, g);
