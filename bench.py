@@ -5,7 +5,8 @@ rho_H/rho_L = 1000, mu_H/mu_L = 100, R = 16, W = 4, Eotvos number 10, hydrostati
 start; distributions stored in FP32 (the value), with FP16-shifted storage timed beside
 it (speed-up and the phi difference between the two after the same steps).  The D3Q19
 droplet impact on a film (256x256x128, both storages) is timed as a second block, and
-the learned 16-step surrogate (D2Q9 256^2 droplets) as a third: trained here on solver
+the D2Q9 Rayleigh-Taylor case (256x1024) as a third, and the learned 16-step surrogate
+(D2Q9 256^2 droplets) as a fourth: trained here on solver
 trajectories, then its held-out error, its forward/training rate against the BF16 MFMA
 peak, and its speed-up over 16 plain steps with the guard.
 
@@ -360,6 +361,21 @@ def main():
                 print(f"[bench] droplet_impact {st}: {r2['kernel_ms']:.4f} ms/step",
                       file=sys.stderr, flush=True)
             out["droplet_impact"] = blk
+            # D2Q9 Rayleigh-Taylor (256 x 1024, y walls): 38 MB of state per set, so the
+            # step runs largely from the 256 MB Infinity Cache; reported as effective rates
+            cfg3 = pfinputs.rayleigh_taylor()
+            n3 = 256 * 1024
+            blk = {"workload": "rayleigh_taylor D2Q9 256x1024 (x periodic, y walls, Atwood 0.5, "
+                               "g 1e-5, W 5, Re 3000)"}
+            for st in ("fp32", "fp16s"):
+                r3 = time_storage(cfg3, st, max(200, args.steps), args.warmup)
+                blk[st] = {"mlups": round(n3 / (r3["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r3["kernel_ms"], 5),
+                           "effective_GBs": round(BYTES_PER_SITE[("9", st)] * n3 /
+                                                  (r3["kernel_ms"] * 1e-3) / 1e9, 1)}
+                print(f"[bench] rayleigh_taylor {st}: {r3['kernel_ms']:.4f} ms/step",
+                      file=sys.stderr, flush=True)
+            out["rayleigh_taylor"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

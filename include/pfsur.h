@@ -8,7 +8,7 @@
  * and SiLU, 2x2 average pooling, nearest 2x upsampling with skip concatenation, and a
  * 1x1 head predicting the normalised residual).  Convolutions are implicit GEMMs on
  * BF16 MFMA with FP32 accumulation; weights are kept as FP32 masters with BF16 copies.
- * The plain lattice Boltzmann step is the fallback and the judge of the surrogate's
+ * The plain lattice Boltzmann step is the fallback and the reference for the surrogate's
  * error (pflb_advance_guarded).
  *
  * Conventions (as in pflb.h): device pointers unless stated "host"; the caller owns
