@@ -125,14 +125,18 @@ void derive(pflb_ctx* c) {
     const char* tenv = getenv("PFLB_TILE");
     if (tenv && atoi(tenv) >= 0 && atoi(tenv) <= 3) c->L.tile = atoi(tenv);
     // planes per workgroup: long z-marches (each chunk re-gathers two extra planes of h)
-    // with about two 4-wave workgroups per CU (8 one-wave workgroups for D2Q9); measured
-    // on the 256x256x128 droplet impact, 64 planes beat 32 and 16
+    // with about two 4-wave workgroups per CU (8 one-wave workgroups for D2Q9).  Measured:
+    // D3Q19 256x256x128 droplet impact, 64 planes beat 32 and 16 (and never below 8);
+    // D2Q9 256x1024 Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8), and a
+    // 256x256 domain runs best with 1: small 2-D domains need the parallelism more than
+    // they lose to the re-gathered planes
     const long cols = (long)((G.nx + 63) / 64) * (p.lattice == 19 ? (G.ny + 3) / 4 : 1);
     const long want_wgs = p.lattice == 19 ? 512 : 2048;
     long chunks = (want_wgs + cols - 1) / cols;
     if (chunks < 1) chunks = 1;
     long bz = (G.nz + chunks - 1) / chunks;
-    if (bz < 8) bz = 8;
+    const long bz_min = p.lattice == 19 ? 8 : 1;
+    if (bz < bz_min) bz = bz_min;
     if (bz > G.nz) bz = G.nz;
     const char* env = getenv("PFLB_BZ");
     if (env && atoi(env) > 0) bz = atoi(env);
