@@ -14,7 +14,8 @@
  * Conventions (as in pflb.h): device pointers unless stated "host"; the caller owns
  * activations, batches and workspaces; the library owns the weights and optimiser
  * state of a context.  Tensors are NHWC: [B][H][W][C], C fastest.  Returns 0 or a
- * negative PFLB_ERR_* code.
+ * negative PFLB_ERR_* code.  A context is not safe for concurrent calls from several
+ * host threads; calls on one stream are ordered.
  */
 #ifndef PFSUR_H
 #define PFSUR_H
@@ -112,7 +113,9 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
  *   lrr[batch]  host array of log10(rho_H/rho_L) per context
  *   work        pfsur_guard_work_bytes(cfg, batch) bytes of device memory, 256-aligned
  *   *n_fallback (host) number of (window, context) pairs that fell back.
- * Synchronous. */
+ * Synchronous.  If an error is returned part-way, each context holds a valid state (the
+ * one before or after its current window) but the windows done so far may differ
+ * between contexts. */
 size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch);
 int pflb_advance_guarded(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int windows,
                          const double* lrr, double mass_tol, double phi_tol, int check_every,

@@ -570,6 +570,7 @@ __global__ void __launch_bounds__(256) k_silu_bwd(const float* __restrict__ dact
     const int pb = blockIdx.x * ppb, pe = min(P, pb + ppb);
     float acc = 0.f;
     if (c < C)
+#pragma unroll 8
         for (int p = pb + r; p < pe; p += 8) {
             const size_t i = (size_t)p * C + c;
             const __bf16 d = (__bf16)(dact[(size_t)p * cs + c0 + c] * silu_grad((float)z[i]));
