@@ -404,3 +404,38 @@ def test_full_size_forward_matches_reference_and_batching(sur_mod):
     got = out32[:1].cpu().numpy()
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert rel <= 2e-2, rel
+
+
+def test_context_calls_reject_bad_arguments(sur_mod, tmp_path):
+    """Errors come back as codes with a message, before any device work: batch outside
+    [1, max_batch], a negative or non-finite learning rate, non-finite parameters, a
+    guarded advance on a lattice the surrogate does not fit, a foreign checkpoint."""
+    from paper_1812_00118_amd._lib import PflbError
+    s = sur_mod.Surrogate(16, 16, 2, NORM)
+    s.set_params(flat_params(U.init_weights(1)))
+    x = torch.zeros((3, 16, 16, U.IN_CH), dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros((3, 16, 16, U.OUT_CH), device="cuda")
+    with pytest.raises(PflbError, match="batch"):
+        s.forward(x)                                            # 3 > max_batch
+    with pytest.raises(PflbError, match="lr"):
+        s.train_step(x[:2], y[:2], -1.0)
+    with pytest.raises(PflbError, match="lr"):
+        s.train_step(x[:2], y[:2], float("nan"))
+    bad = flat_params(U.init_weights(1)).astype(np.float32)
+    bad[123] = np.inf
+    with pytest.raises(PflbError, match="non-finite"):
+        s.set_params(bad)
+    # the rejected calls left the parameters untouched
+    assert np.array_equal(s.get_params(), flat_params(U.init_weights(1)).astype(np.float32))
+    import pfinputs as I
+    from paper_1812_00118_amd import Sim
+    d3 = Sim(I.model_params(I.rising_bubble(n=16, R=4.0)))
+    with pytest.raises(PflbError, match="D2Q9"):
+        s.advance_guarded(d3, 1, 2.0)
+    d2 = Sim(I.model_params(I.drops(1, n=32)))                   # 32 x 32, not 16 x 16
+    with pytest.raises(PflbError, match="D2Q9"):
+        s.advance_guarded(d2, 1, 2.0)
+    junk = tmp_path / "junk.ck"
+    junk.write_bytes(b"not a checkpoint" * 8)
+    with pytest.raises(PflbError):
+        s.load(junk)
