@@ -213,20 +213,21 @@ struct SiteWriter<L, StoreF16S> {
     uint32_t site, S;
     const Codec& cd;
     double th;                     // h total (the site's phi)
-    double tg;                     // g total
-    double dh, dg;                 // sums of the decoded deviations (exact dyadic terms)
+    double dh;                     // sum of the decoded h deviations (exact dyadic terms)
+    float tg, dg;                  // g total and decoded g deviations: no total of the g
+                                   // set is conserved exactly, so float32 sums suffice
     float Rh0, Rg0;
     __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site_, uint32_t S_,
                                           const Codec& cd_, float th_, float th_lo_)
-        : b(b_), site(site_), S(S_), cd(cd_), th((double)th_ + (double)th_lo_), tg(0.0),
-          dh(0.0), dg(0.0), Rh0(0.f), Rg0(0.f) {}
+        : b(b_), site(site_), S(S_), cd(cd_), th((double)th_ + (double)th_lo_), dh(0.0),
+          tg(0.f), dg(0.f), Rh0(0.f), Rg0(0.f) {}
     __device__ __forceinline__ char* dev_addr(int i) const {
         return b + (size_t)S * 8 + (size_t)i * ((size_t)S * 4) + site * 4u;
     }
     template <int I>
     __device__ __forceinline__ void put(float h, float g) {
         static_assert(dyadic_refs_sum_to_four<L>(), "reference coefficients must sum to 4");
-        tg += (double)g;
+        tg += g;
         if constexpr (I == 0) {
             Rh0 = h * (1.0f / L::r(0));
             Rg0 = g * (1.0f / L::r(0));
@@ -234,19 +235,20 @@ struct SiteWriter<L, StoreF16S> {
             const __half qh = __float2half_rn((h - L::r(I) * Rh0) * cd.sh);
             const __half qg = __float2half_rn((g - L::r(I) * Rg0) * cd.sg);
             dh += (double)(__half2float(qh) * cd.ish);
-            dg += (double)(__half2float(qg) * cd.isg);
+            dg = fmaf(__half2float(qg), cd.isg, dg);
             store_nt(dev_addr(I), __halves2half2(qh, qg));
         }
     }
     // R from the float64 complement, and the rest word from what R's rounding left over
     __device__ __forceinline__ void finish() {
         const float Rh = (float)(0.25 * (th - dh));
-        const float Rg = (float)(0.25 * (tg - dg));
         const double resh = (th - dh) - 4.0 * (double)Rh;
-        const double resg = (tg - dg) - 4.0 * (double)Rg;
+        const float cg = tg - dg;
+        const float Rg = 0.25f * cg;
+        const float resg = fmaf(-4.0f, Rg, cg);
         store_nt(b + site * 8u, Rh, Rg);
         store_nt(dev_addr(0), __halves2half2(__float2half_rn((float)resh * cd.sh),
-                                             __float2half_rn((float)resg * cd.sg)));
+                                             __float2half_rn(resg * cd.sg)));
     }
 };
 
