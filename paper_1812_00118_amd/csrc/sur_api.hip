@@ -438,10 +438,14 @@ int pfsur_pack(pfsur_ctx* c, const float* phi, const float* P, const float* J, c
     if (!aligned16(x)) return fail(c, PFLB_ERR_ALIGN, "x must be 16-byte aligned");
     const size_t HW = (size_t)c->cfg.H * c->cfg.W;
     hipStream_t st = (hipStream_t)stream;
-    for (int b = 0; b < batch; ++b)
-        SUR_TRY(pack(phi + b * HW, P + b * HW, J + 2 * b * HW, (float)lrr[b], c->nm, HW,
-                     static_cast<__bf16*>(x) + b * HW * PFSUR_IN_CH, st),
+    for (int b0 = 0; b0 < batch; b0 += LRR_MAX) {
+        const int nb = std::min(LRR_MAX, batch - b0);
+        LrrTab tab;
+        for (int k = 0; k < LRR_MAX; ++k) tab.v[k] = k < nb ? (float)lrr[b0 + k] : 0.0f;
+        SUR_TRY(pack(phi + b0 * HW, P + b0 * HW, J + 2 * b0 * HW, tab, nb, c->nm, HW,
+                     static_cast<__bf16*>(x) + b0 * HW * PFSUR_IN_CH, st),
                 "pack");
+    }
     return PFLB_OK;
 }
 
@@ -532,6 +536,9 @@ struct GuardPlan {
     size_t phi, P, J, phi_lb, x, out, ws, recon, dpart, fpart, total;
 };
 
+// dpart holds the per-block sums before and after the prediction ([2][n][blocks]) and
+// fpart the per-block phi differences of checked windows ([n][blocks]), so that one
+// read-back per window serves every decision
 GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     GuardPlan g;
     const size_t HW = (size_t)cfg->H * cfg->W;
@@ -544,32 +551,15 @@ GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     g.phi = take(n * HW * 4);
     g.P = take(n * HW * 4);
     g.J = take(n * 2 * HW * 4);
-    g.phi_lb = take(HW * 4);
+    g.phi_lb = take(n * HW * 4);
     g.x = take(n * HW * PFSUR_IN_CH * 2);
     g.out = take(n * HW * PFSUR_OUT_CH * 4);
     g.ws = take(make_plan(cfg->H, cfg->W, n, false).total);
     g.recon = take((2 * 9 + 2) * HW * 4);
-    g.dpart = take((size_t)n * GUARD_BLOCKS * 8);
-    g.fpart = take(GUARD_BLOCKS * 4);
+    g.dpart = take((size_t)2 * n * GUARD_BLOCKS * 8);
+    g.fpart = take((size_t)n * GUARD_BLOCKS * 4);
     g.total = o;
     return g;
-}
-
-// per-sample sums of n fields of HW values, each a fixed-order host sum of per-block
-// partial sums (deterministic)
-int field_sums(pfsur_ctx* c, const float* a, int n, size_t HW, double* dpart, hipStream_t st,
-               std::vector<double>& res) {
-    for (int k = 0; k < n; ++k)
-        SUR_TRY(sum_field(a + k * HW, HW, dpart + (size_t)k * GUARD_BLOCKS, GUARD_BLOCKS, st),
-                "field sum");
-    std::vector<double> h((size_t)n * GUARD_BLOCKS);
-    SUR_TRY(hipMemcpyAsync(h.data(), dpart, h.size() * 8, hipMemcpyDeviceToHost, st),
-            "field sum read-back");
-    SUR_TRY(hipStreamSynchronize(st), "field sum read-back");
-    res.assign(n, 0.0);
-    for (int k = 0; k < n; ++k)
-        for (int b = 0; b < GUARD_BLOCKS; ++b) res[k] += h[(size_t)k * GUARD_BLOCKS + b];
-    return PFLB_OK;
 }
 
 }  // namespace
@@ -608,35 +598,51 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
     float* out = reinterpret_cast<float*>(w + g.out);
     double* dpart = reinterpret_cast<double*>(w + g.dpart);
     float* fpart = reinterpret_cast<float*>(w + g.fpart);
+    const size_t nb = (size_t)n * GUARD_BLOCKS;
+    std::vector<double> hd(2 * nb);
+    std::vector<float> hf(nb);
     *n_fallback = 0;
-    std::vector<double> s_in, s_out;
     for (int win = 0; win < windows; ++win) {
         int r;
         for (int k = 0; k < n; ++k)
             if ((r = pflb_read(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW, nullptr, st)))
                 return fail(c, r, std::string("lattice read: ") + pflb_last_error(lbs[k]));
-        if ((r = field_sums(c, phi, n, HW, dpart, st, s_in))) return r;
+        SUR_TRY(sum_field(phi, n, HW, dpart, GUARD_BLOCKS, st), "field sum");
         if ((r = pfsur_pack(c, phi, P, J, lrr, n, w + g.x, st))) return r;
         if ((r = run_forward(c, w + g.x, out, n, w + g.ws, false, st))) return r;
         if ((r = pfsur_apply(c, out, phi, P, J, n, st))) return r;
-        if ((r = field_sums(c, phi, n, HW, dpart, st, s_out))) return r;
+        SUR_TRY(sum_field(phi, n, HW, dpart + nb, GUARD_BLOCKS, st), "field sum");
         const bool checked = check_every > 0 && (win + 1) % check_every == 0;
-        for (int k = 0; k < n; ++k) {
-            double err = 0.0;
-            if (checked) {
-                // the plain steps from the same state are the reference; if the
-                // prediction is rejected they are the fallback already taken
+        if (checked) {
+            // the plain steps from the same states are the reference; if a prediction
+            // is rejected they are the fallback already taken
+            for (int k = 0; k < n; ++k) {
                 r = pflb_step(lbs[k], PFSUR_STEPS, st);
-                if (!r) r = pflb_read(lbs[k], phi_lb, nullptr, nullptr, nullptr, st);
+                if (!r) r = pflb_read(lbs[k], phi_lb + k * HW, nullptr, nullptr, nullptr, st);
                 if (r) return fail(c, r, std::string("lattice steps: ") + pflb_last_error(lbs[k]));
-                SUR_TRY(maxdiff(phi + k * HW, phi_lb, HW, fpart, GUARD_BLOCKS, st), "phi check");
-                float h[GUARD_BLOCKS];
-                SUR_TRY(hipMemcpyAsync(h, fpart, sizeof(h), hipMemcpyDeviceToHost, st), "phi check");
-                SUR_TRY(hipStreamSynchronize(st), "phi check");
-                for (int b = 0; b < GUARD_BLOCKS; ++b) err = h[b] > err || h[b] != h[b] ? h[b] : err;
+            }
+            SUR_TRY(maxdiff(phi, phi_lb, n, HW, fpart, GUARD_BLOCKS, st), "phi check");
+            SUR_TRY(hipMemcpyAsync(hf.data(), fpart, nb * 4, hipMemcpyDeviceToHost, st),
+                    "phi check");
+        }
+        SUR_TRY(hipMemcpyAsync(hd.data(), dpart, 2 * nb * 8, hipMemcpyDeviceToHost, st),
+                "field sums");
+        SUR_TRY(hipStreamSynchronize(st), "guard read-back");
+        for (int k = 0; k < n; ++k) {
+            // fixed-order host sums of the per-block partials (deterministic)
+            double s_in = 0.0, s_out = 0.0, err = 0.0;
+            for (int b = 0; b < GUARD_BLOCKS; ++b) {
+                s_in += hd[(size_t)k * GUARD_BLOCKS + b];
+                s_out += hd[nb + (size_t)k * GUARD_BLOCKS + b];
+            }
+            if (checked) {
+                for (int b = 0; b < GUARD_BLOCKS; ++b) {
+                    const float e = hf[(size_t)k * GUARD_BLOCKS + b];
+                    err = e > err || e != e ? e : err;
+                }
                 if (err != err) err = INFINITY;
             }
-            if (pfsur_guard_accept(s_in[k], s_out[k], mass_tol, checked, err, phi_tol)) {
+            if (pfsur_guard_accept(s_in, s_out, mass_tol, checked, err, phi_tol)) {
                 r = pflb_reconstruct(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW,
                                      reinterpret_cast<float*>(w + g.recon), checked ? 0 : PFSUR_STEPS,
                                      st);

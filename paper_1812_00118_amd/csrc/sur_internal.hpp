@@ -49,6 +49,12 @@ struct Norm {
     float shift[4], scale[4], out_scale[4], lrr_scale;
 };
 
+// per-sample log10 density ratios of one packing launch (at most LRR_MAX samples)
+constexpr int LRR_MAX = 64;
+struct LrrTab {
+    float v[LRR_MAX];
+};
+
 hipError_t conv3x3(const ConvP& a, hipStream_t st);
 hipError_t wgrad(const WgradP& a, hipStream_t st);
 int wgrad_nsplit(int B, int H, int W, int Cout, int Cin, int* per_split);
@@ -72,14 +78,15 @@ unsigned mse_blocks(size_t n);
 hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr, int t,
                 hipStream_t st);
 hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* wt, hipStream_t st);
-hipError_t pack(const float* phi, const float* P, const float* J, float lrr, const Norm& nm,
-                size_t HW, __bf16* x, hipStream_t st);
+hipError_t pack(const float* phi, const float* P, const float* J, const LrrTab& lrr, int B,
+                const Norm& nm, size_t HW, __bf16* x, hipStream_t st);
 hipError_t pack_target(const float* phi0, const float* P0, const float* J0, const float* phi1,
                        const float* P1, const float* J1, const Norm& nm, size_t HW, float* y,
                        hipStream_t st);
 hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi, float* P, float* J,
                  hipStream_t st);
-hipError_t maxdiff(const float* a, const float* b, size_t n, float* part, int nblk, hipStream_t st);
-hipError_t sum_field(const float* a, size_t n, double* part, int nblk, hipStream_t st);
+hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part, int nblk,
+                   hipStream_t st);
+hipError_t sum_field(const float* a, int B, size_t n, double* part, int nblk, hipStream_t st);
 
 }  // namespace pfsur

@@ -749,19 +749,22 @@ __global__ void k_weights_bf16(const float* __restrict__ w, int Cout, int Cin, _
     if (wt) wt[((size_t)ci * 9 + (8 - tap)) * Cout + co] = (__bf16)w[i];
 }
 
-// network input of one sample from solver fields: x[y, x, :] = ((phi - s0) k0,
-// (P - s1) k1, (Jx - s2) k2, (Jy - s3) k3, lrr lrr_scale, 0, 0, 0)
+// network input from solver fields, sample b = blockIdx.y of the batch:
+// x[b, y, x, :] = ((phi - s0) k0, (P - s1) k1, (Jx - s2) k2, (Jy - s3) k3,
+// lrr_b lrr_scale, 0, 0, 0)
 __global__ void k_pack(const float* __restrict__ phi, const float* __restrict__ P,
-                       const float* __restrict__ J, float lrr, Norm nm, size_t HW,
+                       const float* __restrict__ J, LrrTab lrr, Norm nm, size_t HW,
                        __bf16* __restrict__ x) {
     const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= HW) return;
-    const float f[4] = {phi[s], P[s], J[s], J[HW + s]};
+    const size_t b = blockIdx.y;
+    const size_t i = b * HW + s;
+    const float f[4] = {phi[i], P[i], J[2 * b * HW + s], J[(2 * b + 1) * HW + s]};
     bf16x8 v;
     for (int c = 0; c < 4; ++c) v[c] = (__bf16)((f[c] - nm.shift[c]) * nm.scale[c]);
-    v[4] = (__bf16)(lrr * nm.lrr_scale);
+    v[4] = (__bf16)(lrr.v[b] * nm.lrr_scale);
     v[5] = v[6] = v[7] = (__bf16)0.0f;
-    *reinterpret_cast<bf16x8*>(x + s * 8) = v;
+    *reinterpret_cast<bf16x8*>(x + i * 8) = v;
 }
 
 // training target of one sample: y[s, c] = (f1_c - f0_c) / out_scale[c]
@@ -790,36 +793,40 @@ __global__ void k_apply(const float* __restrict__ out, Norm nm, int B, size_t HW
     J[(b * 2 + 1) * HW + s] += out[i * 4 + 3] * nm.out_scale[3];
 }
 
-// max |a - b| per block (for the surrogate-vs-solver check)
+// max |a - b| per block for sample blockIdx.y of a batch of fields of n values:
+// part[sample][block]
 __global__ void __launch_bounds__(256) k_maxdiff(const float* __restrict__ a, const float* __restrict__ b,
                                                  size_t n, float* __restrict__ part) {
-    __shared__ float s[256];
+    __shared__ float sred[256];
+    const size_t off = (size_t)blockIdx.y * n;
     float m = 0.f;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-        m = fmaxf(m, fabsf(a[i] - b[i]));
-    s[threadIdx.x] = m;
+        m = fmaxf(m, fabsf(a[off + i] - b[off + i]));
+    sred[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < (unsigned)w) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
+        if (threadIdx.x < (unsigned)w) sred[threadIdx.x] = fmaxf(sred[threadIdx.x], sred[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sred[0];
 }
 
-// sum of a float field in float64, per block
+// sum of a float field in float64, per block, for sample blockIdx.y of a batch of
+// fields of n values: part[sample][block]
 __global__ void __launch_bounds__(256) k_sum_field(const float* __restrict__ a, size_t n,
                                                    double* __restrict__ part) {
-    __shared__ double s[256];
+    __shared__ double sred[256];
+    const size_t off = (size_t)blockIdx.y * n;
     double m = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-        m += (double)a[i];
-    s[threadIdx.x] = m;
+        m += (double)a[off + i];
+    sred[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+        if (threadIdx.x < (unsigned)w) sred[threadIdx.x] += sred[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sred[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -964,9 +971,9 @@ hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* w
     return hipGetLastError();
 }
 
-hipError_t pack(const float* phi, const float* P, const float* J, float lrr, const Norm& nm,
-                size_t HW, __bf16* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack, dim3(blocks(HW)), dim3(256), 0, st, phi, P, J, lrr, nm, HW, x);
+hipError_t pack(const float* phi, const float* P, const float* J, const LrrTab& lrr, int B,
+                const Norm& nm, size_t HW, __bf16* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3(blocks(HW), B), dim3(256), 0, st, phi, P, J, lrr, nm, HW, x);
     return hipGetLastError();
 }
 
@@ -985,13 +992,25 @@ hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi,
     return hipGetLastError();
 }
 
-hipError_t maxdiff(const float* a, const float* b, size_t n, float* part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_maxdiff, dim3(nblk), dim3(256), 0, st, a, b, n, part);
+// grid y is at most 65535: larger batches take several launches
+constexpr int MAX_GRID_Y = 65535;
+
+hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part, int nblk,
+                   hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += MAX_GRID_Y) {
+        const int nb = B - b0 < MAX_GRID_Y ? B - b0 : MAX_GRID_Y;
+        hipLaunchKernelGGL(k_maxdiff, dim3(nblk, nb), dim3(256), 0, st, a + b0 * n, b + b0 * n, n,
+                           part + (size_t)b0 * nblk);
+    }
     return hipGetLastError();
 }
 
-hipError_t sum_field(const float* a, size_t n, double* part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_field, dim3(nblk), dim3(256), 0, st, a, n, part);
+hipError_t sum_field(const float* a, int B, size_t n, double* part, int nblk, hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += MAX_GRID_Y) {
+        const int nb = B - b0 < MAX_GRID_Y ? B - b0 : MAX_GRID_Y;
+        hipLaunchKernelGGL(k_sum_field, dim3(nblk, nb), dim3(256), 0, st, a + b0 * n, n,
+                           part + (size_t)b0 * nblk);
+    }
     return hipGetLastError();
 }
 
