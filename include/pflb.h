@@ -143,9 +143,10 @@ int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const floa
 
 /* Replace the state by the equilibria of given macroscopic fields (a hand-over from
  * another model of the same flow, e.g. a learned surrogate): u = J / rho' with rho' the
- * density read-out divides by, then pflb_equilibrium and the state load of
- * pflb_init_fields.  Reading back returns phi, P and J up to FP32 rounding.
- *   phi [N], P [N] (NULL: zero), J [D][N]; work: (2*Q + D)*N floats of device memory.
+ * density read-out divides by, then the equilibria of pflb_equilibrium and the state
+ * load of pflb_init_fields.  Reading back returns phi, P and J up to FP32 rounding.
+ *   phi [N], P [N] (NULL: zero), J [D][N]; work: 2*Q*N floats of device memory (the
+ *   (2*Q + D)*N floats earlier versions asked for remain enough).
  * The step counter is kept and increased by `advance` (>= 0), the number of steps the
  * given fields lie ahead of the current state. */
 int pflb_reconstruct(pflb_ctx* ctx, const float* phi, const float* P, const float* J,

@@ -287,20 +287,8 @@ int pflb_init_fields(pflb_ctx* c, const float* phi, const float* u, const float*
 
 int pflb_reconstruct(pflb_ctx* c, const float* phi, const float* P, const float* J, float* work,
                      int advance, void* stream) {
-    int r = need_bound(c);
-    if (r) return r;
-    if (!phi || !J || !work) return fail(c, PFLB_ERR_PARAM, "NULL field or work pointer");
-    if (advance < 0) return fail(c, PFLB_ERR_PARAM, "advance < 0");
-    Launch a = c->L;
-    a.stream = (hipStream_t)stream;
-    float* u = work + (size_t)2 * c->Q * c->N;
-    hipError_t e = launch_u_from_j(a, c->N, phi, J, u);
-    if (e != hipSuccess) return hip_fail(c, e, "u_from_j launch");
-    const long long steps = c->steps;
-    r = pflb_init_fields(c, phi, u, P, work, stream);
-    if (r) return r;
-    c->steps = steps + advance;
-    return PFLB_OK;
+    if (!c) return PFLB_ERR_PARAM;
+    return pflb_reconstruct_many(&c, 1, &phi, &P, &J, work, advance, (hipStream_t)stream);
 }
 
 int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
@@ -427,5 +415,93 @@ int pflb_ctx_info(const pflb_ctx* c, CtxInfo* out) {
     for (int a = 0; a < 3; ++a) out->bc[a] = c->p.bc[a];
     out->N = c->N;
     out->bound = c->bound;
+    return PFLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched read-out and hand-over (library-internal, used by the surrogate's guard)
+// ---------------------------------------------------------------------------
+namespace {
+
+// contexts of one batched launch must be bound and share lattice, storage and geometry
+int check_many(pflb_ctx* const* c, int n) {
+    if (!c || n < 1 || !c[0]) return PFLB_ERR_PARAM;
+    for (int k = 0; k < n; ++k) {
+        if (!c[k]) return fail(c[0], PFLB_ERR_PARAM, "NULL context in a batch");
+        if (!c[k]->bound) return fail(c[0], PFLB_ERR_UNBOUND, "context in a batch is not bound");
+        const Launch& a = c[0]->L;
+        const Launch& b = c[k]->L;
+        if (b.q != a.q || b.half != a.half || b.G.nx != a.G.nx || b.G.ny != a.G.ny ||
+            b.G.nz != a.G.nz || b.G.wx != a.G.wx || b.G.wy != a.G.wy || b.G.wz != a.G.wz)
+            return fail(c[0], PFLB_ERR_PARAM,
+                        "contexts of a batch must share lattice, storage, sizes and walls");
+    }
+    return PFLB_OK;
+}
+
+}  // namespace
+
+int pflb_read_many(pflb_ctx* const* c, int n, float* const* phi, float* const* P,
+                   float* const* J, hipStream_t st) {
+    int r = check_many(c, n);
+    if (r) return r;
+    if (!phi) return fail(c[0], PFLB_ERR_PARAM, "phi outputs are required");
+    for (int k0 = 0; k0 < n; k0 += BATCH_MAX) {
+        const int nb = n - k0 < BATCH_MAX ? n - k0 : BATCH_MAX;
+        Batch bt;
+        memset(&bt, 0, sizeof(bt));
+        bool macro = false;
+        for (int j = 0; j < nb; ++j) {
+            pflb_ctx* ck = c[k0 + j];
+            BatchEnt& e = bt.e[j];
+            if (!phi[k0 + j]) return fail(c[0], PFLB_ERR_PARAM, "phi outputs are required");
+            e.state = static_cast<char*>(state(ck));
+            e.phi = phi[k0 + j];
+            e.P = P ? P[k0 + j] : nullptr;
+            e.J = J ? J[k0 + j] : nullptr;
+            e.m = ck->L.m;
+            e.cd = ck->L.cd;
+            macro = macro || e.P || e.J;
+        }
+        Launch a = c[k0]->L;
+        a.stream = st;
+        hipError_t e = launch_read_batch(a, c[0]->N, bt, nb, macro);
+        if (e != hipSuccess) return hip_fail(c[0], e, "batched read launch");
+    }
+    return PFLB_OK;
+}
+
+int pflb_reconstruct_many(pflb_ctx* const* c, int n, const float* const* phi,
+                          const float* const* P, const float* const* J, float* work, int advance,
+                          hipStream_t st) {
+    int r = check_many(c, n);
+    if (r) return r;
+    if (!phi || !J || !work) return fail(c[0], PFLB_ERR_PARAM, "NULL field or work pointer");
+    if (advance < 0) return fail(c[0], PFLB_ERR_PARAM, "advance < 0");
+    const size_t per = (size_t)2 * c[0]->Q * c[0]->N;   // floats of work per context
+    for (int k0 = 0; k0 < n; k0 += BATCH_MAX) {
+        const int nb = n - k0 < BATCH_MAX ? n - k0 : BATCH_MAX;
+        Batch bt;
+        memset(&bt, 0, sizeof(bt));
+        for (int j = 0; j < nb; ++j) {
+            pflb_ctx* ck = c[k0 + j];
+            if (!phi[k0 + j] || !J[k0 + j])
+                return fail(c[0], PFLB_ERR_PARAM, "NULL field or work pointer");
+            ck->cur = 0;   // the hand-over fills the first state buffer
+            BatchEnt& e = bt.e[j];
+            e.state = static_cast<char*>(state(ck));
+            e.phi = const_cast<float*>(phi[k0 + j]);
+            e.P = P ? const_cast<float*>(P[k0 + j]) : nullptr;
+            e.J = const_cast<float*>(J[k0 + j]);
+            e.work = work + (size_t)j * per;
+            e.m = ck->L.m;
+            e.cd = ck->L.cd;
+        }
+        Launch a = c[k0]->L;
+        a.stream = st;
+        hipError_t e = launch_reconstruct_batch(a, c[0]->N, bt, nb);
+        if (e != hipSuccess) return hip_fail(c[0], e, "batched hand-over launch");
+        for (int j = 0; j < nb; ++j) c[k0 + j]->steps += advance;
+    }
     return PFLB_OK;
 }

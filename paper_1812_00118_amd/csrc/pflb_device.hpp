@@ -123,6 +123,23 @@ struct Codec {                // FP16S: power-of-two scales of the fp16 deviatio
     float sh, ish, sg, isg;
 };
 
+// One context of a batched launch.  Read-out: phi (and P, J when not NULL) are outputs.
+// Hand-over: phi, J and P (NULL: 0) are inputs and work holds the context's equilibria
+// (h then g, Q N floats each) between the two kernels.
+struct BatchEnt {
+    char* state;
+    float* phi;
+    float* P;
+    float* J;
+    float* work;
+    Model m;
+    Codec cd;
+};
+constexpr int BATCH_MAX = 16;
+struct Batch {
+    BatchEnt e[BATCH_MAX];
+};
+
 // ---------------------------------------------------------------------------
 // storage codecs.  One state buffer holds both sets, interleaved per population so
 // that one load brings h_i and g_i of a slot:

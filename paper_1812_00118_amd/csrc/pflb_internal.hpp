@@ -23,8 +23,6 @@ struct Launch {
 hipError_t launch_step(const Launch& a, const void* src, void* dst);
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
                               const float* P, float* h, float* g);
-hipError_t launch_u_from_j(const Launch& a, uint32_t N, const float* phi, const float* J,
-                          float* u);
 hipError_t launch_set_state(const Launch& a, uint32_t N, const float* h, const float* g,
                             void* b);
 hipError_t launch_get_state(const Launch& a, uint32_t N, const void* b, float* h, float* g);
@@ -32,6 +30,12 @@ hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, f
                        float* J, float* U);
 hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch);
 size_t state_bytes(int q, bool half, uint32_t S);
+
+// Batched launches over contexts that share the lattice, the storage and the geometry
+// (blockIdx.y = context); per-context pointers and constants go by value in the kernel
+// arguments, at most BATCH_MAX contexts per launch.
+hipError_t launch_read_batch(const Launch& a, uint32_t N, const Batch& bt, int n, bool macro);
+hipError_t launch_reconstruct_batch(const Launch& a, uint32_t N, const Batch& bt, int n);
 
 // shape of a context as the user gave it (nx, ny, nz, bc), for the surrogate hand-over
 struct CtxInfo {
@@ -48,3 +52,15 @@ size_t mass_flag_offset();
 
 struct pflb_ctx;
 int pflb_ctx_info(const ::pflb_ctx* c, pflb::CtxInfo* out);
+
+// Read-out of n contexts that share lattice, storage, sizes and walls, one launch per
+// BATCH_MAX of them: context k writes phi[k] and, where the arrays and entries are not
+// NULL, P[k] and J[k] (layouts as pflb_read).  Errors are reported on c[0].
+int pflb_read_many(::pflb_ctx* const* c, int n, float* const* phi, float* const* P,
+                   float* const* J, hipStream_t st);
+// Hand-over of n such contexts from (phi[k], P[k] (NULL: 0), J[k]) as pflb_reconstruct
+// does for one; work holds 2 Q N floats for each of min(n, BATCH_MAX) contexts.  Each
+// context keeps its step count, increased by advance.
+int pflb_reconstruct_many(::pflb_ctx* const* c, int n, const float* const* phi,
+                          const float* const* P, const float* const* J, float* work, int advance,
+                          hipStream_t st);

@@ -1,10 +1,11 @@
 // HIP kernels of the phase-field lattice Boltzmann library (gfx950).
 //
 //   k_step         one fused pull-stream + collide pass for both sets (Eqs. 1, 10)
-//   k_equilibrium  pre-collision equilibria from (phi, u, P)
+//   k_equilibrium  pre-collision equilibria from (phi, u, P); *_j_b: from (phi, J, P)
 //   k_set_state    pre-collision distributions -> pull storage
 //   k_get_state    pull storage -> pre-collision distributions
 //   k_phi, k_macro read-out of phi, P, J, u (end of Section 2)
+//   *_b            the same over a batch of contexts (blockIdx.y = context)
 //   k_mass_*       deterministic float64 sum of phi and non-finite flag
 #include "pflb_device.hpp"
 #include "pflb_internal.hpp"
@@ -155,15 +156,33 @@ __device__ __forceinline__ int user_axis(int a) {
 }
 
 // ---------------------------------------------------------------------------
-// equilibrium start
+// equilibrium start and hand-over.  Each kernel body is a per-site function, called by
+// a single-context kernel (parameters by value) and by a batched kernel whose
+// blockIdx.y picks one context of a Batch (same lattice, storage and geometry).
 // ---------------------------------------------------------------------------
+
+// 1 / rho' with rho' = rho + beta rho_dif lap(phi) / 4: the density read-out divides the
+// momentum by, so a hand-over of macroscopic fields takes u = J / rho'
 template <class L>
-__global__ void __launch_bounds__(256)
-k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
-              const float* __restrict__ u, const float* __restrict__ P,
-              float* __restrict__ h, float* __restrict__ g) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= N) return;
+__device__ __forceinline__ float inv_rho_prime(const Model& m, const float (&pn)[L::Q]) {
+    float ls = 0.f;
+    static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i & 1) ls = fmaf(L::w(i), (pn[i] - pn[0]) + (pn[i + 1] - pn[0]), ls);
+    });
+    const float rho = fmaf(pn[0], m.rho_dif, m.rho_L);
+    return 1.0f / fmaf(m.beta * 0.25f * m.rho_dif, 6.0f * ls, rho);
+}
+
+// pre-collision equilibria of site s from phi, P (NULL: 0) and the velocity, given as
+// u or (u == NULL) as the momentum J
+template <class L>
+__device__ __forceinline__ void equilibrium_site(const Geom& G, const Model& m, uint32_t N,
+                                                 uint32_t s, const float* __restrict__ phi,
+                                                 const float* __restrict__ u,
+                                                 const float* __restrict__ J,
+                                                 const float* __restrict__ P,
+                                                 float* __restrict__ h, float* __restrict__ g) {
     int x, y, z;
     site_coords(G, s, x, y, z);
     float pn[L::Q];
@@ -173,7 +192,12 @@ k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
     static_for<0, L::Q>([&](auto I) { zero[decltype(I)::value] = 0.0f; });
     Macro a = macros<L>(m, pn, zero);
     float uu[3] = {0.f, 0.f, 0.f};
-    for (int c = 0; c < L::D; ++c) uu[user_axis<L>(c)] = u[(size_t)c * N + s];
+    if (u) {
+        for (int c = 0; c < L::D; ++c) uu[user_axis<L>(c)] = u[(size_t)c * N + s];
+    } else {
+        const float irp = inv_rho_prime<L>(m, pn);
+        for (int c = 0; c < L::D; ++c) uu[user_axis<L>(c)] = J[(size_t)c * N + s] * irp;
+    }
     a.ux = uu[0]; a.uy = uu[1]; a.uz = uu[2];
     a.P = P ? P[s] : 0.0f;
     const EqTerms t = eq_terms(m, a);
@@ -187,26 +211,24 @@ k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
     });
 }
 
-// velocity from momentum for a hand-over of macroscopic fields: u = J / rho' with
-// rho' = rho + beta rho_dif lap(phi) / 4, the density that read-out divides by
 template <class L>
 __global__ void __launch_bounds__(256)
-k_u_from_j(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
-           const float* __restrict__ J, float* __restrict__ u) {
+k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
+              const float* __restrict__ u, const float* __restrict__ P,
+              float* __restrict__ h, float* __restrict__ g) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
-    int x, y, z;
-    site_coords(G, s, x, y, z);
-    float pn[L::Q];
-    phi_stencil<L>(G, phi, x, y, z, pn);
-    float ls = 0.f;
-    static_for<1, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (i & 1) ls = fmaf(L::w(i), (pn[i] - pn[0]) + (pn[i + 1] - pn[0]), ls);
-    });
-    const float rho = fmaf(pn[0], m.rho_dif, m.rho_L);
-    const float irp = 1.0f / fmaf(m.beta * 0.25f * m.rho_dif, 6.0f * ls, rho);
-    for (int c = 0; c < L::D; ++c) u[(size_t)c * N + s] = J[(size_t)c * N + s] * irp;
+    equilibrium_site<L>(G, m, N, s, phi, u, nullptr, P, h, g);
+}
+
+// hand-over: equilibria from (phi, P, J) of context blockIdx.y into its work (h, then g)
+template <class L>
+__global__ void __launch_bounds__(256) k_equilibrium_j_b(Geom G, uint32_t N, Batch bt) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    const BatchEnt& e = bt.e[blockIdx.y];
+    equilibrium_site<L>(G, e.m, N, s, e.phi, nullptr, e.J, e.P, e.work,
+                        e.work + (size_t)L::Q * N);
 }
 
 // ---------------------------------------------------------------------------
@@ -215,11 +237,10 @@ k_u_from_j(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
 // otherwise by y itself as population opp(j)
 // ---------------------------------------------------------------------------
 template <class L, class ST>
-__global__ void __launch_bounds__(256)
-k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
-            const float* __restrict__ g, char* __restrict__ b) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= N) return;
+__device__ __forceinline__ void set_state_site(const Geom& G, const Codec& cd, uint32_t N,
+                                               uint32_t s, const float* __restrict__ h,
+                                               const float* __restrict__ g,
+                                               char* __restrict__ b) {
     int x, y, z;
     site_coords(G, s, x, y, z);
     float fh[L::Q], fg[L::Q];
@@ -239,6 +260,24 @@ k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
         }
     });
     encode_site<L, ST>(b, s, G.S, fh, fg, cd);
+}
+
+template <class L, class ST>
+__global__ void __launch_bounds__(256)
+k_set_state(Geom G, Codec cd, uint32_t N, const float* __restrict__ h,
+            const float* __restrict__ g, char* __restrict__ b) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    set_state_site<L, ST>(G, cd, N, s, h, g, b);
+}
+
+// hand-over: the work equilibria of context blockIdx.y into its state buffer
+template <class L, class ST>
+__global__ void __launch_bounds__(256) k_set_state_b(Geom G, uint32_t N, Batch bt) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    const BatchEnt& e = bt.e[blockIdx.y];
+    set_state_site<L, ST>(G, e.cd, N, s, e.work, e.work + (size_t)L::Q * N, e.state);
 }
 
 template <class L, class ST, int WALLS>
@@ -262,23 +301,20 @@ k_get_state(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __r
 // read-out
 // ---------------------------------------------------------------------------
 template <class L, class ST, int WALLS>
-__global__ void __launch_bounds__(256)
-k_phi(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __restrict__ phi) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= N) return;
+__device__ __forceinline__ void phi_site(const Geom& G, const Codec& cd, uint32_t s,
+                                         const char* __restrict__ b, float* __restrict__ phi) {
     int x, y, z;
     site_coords(G, s, x, y, z);
     float f[L::Q];
     phi[s] = (float)pull_site_h<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, f);
 }
 
+// P, J and u of site s (each output may be NULL) from the state and the phi field
 template <class L, class ST, int WALLS>
-__global__ void __launch_bounds__(256)
-k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ b,
-        const float* __restrict__ phi, float* __restrict__ P, float* __restrict__ J,
-        float* __restrict__ U) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
-    if (s >= N) return;
+__device__ __forceinline__ void macro_site(const Geom& G, const Model& m, const Codec& cd,
+                                           uint32_t N, uint32_t s, const char* __restrict__ b,
+                                           const float* __restrict__ phi, float* __restrict__ P,
+                                           float* __restrict__ J, float* __restrict__ U) {
     int x, y, z;
     site_coords(G, s, x, y, z);
     float pn[L::Q], hv[L::Q], gv[L::Q];
@@ -292,6 +328,40 @@ k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ b,
         if (J) J[(size_t)c * N + s] = jv[user_axis<L>(c)];
         if (U) U[(size_t)c * N + s] = uv[user_axis<L>(c)];
     }
+}
+
+template <class L, class ST, int WALLS>
+__global__ void __launch_bounds__(256)
+k_phi(Geom G, Codec cd, uint32_t N, const char* __restrict__ b, float* __restrict__ phi) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    phi_site<L, ST, WALLS>(G, cd, s, b, phi);
+}
+
+template <class L, class ST, int WALLS>
+__global__ void __launch_bounds__(256)
+k_macro(Geom G, Model m, Codec cd, uint32_t N, const char* __restrict__ b,
+        const float* __restrict__ phi, float* __restrict__ P, float* __restrict__ J,
+        float* __restrict__ U) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    macro_site<L, ST, WALLS>(G, m, cd, N, s, b, phi, P, J, U);
+}
+
+template <class L, class ST, int WALLS>
+__global__ void __launch_bounds__(256) k_phi_b(Geom G, uint32_t N, Batch bt) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    const BatchEnt& e = bt.e[blockIdx.y];
+    phi_site<L, ST, WALLS>(G, e.cd, s, e.state, e.phi);
+}
+
+template <class L, class ST, int WALLS>
+__global__ void __launch_bounds__(256) k_macro_b(Geom G, uint32_t N, Batch bt) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    const BatchEnt& e = bt.e[blockIdx.y];
+    macro_site<L, ST, WALLS>(G, e.m, e.cd, N, s, e.state, e.phi, e.P, e.J, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,15 +514,21 @@ hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, con
                      : equilibrium_t<LatD2Q9>(a, N, phi, u, P, h, g);
 }
 
-hipError_t launch_u_from_j(const Launch& a, uint32_t N, const float* phi, const float* J,
-                          float* u) {
-    if (a.q == 19)
-        hipLaunchKernelGGL((k_u_from_j<LatD3Q19>), grid1(N), dim3(256), 0, a.stream, a.G, a.m, N,
-                           phi, J, u);
-    else
-        hipLaunchKernelGGL((k_u_from_j<LatD2Q9>), grid1(N), dim3(256), 0, a.stream, a.G, a.m, N,
-                           phi, J, u);
+template <class L, class ST>
+static hipError_t reconstruct_batch_t(const Launch& a, uint32_t N, const Batch& bt, int n) {
+    const dim3 grid((N + 255u) / 256u, n);
+    hipLaunchKernelGGL((k_equilibrium_j_b<L>), grid, dim3(256), 0, a.stream, a.G, N, bt);
+    hipLaunchKernelGGL((k_set_state_b<L, ST>), grid, dim3(256), 0, a.stream, a.G, N, bt);
     return hipGetLastError();
+}
+
+hipError_t launch_reconstruct_batch(const Launch& a, uint32_t N, const Batch& bt, int n) {
+    if (n < 1 || n > BATCH_MAX) return hipErrorInvalidValue;
+    if (a.q == 19)
+        return a.half ? reconstruct_batch_t<LatD3Q19, StoreF16S>(a, N, bt, n)
+                      : reconstruct_batch_t<LatD3Q19, StoreF32>(a, N, bt, n);
+    return a.half ? reconstruct_batch_t<LatD2Q9, StoreF16S>(a, N, bt, n)
+                  : reconstruct_batch_t<LatD2Q9, StoreF32>(a, N, bt, n);
 }
 
 template <class L, class ST>
@@ -518,6 +594,30 @@ hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, f
                       : read_w<LatD3Q19, StoreF32>(a, N, b, phi, P, J, U);
     return a.half ? read_w<LatD2Q9, StoreF16S>(a, N, b, phi, P, J, U)
                   : read_w<LatD2Q9, StoreF32>(a, N, b, phi, P, J, U);
+}
+
+template <class L, class ST, int WALLS>
+static hipError_t read_batch_t(const Launch& a, uint32_t N, const Batch& bt, int n, bool macro) {
+    const dim3 grid((N + 255u) / 256u, n);
+    hipLaunchKernelGGL((k_phi_b<L, ST, WALLS>), grid, dim3(256), 0, a.stream, a.G, N, bt);
+    if (macro)
+        hipLaunchKernelGGL((k_macro_b<L, ST, WALLS>), grid, dim3(256), 0, a.stream, a.G, N, bt);
+    return hipGetLastError();
+}
+
+template <class L, class ST>
+static hipError_t read_batch_w(const Launch& a, uint32_t N, const Batch& bt, int n, bool macro) {
+    if (wallset(a.G)) return read_batch_t<L, ST, WALLS_XYZ>(a, N, bt, n, macro);
+    return read_batch_t<L, ST, WALLS_NONE>(a, N, bt, n, macro);
+}
+
+hipError_t launch_read_batch(const Launch& a, uint32_t N, const Batch& bt, int n, bool macro) {
+    if (n < 1 || n > BATCH_MAX) return hipErrorInvalidValue;
+    if (a.q == 19)
+        return a.half ? read_batch_w<LatD3Q19, StoreF16S>(a, N, bt, n, macro)
+                      : read_batch_w<LatD3Q19, StoreF32>(a, N, bt, n, macro);
+    return a.half ? read_batch_w<LatD2Q9, StoreF16S>(a, N, bt, n, macro)
+                  : read_batch_w<LatD2Q9, StoreF32>(a, N, bt, n, macro);
 }
 
 template <class L, class ST>

@@ -555,7 +555,7 @@ GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     g.x = take(n * HW * PFSUR_IN_CH * 2);
     g.out = take(n * HW * PFSUR_OUT_CH * 4);
     g.ws = take(make_plan(cfg->H, cfg->W, n, false).total);
-    g.recon = take((2 * 9 + 2) * HW * 4);
+    g.recon = take((size_t)std::min(n, pflb::BATCH_MAX) * 2 * 9 * HW * 4);
     g.dpart = take((size_t)2 * n * GUARD_BLOCKS * 8);
     g.fpart = take((size_t)n * GUARD_BLOCKS * 4);
     g.total = o;
@@ -601,12 +601,24 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
     const size_t nb = (size_t)n * GUARD_BLOCKS;
     std::vector<double> hd(2 * nb);
     std::vector<float> hf(nb);
+    // per-context field pointers of the batched read-out and hand-over
+    std::vector<float*> fphi(n), fP(n), fJ(n), flb(n);
+    for (int k = 0; k < n; ++k) {
+        fphi[k] = phi + k * HW;
+        fP[k] = P + k * HW;
+        fJ[k] = J + 2 * k * HW;
+        flb[k] = phi_lb + k * HW;
+    }
+    std::vector<pflb_ctx*> acc_ctx;
+    std::vector<const float*> acc_phi, acc_P, acc_J;
+    auto lb_fail = [&](int r, pflb_ctx* lc, const char* what) {
+        return fail(c, r, std::string(what) + pflb_last_error(lc));
+    };
     *n_fallback = 0;
     for (int win = 0; win < windows; ++win) {
         int r;
-        for (int k = 0; k < n; ++k)
-            if ((r = pflb_read(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW, nullptr, st)))
-                return fail(c, r, std::string("lattice read: ") + pflb_last_error(lbs[k]));
+        if ((r = pflb_read_many(lbs, n, fphi.data(), fP.data(), fJ.data(), st)))
+            return lb_fail(r, lbs[0], "lattice read: ");
         SUR_TRY(sum_field(phi, n, HW, dpart, GUARD_BLOCKS, st), "field sum");
         if ((r = pfsur_pack(c, phi, P, J, lrr, n, w + g.x, st))) return r;
         if ((r = run_forward(c, w + g.x, out, n, w + g.ws, false, st))) return r;
@@ -616,11 +628,11 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if (checked) {
             // the plain steps from the same states are the reference; if a prediction
             // is rejected they are the fallback already taken
-            for (int k = 0; k < n; ++k) {
-                r = pflb_step(lbs[k], PFSUR_STEPS, st);
-                if (!r) r = pflb_read(lbs[k], phi_lb + k * HW, nullptr, nullptr, nullptr, st);
-                if (r) return fail(c, r, std::string("lattice steps: ") + pflb_last_error(lbs[k]));
-            }
+            for (int k = 0; k < n; ++k)
+                if ((r = pflb_step(lbs[k], PFSUR_STEPS, st)))
+                    return lb_fail(r, lbs[k], "lattice steps: ");
+            if ((r = pflb_read_many(lbs, n, flb.data(), nullptr, nullptr, st)))
+                return lb_fail(r, lbs[0], "lattice read: ");
             SUR_TRY(maxdiff(phi, phi_lb, n, HW, fpart, GUARD_BLOCKS, st), "phi check");
             SUR_TRY(hipMemcpyAsync(hf.data(), fpart, nb * 4, hipMemcpyDeviceToHost, st),
                     "phi check");
@@ -628,6 +640,10 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         SUR_TRY(hipMemcpyAsync(hd.data(), dpart, 2 * nb * 8, hipMemcpyDeviceToHost, st),
                 "field sums");
         SUR_TRY(hipStreamSynchronize(st), "guard read-back");
+        acc_ctx.clear();
+        acc_phi.clear();
+        acc_P.clear();
+        acc_J.clear();
         for (int k = 0; k < n; ++k) {
             // fixed-order host sums of the per-block partials (deterministic)
             double s_in = 0.0, s_out = 0.0, err = 0.0;
@@ -643,16 +659,22 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
                 if (err != err) err = INFINITY;
             }
             if (pfsur_guard_accept(s_in, s_out, mass_tol, checked, err, phi_tol)) {
-                r = pflb_reconstruct(lbs[k], phi + k * HW, P + k * HW, J + 2 * k * HW,
-                                     reinterpret_cast<float*>(w + g.recon), checked ? 0 : PFSUR_STEPS,
-                                     st);
-                if (r) return fail(c, r, std::string("hand-over: ") + pflb_last_error(lbs[k]));
+                acc_ctx.push_back(lbs[k]);
+                acc_phi.push_back(fphi[k]);
+                acc_P.push_back(fP[k]);
+                acc_J.push_back(fJ[k]);
             } else {
                 *n_fallback += 1;
                 if (!checked && (r = pflb_step(lbs[k], PFSUR_STEPS, st)))
-                    return fail(c, r, std::string("fallback steps: ") + pflb_last_error(lbs[k]));
+                    return lb_fail(r, lbs[k], "fallback steps: ");
             }
         }
+        if (!acc_ctx.empty() &&
+            (r = pflb_reconstruct_many(acc_ctx.data(), (int)acc_ctx.size(), acc_phi.data(),
+                                             acc_P.data(), acc_J.data(),
+                                             reinterpret_cast<float*>(w + g.recon),
+                                             checked ? 0 : PFSUR_STEPS, st)))
+            return lb_fail(r, acc_ctx[0], "hand-over: ");
     }
     SUR_TRY(hipStreamSynchronize(st), "guarded advance");
     return PFLB_OK;

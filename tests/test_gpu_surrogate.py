@@ -380,6 +380,31 @@ def test_batched_guard_matches_single_context_guard(sur_mod):
         assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
 
 
+def test_batched_guard_over_more_contexts_than_one_launch_holds(sur_mod):
+    """17 contexts take two launches of the batched read-out and hand-over (at most 16
+    contexts each): every context matches its own single-context guard bitwise, with
+    and without the checked window's plain steps."""
+    norm = dict(in_shift=[0.5, 0.0, 0.0, 0.0], in_scale=[2.0, 100.0, 100.0, 100.0],
+                out_scale=[1e-3] * 4, lrr_scale=0.5)
+    n_ctx, n = 17, 64
+    s = sur_mod.Surrogate(n, n, n_ctx, norm)
+    s.set_params(flat_params(U.init_weights(1, scale=0.1)))
+    seeds = list(range(10, 10 + n_ctx))
+    lrr = [float(np.log10(pfinputs_drops(k, n)["rho_H"])) for k in seeds]
+    for check_every in (0, 1):
+        batch = [_drops_sim(n=n, seed=k)[0] for k in seeds]
+        nf = s.advance_guarded(batch, 1, lrr, mass_tol=1e30, phi_tol=1e30,
+                               check_every=check_every)
+        assert nf == 0
+        for k in (0, 15, 16):
+            one, _ = _drops_sim(n=n, seed=seeds[k])
+            assert s.advance_guarded(one, 1, lrr[k], mass_tol=1e30, phi_tol=1e30,
+                                     check_every=check_every) == 0
+            assert batch[k].steps == one.steps == 16
+            assert torch.equal(batch[k].read(("phi",))["phi"], one.read(("phi",))["phi"])
+            assert torch.equal(batch[k].read(("J",))["J"], one.read(("J",))["J"])
+
+
 def pfinputs_drops(seed, n=64):
     import pfinputs as I
     return I.drops(seed, n=n)
