@@ -19,34 +19,47 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU z sigmoid(z) and its derivative.  The sigmoid's reciprocal is the hardware
+// v_rcp_f32 (1 ulp): the results are rounded to BF16 (or feed BF16 products) anyway, and
+// an IEEE division would cost three times the instructions of the whole activation.
+__device__ __forceinline__ float sigmoid(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // 8 consecutive input channels at output-resolution pixel (b, y, x), through the layer's
-// input mode (same resolution, 2x nearest upsampling, or 2x2 average pooling).
+// input mode (same resolution, 2x nearest upsampling, or 2x2 average pooling).  M is the
+// mode when the caller fixes it at compile time, -1 to take g.mode.  Pixel indices fit
+// 32 bits (at most 2^28 input pixels).
+template <int M>
 __device__ __forceinline__ bf16x8 gather8(const GatherP& g, int b, int y, int x, int c) {
-    if (g.mode == MODE_UP) {
+    const int mode = M >= 0 ? M : g.mode;
+    if (mode == MODE_UP) {
         y >>= 1;
         x >>= 1;
     }
-    if (g.mode != MODE_POOL) {
-        const size_t idx = (((size_t)b * g.Hin + y) * g.Win + x) * g.cs + g.c0 + c;
-        return *reinterpret_cast<const bf16x8*>(g.p + idx);
+    const int cc = g.c0 + c;
+    if (mode != MODE_POOL) {
+        const uint32_t pix = ((uint32_t)b * (uint32_t)g.Hin + (uint32_t)y) * (uint32_t)g.Win + (uint32_t)x;
+        return *reinterpret_cast<const bf16x8*>(g.p + (size_t)pix * g.cs + cc);
     }
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
-            const size_t idx = (((size_t)b * g.Hin + 2 * y + i) * g.Win + 2 * x + j) * g.cs + g.c0 + c;
-            const bf16x8 v = *reinterpret_cast<const bf16x8*>(g.p + idx);
-            for (int k = 0; k < 8; ++k) acc[k] += (float)v[k];
-        }
+    const uint32_t pix =
+        ((uint32_t)b * (uint32_t)g.Hin + 2u * (uint32_t)y) * (uint32_t)g.Win + 2u * (uint32_t)x;
+    const __bf16* q = g.p + (size_t)pix * g.cs + cc;
+    const size_t row = (size_t)g.Win * g.cs;
+    const bf16x8 v0 = *reinterpret_cast<const bf16x8*>(q);
+    const bf16x8 v1 = *reinterpret_cast<const bf16x8*>(q + g.cs);
+    const bf16x8 v2 = *reinterpret_cast<const bf16x8*>(q + row);
+    const bf16x8 v3 = *reinterpret_cast<const bf16x8*>(q + row + g.cs);
     bf16x8 r;
-    for (int k = 0; k < 8; ++k) r[k] = (__bf16)(0.25f * acc[k]);
+    for (int k = 0; k < 8; ++k)
+        r[k] = (__bf16)(0.25f * ((((float)v0[k] + (float)v1[k]) + (float)v2[k]) + (float)v3[k]));
     return r;
 }
 
@@ -87,7 +100,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvP a) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         bf16x8 A[4], Bm[2];
         for (int mb = 0; mb < 4; ++mb)
-            A[mb] = (kv && pv[mb]) ? gather8(a.g, pb[mb], wrap(py[mb] + dy, a.H), wrap(px[mb] + dx, a.W), cg * 8)
+            A[mb] = (kv && pv[mb]) ? gather8<-1>(a.g, pb[mb], wrap(py[mb] + dy, a.H), wrap(px[mb] + dx, a.W), cg * 8)
                                    : zero8;
         for (int nb = 0; nb < 2; ++nb) {
             const int co = co0 + nb * 16 + r16;
@@ -140,13 +153,17 @@ constexpr int BPAD = 9 * 32 + 8;       // BF16 per staged output channel
 constexpr int A_ITEMS = HP * HP * 4;   // 16-byte items of the halo patch
 constexpr int A_PER_T = (A_ITEMS + 255) / 256;
 
-// Epilogue of a 16x16-pixel tile.  The MFMAs compute D[channel][pixel] (weights as the
+// Epilogues of a 16x16-pixel tile.  The MFMAs compute D[channel][pixel] (weights as the
 // A operand), so lane l holds pixel l%32 of its 32-pixel row block and, for j = 0..15,
-// channel 8(j/4) + 4(l/32) + j%4 of the 32-channel block: runs of 4 consecutive channels,
-// written as one 8-byte (BF16) or 16-byte (FP32) store each.
+// channel 8(j/4) + 4(l/32) + j%4 of the 32-channel block.
+//
+// Direct: each lane writes its runs of 4 consecutive channels as one 8-byte (BF16) or
+// 16-byte (FP32) store.  Used for 32-channel tiles, where it measured as fast as the
+// staged form without its extra barrier.
 template <int NB>
-__device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc)[2][NB], int b,
-                                              int y0, int x0, int co0, int wave, int l32, int g) {
+__device__ __forceinline__ void tile_epilogue_direct(const ConvP& a, const f32x16 (&acc)[2][NB],
+                                                     int b, int y0, int x0, int co0, int wave,
+                                                     int l32, int g) {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
@@ -188,6 +205,90 @@ __device__ __forceinline__ void tile_epilogue(const ConvP& a, const f32x16 (&acc
     }
 }
 
+// Staged (64-channel tiles, 8-12% faster there): the BF16 outputs go through LDS, one
+// 32-channel block at a time, in the wave's own region of OROW BF16 per pixel (sO: 64
+// OROW per wave): each lane writes its 4-channel runs, then reads back 16 bytes (8
+// channels) of one pixel so that four consecutive lanes store one pixel's 64 contiguous
+// bytes and a store instruction covers 16 pixels instead of 64 scattered 8-byte pieces.
+// The FP32 output (input gradients) keeps direct 16-byte stores.
+constexpr int OROW = 40;   // BF16 per staged pixel: 32 channels + pad
+
+// LDS accesses of one wave complete in order; the wait and the clobber keep the
+// compiler from moving the read-back across the writes (and the next writes across it)
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <int NB>
+__device__ __forceinline__ void tile_epilogue_staged(const ConvP& a, const f32x16 (&acc)[2][NB],
+                                                     int b, int y0, int x0, int co0, int wave,
+                                                     int l32, int g, __bf16* __restrict__ sO) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    const int lane = l32 + 32 * g;
+    __bf16* so = sO + wave * 64 * OROW;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int cb = co0 + nb * 32;            // first channel of the block
+        if (cb >= a.Cout) break;
+        // value of channel run q (4 channels), element e, row block mb
+        auto val = [&](int mb, int q, int e) {
+            return acc[mb][nb][4 * q + e] + (a.bias ? a.bias[cb + 8 * q + 4 * g + e] : 0.0f);
+        };
+        if (a.fout) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const int y = y0 + 4 * wave + 2 * mb + (l32 >> 4), x = x0 + (l32 & 15);
+                if (y >= a.H || x >= a.W) continue;
+                const size_t p = ((size_t)b * a.H + y) * a.W + x;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float4* f = reinterpret_cast<float4*>(a.fout + p * a.f_cs + a.f_c0 + cb +
+                                                          8 * q + 4 * g);
+                    float4 w = make_float4(val(mb, q, 0), val(mb, q, 1), val(mb, q, 2),
+                                           val(mb, q, 3));
+                    if (a.f_accum) {
+                        const float4 o = *f;
+                        w.x += o.x; w.y += o.y; w.z += o.z; w.w += o.w;
+                    }
+                    *f = w;
+                }
+            }
+        }
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            __bf16* dst = pass == 0 ? a.zout : a.out;
+            if (!dst) continue;
+            const int cs = pass == 0 ? a.Cout : a.out_cs;
+            const int c0 = pass == 0 ? 0 : a.out_c0;
+            const bool act = pass == 1 && a.act;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float t = val(mb, q, e);
+                        o[e] = (__bf16)(act ? silu(t) : t);
+                    }
+                    *reinterpret_cast<bf16x4*>(&so[(mb * 32 + l32) * OROW + 8 * q + 4 * g]) = o;
+                }
+            wave_lds_sync();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int i = lane + 64 * k;                 // 16-byte item: pixel i/4
+                const int px = i >> 2, grp = i & 3;
+                const int mb = px >> 5, pl = px & 31;
+                const int y = y0 + 4 * wave + 2 * mb + (pl >> 4), x = x0 + (pl & 15);
+                const bf16x8 val = *reinterpret_cast<const bf16x8*>(&so[px * OROW + 8 * grp]);
+                if (y < a.H && x < a.W) {
+                    const size_t p = ((size_t)b * a.H + y) * a.W + x;
+                    *reinterpret_cast<bf16x8*>(dst + p * cs + c0 + cb + 8 * grp) = val;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
 // 32-channel tiles use 45 KB of LDS, so three workgroups fit a CU when the registers
 // allow it; 64-channel tiles (64 KB) fit two.
 template <int NT, int MODE>
@@ -195,8 +296,9 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
     constexpr int NB = NT / 32;
-    __shared__ __bf16 sA[HP * HP * APAD];
-    __shared__ __bf16 sB[NT * BPAD];
+    __shared__ __align__(16) __bf16 sA[HP * HP * APAD];
+    __shared__ __align__(16) __bf16 sB[NT * BPAD];
+    static_assert(4 * 64 * OROW <= HP * HP * APAD, "epilogue staging must fit the patch buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l32 = lane & 31, g = lane >> 5;
     const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
@@ -231,7 +333,7 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
             if (i < A_ITEMS) {
                 const int pi = i >> 2, grp = i & 3;
                 const int py = pi / HP, px = pi - py * HP;
-                ra[k] = gather8(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W),
+                ra[k] = gather8<MODE>(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W),
                                 c0 + 8 * grp);
             }
         }
@@ -319,7 +421,12 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
         if (ch == nchunk - 1) {
             int b, y0, x0;
             tile_xy(t_beg + it / nchunk, b, y0, x0);
-            tile_epilogue<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
+            if constexpr (NB == 2) {
+                __syncthreads();                 // every wave is done reading the patch
+                tile_epilogue_staged<NB>(a, acc, b, y0, x0, co0, wave, l32, g, sA);
+            } else {
+                tile_epilogue_direct<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
+            }
         }
     }
 }
@@ -332,8 +439,8 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
 constexpr int BPAD1 = 88;   // 10 taps x 8 channels + pad: conflict-free 16-byte reads
 
 __global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
-    __shared__ __bf16 sA[HP * HP * 8];
-    __shared__ __bf16 sB[32 * BPAD1];
+    __shared__ __align__(16) __bf16 sA[HP * HP * 8];
+    __shared__ __align__(16) __bf16 sB[32 * BPAD1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l32 = lane & 31, g = lane >> 5;
     const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
@@ -348,7 +455,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
     for (int it = threadIdx.x; it < HP * HP; it += 256) {
         const int py = it / HP, px = it - py * HP;
         *reinterpret_cast<bf16x8*>(&sA[it * 8]) =
-            gather8(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W), 0);
+            gather8<MODE_SAME>(a.g, b, wrap(y0 - 1 + py, a.H), wrap(x0 - 1 + px, a.W), 0);
     }
     for (int it = threadIdx.x; it < 32 * 10; it += 256) {
         const int col = it / 10, tap = it - col * 10;
@@ -379,7 +486,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
             acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm, A, acc[mb][0], 0, 0, 0);
         }
     }
-    tile_epilogue<1>(a, acc, b, y0, x0, co0, wave, l32, g);
+    tile_epilogue_direct<1>(a, acc, b, y0, x0, co0, wave, l32, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,7 +547,7 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_tiled(WgradP a, int patches_pe
                 const int pi = it >> 2, cg = it & 3;
                 const int hy = pi / HP, hx = pi - hy * HP;
                 const int c = c0 + 8 * cg;
-                rx[k] = c < C ? gather8(a.g, b, wrap(y0 - 1 + hy, a.H), wrap(x0 - 1 + hx, a.W), c)
+                rx[k] = c < C ? gather8<MODE>(a.g, b, wrap(y0 - 1 + hy, a.H), wrap(x0 - 1 + hx, a.W), c)
                               : zero8;
             }
         }
