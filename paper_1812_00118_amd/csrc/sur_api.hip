@@ -19,29 +19,38 @@ namespace {
 
 // Activation buffers, NHWC BF16 at one level (resolution H >> level), with C channels.
 // Skip connections share a buffer with the decoder branch they are concatenated with,
-// so the concatenation is a channel offset.
-enum Buf { X, E0A, CAT0, D0A, D0B, E1A, CAT1, D1A, D1B, E2A, CAT2, D2A, D2B, B3A, B3B, NBUFS };
-struct BufDef {
-    int level, C;
+// so the concatenation is a channel offset.  POOLk holds the 2x2 averages of an encoder
+// output, written by the producing layer's epilogue and read by the next level's pooling
+// layer (no gradient buffer: the backward distributes through the pooling explicitly).
+enum Buf {
+    X, E0A, CAT0, D0A, D0B, E1A, CAT1, D1A, D1B, E2A, CAT2, D2A, D2B, B3A, B3B,
+    POOL0, POOL1, POOL2, NBUFS
 };
-const BufDef BUFS[NBUFS] = {{0, 8},   {0, 32},  {0, 64},  {0, 32},  {0, 32},
-                            {1, 64},  {1, 128}, {1, 64},  {1, 64},  {2, 128},
-                            {2, 256}, {2, 128}, {2, 128}, {3, 256}, {3, 256}};
+struct BufDef {
+    int level, C, grad;
+};
+constexpr BufDef BUFS[NBUFS] = {{0, 8, 1},   {0, 32, 1},  {0, 64, 1},  {0, 32, 1},  {0, 32, 1},
+                            {1, 64, 1},  {1, 128, 1}, {1, 64, 1},  {1, 64, 1},  {2, 128, 1},
+                            {2, 256, 1}, {2, 128, 1}, {2, 128, 1}, {3, 256, 1}, {3, 256, 1},
+                            {1, 32, 0},  {2, 64, 0},  {3, 128, 0}};
 
-// 3x3 layers in network order; level = output resolution
+// 3x3 layers in network order; level = output resolution.  pool_out: the buffer that also
+// receives the 2x2 average of this layer's output (channels 0..Cout); pool_in: a pooling
+// layer reads that buffer at its own resolution instead of pooling its input itself.
 struct LayerDef {
     const char* name;
     int in_buf, in_c0, Cin, Cout, level, mode, out_buf, out_c0;
+    int pool_out = -1, pool_in = -1;
 };
 constexpr int NL = 17;
-const LayerDef LAYERS[NL] = {
+constexpr LayerDef LAYERS[NL] = {
     {"e0a", X, 0, 8, 32, 0, MODE_SAME, E0A, 0},
-    {"e0b", E0A, 0, 32, 32, 0, MODE_SAME, CAT0, 0},
-    {"e1a", CAT0, 0, 32, 64, 1, MODE_POOL, E1A, 0},
-    {"e1b", E1A, 0, 64, 64, 1, MODE_SAME, CAT1, 0},
-    {"e2a", CAT1, 0, 64, 128, 2, MODE_POOL, E2A, 0},
-    {"e2b", E2A, 0, 128, 128, 2, MODE_SAME, CAT2, 0},
-    {"b3a", CAT2, 0, 128, 256, 3, MODE_POOL, B3A, 0},
+    {"e0b", E0A, 0, 32, 32, 0, MODE_SAME, CAT0, 0, POOL0},
+    {"e1a", CAT0, 0, 32, 64, 1, MODE_POOL, E1A, 0, -1, POOL0},
+    {"e1b", E1A, 0, 64, 64, 1, MODE_SAME, CAT1, 0, POOL1},
+    {"e2a", CAT1, 0, 64, 128, 2, MODE_POOL, E2A, 0, -1, POOL1},
+    {"e2b", E2A, 0, 128, 128, 2, MODE_SAME, CAT2, 0, POOL2},
+    {"b3a", CAT2, 0, 128, 256, 3, MODE_POOL, B3A, 0, -1, POOL2},
     {"b3b", B3A, 0, 256, 256, 3, MODE_SAME, B3B, 0},
     {"u2", B3B, 0, 256, 128, 2, MODE_UP, CAT2, 128},
     {"d2a", CAT2, 0, 256, 128, 2, MODE_SAME, D2A, 0},
@@ -54,6 +63,29 @@ const LayerDef LAYERS[NL] = {
     {"d0b", D0A, 0, 32, 32, 0, MODE_SAME, D0B, 0},
 };
 constexpr int HEAD_C = 32;
+
+// a pooled buffer is written whole by one layer at the level above the pooling layer that
+// reads it, and holds exactly the channels that layer would pool from its input buffer
+constexpr bool pool_links_ok() {
+    for (int c = 0; c < NL; ++c) {
+        const LayerDef& R = LAYERS[c];
+        if (R.pool_in < 0) continue;
+        int writers = 0;
+        for (int l = 0; l < NL; ++l) {
+            const LayerDef& W = LAYERS[l];
+            if (W.pool_out != R.pool_in) continue;
+            ++writers;
+            if (l >= c || W.out_buf != R.in_buf || W.out_c0 != R.in_c0 || W.Cout != R.Cin ||
+                W.level + 1 != R.level)
+                return false;
+        }
+        if (writers != 1 || R.mode != MODE_POOL || BUFS[R.pool_in].C != R.Cin ||
+            BUFS[R.pool_in].level != R.level || BUFS[R.pool_in].grad)
+            return false;
+    }
+    return true;
+}
+static_assert(pool_links_ok(), "inconsistent pooled-input links in the layer table");
 
 struct ParamLayout {
     size_t w[NL], b[NL], head, total;
@@ -107,7 +139,8 @@ Plan make_plan(int H, int W, int B, bool training) {
     for (int k = 1; k < NBUFS; ++k) p.act[k] = take(pix(BUFS[k].level) * BUFS[k].C * 2);
     if (training) {
         for (int l = 0; l < NL; ++l) p.z[l] = take(pix(LAYERS[l].level) * LAYERS[l].Cout * 2);
-        for (int k = 1; k < NBUFS; ++k) p.dact[k] = take(pix(BUFS[k].level) * BUFS[k].C * 4);
+        for (int k = 1; k < NBUFS; ++k)
+            if (BUFS[k].grad) p.dact[k] = take(pix(BUFS[k].level) * BUFS[k].C * 4);
         p.out = take(pix(0) * PFSUR_OUT_CH * 4);
         p.dout = take(pix(0) * PFSUR_OUT_CH * 4);
         size_t dz = 0, dx = 0, part = (size_t)head_blocks(pix(0)) * 132;
@@ -181,6 +214,16 @@ hipError_t refresh_bf16(pfsur_ctx* c, hipStream_t st) {
 
 GatherP gather_of(const LayerDef& L, const char* ws, const Plan& p, const void* x, int H, int W) {
     GatherP g;
+    if (L.pool_in >= 0) {   // the pooled input, already averaged, at the layer's resolution
+        g.p = reinterpret_cast<const __bf16*>(ws + p.act[L.pool_in]);
+        g.Hin = H >> L.level;
+        g.Win = W >> L.level;
+        g.cs = BUFS[L.pool_in].C;
+        g.c0 = 0;
+        g.C = L.Cin;
+        g.mode = MODE_SAME;
+        return g;
+    }
     g.p = L.in_buf == X ? static_cast<const __bf16*>(x)
                         : reinterpret_cast<const __bf16*>(ws + p.act[L.in_buf]);
     const int Hl = H >> L.level, Wl = W >> L.level;
@@ -214,6 +257,10 @@ int run_forward(pfsur_ctx* c, const void* x, float* out, int B, char* ws, bool t
         a.out = reinterpret_cast<__bf16*>(ws + p.act[L.out_buf]);
         a.out_cs = BUFS[L.out_buf].C;
         a.out_c0 = L.out_c0;
+        if (L.pool_out >= 0) {
+            a.pout = reinterpret_cast<__bf16*>(ws + p.act[L.pool_out]);
+            a.pout_cs = BUFS[L.pool_out].C;
+        }
         SUR_TRY(conv3x3(a, st), "conv forward");
     }
     const size_t P0 = (size_t)B * H * W;

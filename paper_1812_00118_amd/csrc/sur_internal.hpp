@@ -20,7 +20,9 @@ struct GatherP {
 
 // out[p, co] for p over B x H x W output pixels, co < Cout; weights [Cout][9][C] BF16.
 // Epilogue: v = acc + bias; zout (BF16 [P][Cout]) <- v; out (BF16 at channel stride
-// out_cs, offset out_c0) <- act ? silu(v) : v; fout (FP32 at f_cs, f_c0) <- v (or += v).
+// out_cs, offset out_c0) <- act ? silu(v) : v; fout (FP32 at f_cs, f_c0) <- v (or += v);
+// pout (BF16 [B][H/2][W/2][pout_cs], channels from 0; needs out and even H, W) <- the 2x2
+// average of what out receives, as the pooling gather computes it.
 struct ConvP {
     GatherP g;
     int B, H, W;
@@ -33,6 +35,8 @@ struct ConvP {
     int out_cs, out_c0;
     float* fout;
     int f_cs, f_c0, f_accum;
+    __bf16* pout;
+    int pout_cs;
 };
 
 // part[split][Cout][9][C] = sum over the split's pixels of dz[p, co] in[p + off(tap), ci]

@@ -210,7 +210,9 @@ __device__ __forceinline__ void tile_epilogue_direct(const ConvP& a, const f32x1
 // OROW per wave): each lane writes its 4-channel runs, then reads back 16 bytes (8
 // channels) of one pixel so that four consecutive lanes store one pixel's 64 contiguous
 // bytes and a store instruction covers 16 pixels instead of 64 scattered 8-byte pieces.
-// The FP32 output (input gradients) keeps direct 16-byte stores.
+// The FP32 output (input gradients) keeps direct 16-byte stores.  With pout set, the
+// staged activations also give their 2x2 averages (the input of the next level's pooling
+// layer), so that layer reads a compact quarter-size tensor at its own resolution.
 constexpr int OROW = 40;   // BF16 per staged pixel: 32 channels + pad
 
 // LDS accesses of one wave complete in order; the wait and the clobber keep the
@@ -284,6 +286,29 @@ __device__ __forceinline__ void tile_epilogue_staged(const ConvP& a, const f32x1
                     *reinterpret_cast<bf16x8*>(dst + p * cs + c0 + cb + 8 * grp) = val;
                 }
             }
+            if (pass == 1 && a.pout) {
+                // 2x2 average of the stored activations for the next level's pooling
+                // layer, added in the pooling gather's order: (y, x), (y, x+1), (y+1, x),
+                // (y+1, x+1).  The wave's 4 x 16 pixels give 2 x 8 pooled pixels x 4
+                // groups of 8 channels: one item per lane.
+                const int pp = lane >> 2, grp = lane & 3;
+                const int mb = pp >> 3, pc = pp & 7;
+                const int base = mb * 32 + 2 * pc;               // staged pixel (y, x)
+                const bf16x8 v00 = *reinterpret_cast<const bf16x8*>(&so[base * OROW + 8 * grp]);
+                const bf16x8 v01 = *reinterpret_cast<const bf16x8*>(&so[(base + 1) * OROW + 8 * grp]);
+                const bf16x8 v10 = *reinterpret_cast<const bf16x8*>(&so[(base + 16) * OROW + 8 * grp]);
+                const bf16x8 v11 = *reinterpret_cast<const bf16x8*>(&so[(base + 17) * OROW + 8 * grp]);
+                bf16x8 r;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    r[e] = (__bf16)(0.25f * ((((float)v00[e] + (float)v01[e]) + (float)v10[e]) +
+                                             (float)v11[e]));
+                const int y = y0 + 4 * wave + 2 * mb, x = x0 + 2 * pc;
+                if (y + 1 < a.H && x + 1 < a.W) {
+                    const size_t q = ((size_t)b * (a.H >> 1) + (y >> 1)) * (a.W >> 1) + (x >> 1);
+                    *reinterpret_cast<bf16x8*>(a.pout + q * a.pout_cs + cb + 8 * grp) = r;
+                }
+            }
             wave_lds_sync();
         }
     }
@@ -291,7 +316,9 @@ __device__ __forceinline__ void tile_epilogue_staged(const ConvP& a, const f32x1
 
 // 32-channel tiles use 45 KB of LDS, so three workgroups fit a CU when the registers
 // allow it; 64-channel tiles (64 KB) fit two.
-template <int NT, int MODE>
+// STAGED selects the staged epilogue (always for 64-channel tiles; for 32-channel tiles
+// only when the layer also writes pooled output).
+template <int NT, int MODE, bool STAGED>
 __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, int tiles_per_wg) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
@@ -421,7 +448,7 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
         if (ch == nchunk - 1) {
             int b, y0, x0;
             tile_xy(t_beg + it / nchunk, b, y0, x0);
-            if constexpr (NB == 2) {
+            if constexpr (STAGED) {
                 __syncthreads();                 // every wave is done reading the patch
                 tile_epilogue_staged<NB>(a, acc, b, y0, x0, co0, wave, l32, g, sA);
             } else {
@@ -942,7 +969,7 @@ __global__ void __launch_bounds__(256) k_sum_field(const float* __restrict__ a, 
 static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int NT>
-static void launch_tiled(const ConvP& a, hipStream_t st) {
+static hipError_t launch_tiled(const ConvP& a, hipStream_t st) {
     // as many workgroups as are resident at once (3 or 2 per CU); each walks a
     // contiguous run of tiles so that the loads of its next tile overlap the MFMAs of
     // the current one
@@ -951,27 +978,30 @@ static void launch_tiled(const ConvP& a, hipStream_t st) {
     const int nblk_n = (a.Cout + NT - 1) / NT;
     const int per = std::max(1, (ntile * nblk_n + resident - 1) / resident);
     const dim3 grid((ntile + per - 1) / per, nblk_n);
+    if (a.pout && (a.H % 2 || a.W % 2 || !a.out || (NT == 32 && a.g.mode != MODE_SAME)))
+        return hipErrorInvalidValue;
+    constexpr bool S64 = NT == 64;
     if (a.g.mode == MODE_POOL)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL, S64>), grid, dim3(256), 0, st, a, per);
     else if (a.g.mode == MODE_UP)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP, S64>), grid, dim3(256), 0, st, a, per);
+    else if (!S64 && a.pout)
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, true>), grid, dim3(256), 0, st, a, per);
     else
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, S64>), grid, dim3(256), 0, st, a, per);
+    return hipGetLastError();
 }
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st) {
     if (a.g.C == 8 && a.g.mode == MODE_SAME && a.Cout % 32 == 0) {
+        if (a.pout) return hipErrorInvalidValue;
         const dim3 grid(a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP), a.Cout / 32);
         hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, st, a);
         return hipGetLastError();
     }
-    if (a.g.C % 32 == 0 && a.Cout % 32 == 0) {
-        if (a.Cout % 64 == 0)
-            launch_tiled<64>(a, st);
-        else
-            launch_tiled<32>(a, st);
-        return hipGetLastError();
-    }
+    if (a.g.C % 32 == 0 && a.Cout % 32 == 0)
+        return a.Cout % 64 == 0 ? launch_tiled<64>(a, st) : launch_tiled<32>(a, st);
+    if (a.pout) return hipErrorInvalidValue;   // pooled output needs the tiled kernels
     const int P = a.B * a.H * a.W;
     hipLaunchKernelGGL(k_conv3x3, dim3((P + 255) / 256, (a.Cout + 31) / 32), dim3(256), 0, st, a);
     return hipGetLastError();
