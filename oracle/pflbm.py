@@ -27,6 +27,12 @@ Readings of points the paper leaves open (each is also listed in the design note
 * Boundaries: periodic axes wrap; wall axes use halfway bounce-back for both sets,
   and the ghost value of phi outside a wall equals the adjacent fluid site's value
   (zero normal gradient).
+* Moving walls (not in the paper; the standard momentum correction of halfway
+  bounce-back for a wall moving with velocity u_w, Ladd 1994): a population leaving x in
+  direction i into a wall face returns as opp(i) at x reduced by 2 w_i (c_i . u_w)/T
+  times phi(x) (set h) or rho(x) (set g), the site's pre-collision values.  u_w is the
+  velocity of the face crossed; a population that crosses two or three wall faces at an
+  edge or corner takes the mean of their velocities.  Face velocities are tangential.
 * No clipping of phi anywhere; n = grad(phi)/(|grad(phi)| + eps) exactly as printed.
 """
 import numpy as np
@@ -35,6 +41,8 @@ from .lattice import T, lattice as _lattice
 
 PERIODIC = "periodic"
 WALL = "wall"
+# wall faces in the order of Params.wall_u: (axis, side)
+FACES = ((0, -1), (0, 1), (1, -1), (1, 1), (2, -1), (2, 1))
 
 
 class Params:
@@ -45,7 +53,7 @@ class Params:
     """
 
     def __init__(self, lattice, shape, bc, rho_L, rho_H, nu_L, nu_H, M, W, sigma,
-                 g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0):
+                 g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0, wall_u=None):
         self.lat = _lattice(lattice)
         nx, ny, nz = shape
         if self.lat.D == 2 and nz != 1:
@@ -65,6 +73,14 @@ class Params:
         self.eps = float(eps)
         self.hoc = int(hoc)
         self.dtheta_C = float(dtheta_C)
+        # velocity of each wall face, rows x-, x+, y-, y+, z-, z+ (see FACES)
+        self.wall_u = (np.zeros((6, 3)) if wall_u is None
+                       else np.asarray(wall_u, dtype=np.float64).reshape(6, 3))
+        for f, (a, _) in enumerate(FACES):
+            if self.wall_u[f, a] != 0.0:
+                raise ValueError("a wall moves tangentially: normal velocity must be 0")
+            if self.bc[a] != WALL and np.any(self.wall_u[f] != 0.0):
+                raise ValueError("velocity given for a face of a periodic axis")
 
     # Eq. 1: relaxation time of h is M/T + 0.5
     @property
@@ -88,7 +104,7 @@ class Params:
     @classmethod
     def from_dict(cls, d):
         keys = ("lattice", "shape", "bc", "rho_L", "rho_H", "nu_L", "nu_H", "M", "W",
-                "sigma", "g", "eps", "hoc", "dtheta_C")
+                "sigma", "g", "eps", "hoc", "dtheta_C", "wall_u")
         return cls(**{k: d[k] for k in keys if k in d})
 
 
@@ -302,14 +318,45 @@ def _source_solid(c, shape, bc):
     return solid
 
 
-def stream(lat, prm, fstar):
+def wall_cu(prm, k, xyz):
+    """c_k . u_w for populations leaving the sites xyz (N, 3 integer (x, y, z)) in
+    direction k: u_w is the velocity of the wall face the population crosses, the mean of
+    the crossed faces' velocities at an edge or corner, 0 where it crosses none."""
+    c = prm.lat.c[k]
+    s = np.zeros(len(xyz))
+    n = np.zeros(len(xyz))
+    for f, (a, side) in enumerate(FACES):
+        if prm.bc[a] != WALL or c[a] != side:
+            continue
+        dest = xyz[:, a] + c[a]
+        crossed = (dest < 0) | (dest >= prm.shape[a])
+        s += np.where(crossed, float(c @ prm.wall_u[f]), 0.0)
+        n += crossed
+    return np.where(n > 0, s / np.maximum(n, 1.0), 0.0)
+
+
+def _all_sites(shape):
+    nx, ny, nz = shape
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+
+
+def stream(lat, prm, fstar, scale=None):
     """f_i(x, n+1) = f*_i(x - c_i, n); where x - c_i is outside a wall the population
-    comes back from x itself: f_i(x, n+1) = f*_opp(i)(x, n) (halfway bounce-back)."""
+    comes back from x itself: f_i(x, n+1) = f*_opp(i)(x, n) (halfway bounce-back), less
+    2 w (c_opp(i) . u_w)/T scale(x) for a moving wall (scale: phi for h, rho for g)."""
     out = np.empty_like(fstar)
+    moving = scale is not None and np.any(prm.wall_u != 0.0)
+    xyz = _all_sites(prm.shape) if moving else None
     for i in range(lat.Q):
         c = lat.c[i]
         pulled = np.roll(fstar[i], shift=(int(c[2]), int(c[1]), int(c[0])), axis=(0, 1, 2))
-        out[i] = np.where(_source_solid(c, prm.shape, prm.bc), fstar[lat.opp[i]], pulled)
+        back = fstar[lat.opp[i]]
+        if moving:
+            j = lat.opp[i]
+            cu = wall_cu(prm, j, xyz).reshape(back.shape)
+            back = back - (2.0 / T) * lat.w[j] * cu * scale
+        out[i] = np.where(_source_solid(c, prm.shape, prm.bc), back, pulled)
     return out
 
 
@@ -322,8 +369,8 @@ def step(prm, h, g):
     lat = prm.lat
     phi = h.sum(0)
     phi_nb = phi_stencil(phi, lat, prm.bc)
-    hstar, gstar, _ = collide(lat, prm, h, g, phi_nb)
-    return stream(lat, prm, hstar), stream(lat, prm, gstar)
+    hstar, gstar, m = collide(lat, prm, h, g, phi_nb)
+    return stream(lat, prm, hstar, m["phi"]), stream(lat, prm, gstar, m["rho"])
 
 
 def run(prm, h, g, nsteps):
@@ -418,13 +465,22 @@ def step_sites(prm, h, g, sites):
         y = _map_axis(ups[:, 1] + lat.c[k, 1], ny, prm.bc[1])
         z = _map_axis(ups[:, 2] + lat.c[k, 2], nz, prm.bc[2])
         phi_nb[k] = hf[:, lin(x, y, z)].astype(np.float64).sum(0)
-    hstar, gstar, _ = collide(lat, prm, hu, gu, phi_nb)
+    hstar, gstar, m = collide(lat, prm, hu, gu, phi_nb)
     hstar = hstar.reshape(lat.Q, S, lat.Q)
     gstar = gstar.reshape(lat.Q, S, lat.Q)
     rows = np.arange(S)
     h_out = np.empty((lat.Q, S))
     g_out = np.empty((lat.Q, S))
+    moving = np.any(prm.wall_u != 0.0)
     for i in range(lat.Q):
         h_out[i] = hstar[pop[:, i], rows, i]
         g_out[i] = gstar[pop[:, i], rows, i]
+        if moving:
+            # bounced entries (pop = opp(i)) come from the output site itself
+            j = lat.opp[i]
+            bounced = pop[:, i] == j if i != 0 else np.zeros(S, dtype=bool)
+            cu = np.where(bounced, wall_cu(prm, j, sites), 0.0)
+            k = (2.0 / T) * lat.w[j] * cu
+            h_out[i] -= k * m["phi"].reshape(S, lat.Q)[:, i]
+            g_out[i] -= k * m["rho"].reshape(S, lat.Q)[:, i]
     return h_out, g_out

@@ -6,7 +6,9 @@
 * Laplace's law dP = sigma/R, error shrinking as W^-2            (Section 4.1)
 * layered two-phase Poiseuille vs the diffuse-profile closed form (Section 3, first case)
 * Galilean invariance of a translating 1-D drop                  (Section 3)
-The last two also pin the reading of the high-order correction (Eq. 13 with the
+* moving walls: linear Couette profile, single phase and layered two-phase (closed form
+  on the diffuse profile), Sigma phi exact
+The layered Poiseuille and Galilean cases also pin the reading of the high-order correction (Eq. 13 with the
 modified velocity): with it the oracle matches, without it it fails, as the paper says.
 """
 import numpy as np
@@ -181,3 +183,71 @@ def test_galilean_invariance():
     assert dphi1 < 0.02
     dev0, _ = _galilean(0, steps=1000)
     assert dev0 > 0.2
+
+
+def _couette_prm(q, shape, rho_H, nu_L, nu_H, W, sigma, Ulo, Uhi):
+    """Walls across x, the x- face moving with Ulo and the x+ face with Uhi along y."""
+    wall = np.zeros((6, 3))
+    wall[0, 1] = Ulo
+    wall[1, 1] = Uhi
+    return O.Params(q, shape, (O.WALL, P_, P_), 1.0, rho_H, nu_L, nu_H, 0.1, W, sigma,
+                    hoc=1, wall_u=wall)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_couette_single_phase_is_linear(q):
+    """One phase (phi = 1, rho = 1000) between walls at x = -1/2 and L - 1/2 moving with
+    -0.01 and 0.02 along y: the steady profile is the straight line between them.  Halfway
+    bounce-back with the moving-wall correction reproduces it to rounding once the
+    slowest transient (rate nu pi^2 / L^2) has decayed; a wrong sign, factor or density in
+    the correction moves the wall velocities."""
+    L, Ulo, Uhi = 8, -0.01, 0.02
+    shape = (L, 1, 1) if q == 9 else (L, 1, 2)
+    prm = _couette_prm(q, shape, 1000.0, 0.1, 0.1, 4.0, 1e-3, Ulo, Uhi)
+    phi = np.ones(shape[::-1])
+    h, g = O.init(prm, phi, np.zeros((3,) + shape[::-1]))
+    m0 = O.mass(h)
+    h, g = O.run(prm, h, g, 2000 if q == 9 else 1600)
+    u = O.read(prm, h, g)["u"]
+    x = np.arange(L)
+    ua = Ulo + (Uhi - Ulo) * (x + 0.5) / L
+    assert np.abs(u[1].reshape(-1, L) - ua).max() <= 1e-9 * (Uhi - Ulo)
+    assert np.abs(u[0]).max() <= 1e-12 and np.abs(u[2]).max() <= 1e-12
+    assert abs(O.mass(h) - m0) <= 1e-12 * m0
+
+
+def test_layered_couette():
+    """Water (phi = 1) left, air right, mu_ratio 100, W 2.5, the x+ wall moving with 0.01
+    along y.  The shear stress mu u' is uniform at steady state, so u(x) = U int 1/mu /
+    int_walls 1/mu with mu = rho T (tau_mix - 1/2) on the diffuse profile; the oracle
+    matches within 4% of U (the same bar as the layered Poiseuille case) and Sigma phi is
+    conserved to rounding."""
+    L, W, nuw, rr, U = 32, 2.5, 0.17, 1000.0, 0.01
+    nua = nuw * rr / 100.0
+    prm = _couette_prm(9, (L, 1, 1), rr, nua, nuw, W, 0.0, 0.0, U)
+    x = np.arange(L, dtype=float)
+    prof = lambda s: 0.5 - 0.5 * np.tanh(2 * (s - (L / 2 - 0.5)) / W)
+    h, g = O.init(prm, prof(x).reshape(1, 1, L), np.zeros((3, 1, 1, L)))
+    m0 = O.mass(h)
+    h, g = O.run(prm, h, g, 6000)
+    uy = O.read(prm, h, g)["u"][1].ravel()
+    xi = np.linspace(-0.5, L - 0.5, 100001)
+    p = prof(xi)
+    rho = 1.0 + p * (rr - 1.0)
+    itau = 1 / (nua / T + 0.5) + p * (1 / (nuw / T + 0.5) - 1 / (nua / T + 0.5))
+    mu = rho * T * (1 / itau - 0.5)
+    I = cumulative_trapezoid(1 / mu, xi, initial=0)
+    ua = np.interp(x, xi, U * I / I[-1])
+    assert np.abs(uy - ua).max() <= 0.04 * U
+    assert abs(O.mass(h) - m0) <= 1e-12 * m0
+
+
+def test_moving_wall_parameters_are_checked():
+    wall = np.zeros((6, 3))
+    wall[1, 0] = 0.01            # normal component of the x+ face
+    with pytest.raises(ValueError):
+        O.Params(9, (8, 1, 1), (O.WALL, P_, P_), 1.0, 10.0, 0.1, 0.1, 0.1, 4.0, 0.0, wall_u=wall)
+    wall = np.zeros((6, 3))
+    wall[2, 0] = 0.01            # a face of the periodic y axis
+    with pytest.raises(ValueError):
+        O.Params(9, (8, 1, 1), (O.WALL, P_, P_), 1.0, 10.0, 0.1, 0.1, 0.1, 4.0, 0.0, wall_u=wall)
