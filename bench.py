@@ -376,6 +376,22 @@ def main():
                 print(f"[bench] rayleigh_taylor {st}: {r3['kernel_ms']:.4f} ms/step",
                       file=sys.stderr, flush=True)
             out["rayleigh_taylor"] = blk
+            # moving walls: the rising-bubble domain with its top wall sliding along x
+            # (the step variant with momentum-corrected bounce-back)
+            cfg4 = dict(cfg, wall_u=[[0.0] * 3] * 5 + [[0.01, 0.0, 0.0]])
+            blk = {"workload": "rising_bubble D3Q19 128^3, z+ wall moving at 0.01 along x"}
+            for st in ("fp32", "fp16s"):
+                r4 = time_storage(cfg4, st, max(50, args.steps // 4), args.warmup)
+                rest = ms if st == args.storage else oms
+                blk[st] = {"mlups": round(N / (r4["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r4["kernel_ms"], 4),
+                           "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * N /
+                                                 (r4["kernel_ms"] * 1e-3) / 1e9, 1),
+                           "time_vs_resting_walls": round(r4["kernel_ms"] / rest, 3)}
+                print(f"[bench] moving_walls {st}: {r4['kernel_ms']:.4f} ms/step "
+                      f"({r4['kernel_ms'] / rest:.3f}x the resting-wall step)",
+                      file=sys.stderr, flush=True)
+            out["moving_walls"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -86,6 +86,15 @@ extern "C" {
  *   storage      PFLB_STORE_FP32 or PFLB_STORE_FP16S
  *   scale_log2   power-of-two scale exponents of the fp16 deviations of h and g
  *                (FP16S only; each in [-14, 24])
+ *   wall_u       velocity of each wall face, rows x-, x+, y-, y+, z-, z+ and columns
+ *                (u_x, u_y, u_z) in the axes above (D2Q9: rows 0-3, columns 0-1; the rest
+ *                must be 0).  Tangential only (the normal component must be 0) and 0 on
+ *                faces of periodic axes; all zeros (e.g. a zero-initialised struct) is a
+ *                resting box.  Not in the paper: the momentum correction of halfway
+ *                bounce-back for a moving wall (Ladd's method) -- a population sent into
+ *                a wall face returns reduced by 2 w_i (c_i . u_w)/T times the sending
+ *                site's phi (h) or rho (g); one crossing two or three faces at an edge or
+ *                corner takes the mean of their velocities.
  */
 typedef struct pflb_params {
     int lattice;
@@ -100,6 +109,7 @@ typedef struct pflb_params {
     double dtheta_C;
     int storage;
     int scale_log2[2];
+    double wall_u[6][3];
 } pflb_params;
 
 typedef struct pflb_ctx pflb_ctx;

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
                 ("hoc", ctypes.c_int),
                 ("dtheta_C", ctypes.c_double),
                 ("storage", ctypes.c_int),
-                ("scale_log2", ctypes.c_int * 2)]
+                ("scale_log2", ctypes.c_int * 2),
+                ("wall_u", ctypes.c_double * 18)]
 
 
 class SurCfg(ctypes.Structure):

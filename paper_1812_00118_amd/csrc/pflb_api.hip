@@ -60,6 +60,17 @@ std::string check_params(const pflb_params* p) {
     if (p->storage == PFLB_STORE_FP16S)
         for (int k = 0; k < 2; ++k)
             if (p->scale_log2[k] < -14 || p->scale_log2[k] > 24) return "scale_log2 out of [-14, 24]";
+    const int naxes = p->lattice == 9 ? 2 : 3;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a) {
+            const double v = p->wall_u[f][a];
+            if (!finite(v)) return "wall velocities must be finite";
+            if (v == 0.0) continue;
+            const int axis = f / 2;
+            if (axis >= naxes || a >= naxes) return "wall velocity on an axis the lattice does not have";
+            if (p->bc[axis] != PFLB_BC_WALL) return "wall velocity given for a face of a periodic axis";
+            if (a == axis) return "a wall moves tangentially: its normal velocity must be 0";
+        }
     return "";
 }
 
@@ -110,6 +121,20 @@ void derive(pflb_ctx* c) {
         m.gx = (float)p.g[0]; m.gy = 0.0f; m.gz = (float)p.g[1];
     }
     m.beta = p.hoc ? 1.0f : 0.0f;
+    // wall faces and velocity components in internal axes (D2Q9: user y is internal z)
+    m.moving = 0;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a) m.uw[f][a] = 0.0f;
+    for (int f = 0; f < 6; ++f) {
+        const int fi = p.lattice == 19 ? f : (f < 2 ? f : (f < 4 ? f + 2 : -1));
+        if (fi < 0) continue;
+        for (int a = 0; a < 3; ++a) {
+            const int ai = p.lattice == 19 ? a : (a == 0 ? 0 : (a == 1 ? 2 : -1));
+            if (ai < 0) continue;
+            m.uw[fi][ai] = (float)p.wall_u[f][a];
+            if (p.wall_u[f][a] != 0.0) m.moving = 1;
+        }
+    }
     Codec& cd = c->L.cd;
     if (p.storage == PFLB_STORE_FP16S) {
         cd.sh = ldexpf(1.0f, p.scale_log2[0]);

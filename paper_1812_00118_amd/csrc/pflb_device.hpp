@@ -117,6 +117,8 @@ struct Model {
     float eps;                // n = grad/(|grad| + eps)
     float gx, gy, gz;         // gravity in internal axes; F = rho g
     float beta;               // 1: Eq. 13 correction and modified velocity
+    float uw[6][3];           // wall face velocities, faces x-, x+, y-, y+, z-, z+ (internal)
+    int moving;               // 1 if any wall moves
 };
 
 struct Codec {                // FP16S: power-of-two scales of the fp16 deviations
@@ -222,6 +224,7 @@ struct SiteWriter<L, StoreF32> {
         store_nt(base + off8, h, g);
     }
     __device__ __forceinline__ void finish() {}
+    __device__ __forceinline__ void shift_h_total(double) {}
 };
 
 template <class L>
@@ -256,6 +259,9 @@ struct SiteWriter<L, StoreF16S> {
             store_nt(dev_addr(I), __halves2half2(qh, qg));
         }
     }
+    // a moving wall changed an h value by d after the total was taken: the stored values
+    // must sum to the changed total
+    __device__ __forceinline__ void shift_h_total(double d) { th += d; }
     // R from the float64 complement, and the rest word from what R's rounding left over
     __device__ __forceinline__ void finish() {
         const float Rh = (float)(0.25 * (th - dh));
@@ -267,6 +273,58 @@ struct SiteWriter<L, StoreF16S> {
         store_nt(dev_addr(0), __halves2half2(__float2half_rn((float)resh * cd.sh),
                                              __float2half_rn(resg * cd.sg)));
     }
+};
+
+// c_I . u_w for the population a site with wall bits `solid` (Col.solid | ZRow.solid)
+// sends in direction I: u_w is the velocity of the wall face it crosses, the mean at an
+// edge or corner, 0 if it crosses none.
+template <class L, int I>
+__device__ __forceinline__ float wall_cu(const Model& m, uint32_t solid) {
+    constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+    float s = 0.f;
+    int n = 0;
+    auto face = [&](int f) {
+        s += (float)ex * m.uw[f][0] + (float)ey * m.uw[f][1] + (float)ez * m.uw[f][2];
+        ++n;
+    };
+    if constexpr (ex > 0) { if (solid & 2u) face(1); }
+    if constexpr (ex < 0) { if (solid & 1u) face(0); }
+    if constexpr (ey > 0) { if (solid & 8u) face(3); }
+    if constexpr (ey < 0) { if (solid & 4u) face(2); }
+    if constexpr (ez > 0) { if (solid & 32u) face(5); }
+    if constexpr (ez < 0) { if (solid & 16u) face(4); }
+    return n == 0 ? 0.f : (n == 1 ? s : (n == 2 ? 0.5f * s : s * (1.0f / 3.0f)));
+}
+
+// Writer for the sites of a wave that has wall sites of a moving wall (halfway
+// bounce-back with the momentum correction): the population a site sends into a wall
+// face is the one it pulls back next step, reduced here by 2 w_I (c_I . u_w)/T times the
+// site's phi (h) or rho (g).  `on` is uniform over the wave, so waves away from moving
+// walls skip the correction with scalar branches.
+template <class L, class W>
+struct WallWriter {
+    W& w;
+    const Model& m;
+    uint32_t solid;
+    float kh, kg;                 // phi 2/T and rho 2/T
+    bool on;
+    template <int I>
+    __device__ __forceinline__ void put(float h, float g) {
+        if constexpr (I != 0) {
+            if (on) {
+                const float k = L::w(I) * wall_cu<L, I>(m, solid);
+                // the h total follows the exact correction (a float product is exact
+                // in double): opposite corrections of a tangential pair cancel exactly,
+                // and at an edge or corner between walls moving differently, where they
+                // need not cancel, the total changes as in the method
+                w.shift_h_total(-(double)k * (double)kh);
+                h = fmaf(-k, kh, h);
+                g = fmaf(-k, kg, g);
+            }
+        }
+        w.template put<I>(h, g);
+    }
+    __device__ __forceinline__ void finish() { w.finish(); }
 };
 
 // ---------------------------------------------------------------------------

@@ -38,7 +38,9 @@ __device__ __forceinline__ void lds_barrier() {
 // One barrier per plane: plane z+2 is written into the slot plane z-2 used, which
 // no thread can still be reading once it has passed the barrier after plane z+1.
 // ---------------------------------------------------------------------------
-template <class L, class ST, int TX, int TY, int WALLS>
+// MOVING: the variant for moving walls (momentum-corrected bounce-back, WallWriter),
+// kept apart so that the other variants carry none of its registers.
+template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
 __global__ void __launch_bounds__(TX * TY)
 k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
        const char* __restrict__ src, char* __restrict__ dst) {
@@ -112,7 +114,16 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             });
             const Macro a = macros<L>(m, pn, gc);
             SiteWriter<L, ST> out(dst, own.base + r.base, G.S, cd, a.phi, lo_c);
-            collide_stream<L>(m, a, lo_c, hc, gc, out);
+            if constexpr (WALLS == WALLS_NONE || !MOVING) {
+                collide_stream<L>(m, a, lo_c, hc, gc, out);
+            } else {
+                const uint32_t solid = own.solid | r.solid;
+                const bool on =
+                    m.moving && __builtin_amdgcn_ballot_w64(solid != 0u) != 0ull;
+                WallWriter<L, SiteWriter<L, ST>> wout{out, m, solid, 6.0f * a.phi,
+                                                      6.0f * a.rho, on};
+                collide_stream<L>(m, a, lo_c, hc, gc, wout);
+            }
         }
     };
     for (int z = z0; z < zend; z += 2) {
@@ -450,19 +461,26 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(uint32_t N) { return dim3((N + 255u) / 256u); }
 
-template <class L, class ST, int WALLS, int TX, int TY>
+template <class L, class ST, int WALLS, int TX, int TY, bool MOVING = false>
 static hipError_t launch_tile(const Launch& a, const char* s, char* d) {
     const int ntx = (a.G.nx + TX - 1) / TX;
     const int nty = (a.G.ny + TY - 1) / TY;
     const int ntz = (a.G.nz + a.bz - 1) / a.bz;
     const int nblk = ntx * nty * ntz;
-    hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS>), dim3(nblk), dim3(TX * TY), 0, a.stream,
-                       a.G, a.m, a.cd, a.bz, ntx, nty, nblk, s, d);
+    hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING>), dim3(nblk), dim3(TX * TY), 0,
+                       a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk, s, d);
     return hipGetLastError();
 }
 
 template <class L, class ST, int WALLS>
 static hipError_t launch_step_t(const Launch& a, const char* s, char* d) {
+    if constexpr (WALLS != WALLS_NONE) {
+        // moving walls: one tile shape per lattice
+        if (a.m.moving) {
+            if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, s, d);
+            else return launch_tile<L, ST, WALLS, 64, 1, true>(a, s, d);
+        }
+    }
     if constexpr (L::USES_Y) {
         switch (a.tile) {
             case 1: return launch_tile<L, ST, WALLS, 64, 8>(a, s, d);

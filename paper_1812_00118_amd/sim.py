@@ -48,6 +48,13 @@ class Sim:
         p.storage = {"fp32": STORE_FP32, "fp16s": STORE_FP16S}[storage]
         sl = scale_log2 if scale_log2 is not None else default_scales(p.rho_H)
         p.scale_log2[0], p.scale_log2[1] = int(sl[0]), int(sl[1])
+        wu = cfg.get("wall_u")
+        if wu is not None:
+            wu = [float(v) for row in wu for v in row]
+            if len(wu) != 18:
+                raise ValueError("wall_u: 6 faces x 3 components")
+            for k in range(18):
+                p.wall_u[k] = wu[k]
         self.params = p
         self.Q = p.lattice
         self.D = 3 if p.lattice == 19 else 2

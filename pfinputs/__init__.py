@@ -117,7 +117,10 @@ def model_params(cfg):
     """The subset of a workload dict both sides take as model parameters."""
     keys = ("lattice", "shape", "bc", "rho_L", "rho_H", "nu_L", "nu_H", "M", "W",
             "sigma", "g", "eps", "hoc", "dtheta_C")
-    return {k: cfg[k] for k in keys}
+    d = {k: cfg[k] for k in keys}
+    if cfg.get("wall_u") is not None:       # wall face velocities, rows x-, x+, y-, y+, z-, z+
+        d["wall_u"] = np.asarray(cfg["wall_u"], dtype=np.float64).reshape(6, 3)
+    return d
 
 
 # ---------------------------------------------------------------------------

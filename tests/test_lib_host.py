@@ -109,6 +109,8 @@ def _params(**kw):
     for k, v in kw.items():
         if k == "scale":
             p.scale_log2[0], p.scale_log2[1] = v
+        elif k == "wall":                      # (face, component, velocity)
+            p.wall_u[3 * v[0] + v[1]] = v[2]
         else:
             setattr(p, k, v)
     return p
@@ -119,16 +121,28 @@ def _params(**kw):
                                  dict(nx=0), dict(lattice=9), dict(sigma=float("nan")),
                                  dict(storage=3), dict(storage=1, scale=(30, 0)),
                                  dict(hoc=2), dict(eps=0.0),
-                                 dict(nx=1024, ny=1024, nz=256)])
+                                 dict(nx=1024, ny=1024, nz=256),
+                                 dict(wall=(0, 1, 0.01)), dict(wall=(4, 2, 0.01)),
+                                 dict(wall=(5, 0, float("nan"))),
+                                 dict(lattice=9, nz=1, wall=(4, 0, 0.01))])
 def test_create_rejects_bad_params(L, bad):
-    """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1
-    and domains beyond 2^28 - 64 sites return PFLB_ERR_PARAM and leave *out NULL."""
+    """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1,
+    domains beyond 2^28 - 64 sites, and wall velocities on periodic faces, normal to
+    their face, non-finite or on faces D2Q9 does not have return PFLB_ERR_PARAM and
+    leave *out NULL."""
     p = _params(**bad)
     ctx = ctypes.c_void_p(1)
     rc = L.pflb_create(ctypes.byref(p), ctypes.byref(ctx))
     assert rc == -1
     assert not ctx.value
     assert L.pflb_required_bytes(ctypes.byref(p), 0) == 0
+
+
+def test_create_accepts_tangential_wall_velocity(L):
+    p = _params(wall=(5, 0, 0.01))            # z+ face moving along x
+    ctx = ctypes.c_void_p()
+    assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    L.pflb_destroy(ctx)
 
 
 def test_required_bytes_and_unbound_errors(L):
