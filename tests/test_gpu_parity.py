@@ -177,6 +177,52 @@ def test_couette_matches_oracle_and_closed_form(q, storage):
     assert abs(m1 - m0) <= (1e-6 * m0 if storage == "fp32" else 3e-11 * 24 * 2000)
 
 
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_two_phase_couette_paper_case(side):
+    """Section 3's two-phase Couette flow (water left, air right, L 100, mu_ratio 100,
+    nu_water 0.17, M 0.1, W 2.5, one wall moving with 1e-3): from the closed-form
+    profile, 2000 FP32 steps stay within 2% of the wall speed of it, and match the
+    oracle's run from the same start at the FP32 momentum bar."""
+    from scipy.integrate import cumulative_trapezoid
+    from oracle.lattice import T
+    L, W, nuw, rr, U = 100, 2.5, 0.17, 1000.0, 1e-3
+    nua = nuw * rr / 100.0
+    wall = _walls(xm=(0, U, 0)) if side == "left" else _walls(xp=(0, U, 0))
+    cfg = _cfg(9, (L, 1, 1), (W_, P_, P_), rho_H=rr, nu_L=nua, nu_H=nuw, W=W, sigma=0.0,
+               wall_u=wall)
+    x = np.arange(L, dtype=float)
+    prof = lambda q: 0.5 - 0.5 * np.tanh(2 * (q - (L / 2 - 0.5)) / W)
+    xi = np.linspace(-0.5, L - 0.5, 200001)
+    p = prof(xi)
+    rho = 1.0 + p * (rr - 1.0)
+    itau = 1 / (nua / T + 0.5) + p * (1 / (nuw / T + 0.5) - 1 / (nua / T + 0.5))
+    mu = rho * T * (1 / itau - 0.5)
+    I = cumulative_trapezoid(1 / mu, xi, initial=0)
+    frac = np.interp(x, xi, I / I[-1])
+    ua = U * (1.0 - frac) if side == "left" else U * frac
+    phi = prof(x).reshape(1, 1, L).astype(np.float32)
+    u = np.zeros((3, 1, 1, L), dtype=np.float32)
+    u[1, 0, 0] = ua
+    sim = _sim(cfg)
+    sim.init_fields(phi, u, np.zeros_like(phi))
+    sim.step(2000)
+    r = sim.read()
+    uy = _np(r["u"])[1].ravel()
+    prm = _oracle_params(cfg)
+    h, g = O.init(prm, phi.astype(np.float64), u.astype(np.float64))
+    h, g = O.run(prm, h, g, 2000)
+    ro = O.read(prm, h, g)
+    uo = ro["u"][1].ravel()
+    eJ = _jerr(_np(r["J"]), ro["J"][:2], rr)
+    print(f"\ncouette paper case {side}: |u - closed form| {np.abs(uy - ua).max() / U:.2e} U, "
+          f"|u - oracle| {np.abs(uy - uo).max() / U:.2e} U, relative J error {eJ:.1e}")
+    assert np.abs(uy - ua).max() <= 0.02 * U
+    # FP32 bar: relative momentum error 1e-4; the velocity on the air side (rho = 1, its
+    # populations ~ 1/36) carries FP32 rounding of ~1e-8 absolute = 1e-5 U
+    assert eJ <= 1e-4
+    assert np.abs(uy - uo).max() <= 1e-4 * U
+
+
 @pytest.mark.parametrize("q,shape,bc", [(9, (40, 31, 1), (P_, W_, P_)),
                                         (19, (19, 12, 14), (P_, P_, W_))])
 def test_state_round_trip_and_equilibrium(q, shape, bc):
