@@ -63,6 +63,9 @@ constexpr LayerDef LAYERS[NL] = {
     {"d0b", D0A, 0, 32, 32, 0, MODE_SAME, D0B, 0},
 };
 constexpr int HEAD_C = 32;
+static_assert(LAYERS[NL - 1].Cout == HEAD_C && LAYERS[NL - 1].mode == MODE_SAME &&
+                  LAYERS[NL - 1].pool_out < 0,
+              "the head is fused into the last layer at inference");
 
 // a pooled buffer is written whole by one layer at the level above the pooling layer that
 // reads it, and holds exactly the channels that layer would pool from its input buffer
@@ -261,13 +264,23 @@ int run_forward(pfsur_ctx* c, const void* x, float* out, int B, char* ws, bool t
             a.pout = reinterpret_cast<__bf16*>(ws + p.act[L.pool_out]);
             a.pout_cs = BUFS[L.pool_out].C;
         }
+        if (!training && l == NL - 1) {
+            // inference: the head runs in the last layer's epilogue, whose activations
+            // are then not stored (training keeps them for the backward pass)
+            a.out = nullptr;
+            a.head_w = c->master + PL.head;
+            a.head_b = c->master + PL.head + PFSUR_OUT_CH * HEAD_C;
+            a.head_out = out;
+        }
         SUR_TRY(conv3x3(a, st), "conv forward");
     }
-    const size_t P0 = (size_t)B * H * W;
-    SUR_TRY(head_fwd(reinterpret_cast<const __bf16*>(ws + p.act[D0B]), HEAD_C, 0,
-                     c->master + PL.head, c->master + PL.head + PFSUR_OUT_CH * HEAD_C, P0, out,
-                     st),
-            "head forward");
+    if (training) {
+        const size_t P0 = (size_t)B * H * W;
+        SUR_TRY(head_fwd(reinterpret_cast<const __bf16*>(ws + p.act[D0B]), HEAD_C, 0,
+                         c->master + PL.head, c->master + PL.head + PFSUR_OUT_CH * HEAD_C, P0,
+                         out, st),
+                "head forward");
+    }
     return PFLB_OK;
 }
 

@@ -22,7 +22,9 @@ struct GatherP {
 // Epilogue: v = acc + bias; zout (BF16 [P][Cout]) <- v; out (BF16 at channel stride
 // out_cs, offset out_c0) <- act ? silu(v) : v; fout (FP32 at f_cs, f_c0) <- v (or += v);
 // pout (BF16 [B][H/2][W/2][pout_cs], channels from 0; needs out and even H, W) <- the 2x2
-// average of what out receives, as the pooling gather computes it.
+// average of what out receives, as the pooling gather computes it.  head_out (FP32
+// [P][4]; 32-channel same-resolution layers only) <- the 1x1 head (head_w [4][32],
+// head_b [4]) applied to the BF16-rounded activations, as head_fwd computes it.
 struct ConvP {
     GatherP g;
     int B, H, W;
@@ -37,6 +39,9 @@ struct ConvP {
     int f_cs, f_c0, f_accum;
     __bf16* pout;
     int pout_cs;
+    const float* head_w;
+    const float* head_b;
+    float* head_out;
 };
 
 // part[split][Cout][9][C] = sum over the split's pixels of dz[p, co] in[p + off(tap), ci]

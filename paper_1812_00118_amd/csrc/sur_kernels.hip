@@ -314,18 +314,75 @@ __device__ __forceinline__ void tile_epilogue_staged(const ConvP& a, const f32x1
     }
 }
 
+// Partial sums of the 1x1 head over the 16 channels 8q + 4g + e (q, e = 0..3) of one
+// pixel, in that order.  A head output is (half(g = 0) + half(g = 1)) + b: the order
+// head_fwd uses and the one the fused epilogue gets, where lanes l and l + 32 of a wave
+// hold the two halves of a pixel's 32 channels.
+__device__ __forceinline__ void head_half(const float (&v)[16], int g, const float* wh,
+                                          float (&p)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                p[k] = fmaf(v[4 * q + e], wh[k * 32 + 8 * q + 4 * g + e], p[k]);
+}
+
+// Epilogue of the last 32-channel layer at inference: its activations (rounded to BF16,
+// as they would be stored) go straight into the 1x1 head; the layer's activation tensor
+// is never written.  sH holds the head's weights and biases.
+__device__ __forceinline__ void tile_epilogue_head(const ConvP& a, const f32x16 (&acc)[2][1],
+                                                   int b, int y0, int x0, int wave, int l32,
+                                                   int g, const float* sH) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const int y = y0 + 4 * wave + 2 * mb + (l32 >> 4), x = x0 + (l32 & 15);
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = 8 * q + 4 * g + e;
+                const float t = acc[mb][0][4 * q + e] + (a.bias ? a.bias[co] : 0.0f);
+                v[4 * q + e] = (float)(__bf16)(a.act ? silu(t) : t);
+            }
+        float p[4], o[4];
+        head_half(v, g, sH, p);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = __shfl_xor(p[k], 32);
+        if (g == 0 && y < a.H && x < a.W) {
+            const size_t px = ((size_t)b * a.H + y) * a.W + x;
+            reinterpret_cast<float4*>(a.head_out)[px] =
+                make_float4((p[0] + o[0]) + sH[128], (p[1] + o[1]) + sH[129],
+                            (p[2] + o[2]) + sH[130], (p[3] + o[3]) + sH[131]);
+        }
+    }
+}
+
 // 32-channel tiles use 45 KB of LDS, so three workgroups fit a CU when the registers
-// allow it; 64-channel tiles (64 KB) fit two.
-// STAGED selects the staged epilogue (always for 64-channel tiles; for 32-channel tiles
-// only when the layer also writes pooled output).
-template <int NT, int MODE, bool STAGED>
-__global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, int tiles_per_wg) {
+// allow it; 64-channel tiles (64 KB) fit two, and so does the fused-head variant, whose
+// head arithmetic needs the registers of two workgroups per CU.
+// Epilogue variants: staged (always for 64-channel tiles; for 32-channel tiles only when
+// the layer also writes pooled output), direct, or the fused 1x1 head.
+enum { EPI_DIRECT = 0, EPI_STAGED = 1, EPI_HEAD = 2 };
+template <int NT, int MODE, int EPI>
+__global__ void __launch_bounds__(256, (NT == 32 && EPI != EPI_HEAD) ? 3 : 2)
+k_conv_tiled(ConvP a, int tiles_per_wg) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
     constexpr int NB = NT / 32;
     __shared__ __align__(16) __bf16 sA[HP * HP * APAD];
     __shared__ __align__(16) __bf16 sB[NT * BPAD];
     static_assert(4 * 64 * OROW <= HP * HP * APAD, "epilogue staging must fit the patch buffer");
+    static_assert(EPI != EPI_HEAD || (NT == 32 && MODE == MODE_SAME), "head fusion: 32 channels");
+    __shared__ float sH[EPI == EPI_HEAD ? 4 * 32 + 4 : 1];
+    if constexpr (EPI == EPI_HEAD) {   // ordered before use by the first tile's barriers
+        for (int i = threadIdx.x; i < 4 * 32 + 4; i += 256)
+            sH[i] = i < 128 ? a.head_w[i] : a.head_b[i - 128];
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int l32 = lane & 31, g = lane >> 5;
     const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
@@ -448,9 +505,11 @@ __global__ void __launch_bounds__(256, NT == 32 ? 3 : 2) k_conv_tiled(ConvP a, i
         if (ch == nchunk - 1) {
             int b, y0, x0;
             tile_xy(t_beg + it / nchunk, b, y0, x0);
-            if constexpr (STAGED) {
+            if constexpr (EPI == EPI_STAGED) {
                 __syncthreads();                 // every wave is done reading the patch
                 tile_epilogue_staged<NB>(a, acc, b, y0, x0, co0, wave, l32, g, sA);
+            } else if constexpr (EPI == EPI_HEAD) {
+                tile_epilogue_head(a, acc, b, y0, x0, wave, l32, g, sH);
             } else {
                 tile_epilogue_direct<NB>(a, acc, b, y0, x0, co0, wave, l32, g);
             }
@@ -760,12 +819,18 @@ __global__ void k_head_fwd(const __bf16* __restrict__ act, int cs, int c0, const
                            const float* __restrict__ bh, size_t P, float* __restrict__ out) {
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
-    float o[4] = {bh[0], bh[1], bh[2], bh[3]};
-    for (int c = 0; c < 32; ++c) {
-        const float v = (float)act[p * cs + c0 + c];
-        for (int k = 0; k < 4; ++k) o[k] += v * wh[k * 32 + c];
-    }
-    for (int k = 0; k < 4; ++k) out[p * 4 + k] = o[k];
+    float v0[16], v1[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v0[4 * q + e] = (float)act[p * cs + c0 + 8 * q + e];
+            v1[4 * q + e] = (float)act[p * cs + c0 + 8 * q + 4 + e];
+        }
+    float p0[4], p1[4];
+    head_half(v0, 0, wh, p0);
+    head_half(v1, 1, wh, p1);
+    for (int k = 0; k < 4; ++k) out[p * 4 + k] = (p0[k] + p1[k]) + bh[k];
 }
 
 // head backward: dact[p, c] = sum_o dout[p, o] wh[o, c]; per block of HEAD_PPB pixels the
@@ -980,28 +1045,40 @@ static hipError_t launch_tiled(const ConvP& a, hipStream_t st) {
     const dim3 grid((ntile + per - 1) / per, nblk_n);
     if (a.pout && (a.H % 2 || a.W % 2 || !a.out || (NT == 32 && a.g.mode != MODE_SAME)))
         return hipErrorInvalidValue;
-    constexpr bool S64 = NT == 64;
+    constexpr int E = NT == 64 ? EPI_STAGED : EPI_DIRECT;
+    if (a.head_out) {
+        if constexpr (NT == 32) {
+            if (a.Cout != 32 || a.g.mode != MODE_SAME || a.out || a.zout || a.fout || a.pout ||
+                !a.head_w || !a.head_b)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_conv_tiled<32, MODE_SAME, EPI_HEAD>), grid, dim3(256), 0, st,
+                               a, per);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.g.mode == MODE_POOL)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL, S64>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_POOL, E>), grid, dim3(256), 0, st, a, per);
     else if (a.g.mode == MODE_UP)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP, S64>), grid, dim3(256), 0, st, a, per);
-    else if (!S64 && a.pout)
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, true>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_UP, E>), grid, dim3(256), 0, st, a, per);
+    else if (NT == 32 && a.pout)
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, EPI_STAGED>), grid, dim3(256), 0, st, a,
+                           per);
     else
-        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, S64>), grid, dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, E>), grid, dim3(256), 0, st, a, per);
     return hipGetLastError();
 }
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st) {
     if (a.g.C == 8 && a.g.mode == MODE_SAME && a.Cout % 32 == 0) {
-        if (a.pout) return hipErrorInvalidValue;
+        if (a.pout || a.head_out) return hipErrorInvalidValue;
         const dim3 grid(a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP), a.Cout / 32);
         hipLaunchKernelGGL(k_conv_first, grid, dim3(256), 0, st, a);
         return hipGetLastError();
     }
     if (a.g.C % 32 == 0 && a.Cout % 32 == 0)
         return a.Cout % 64 == 0 ? launch_tiled<64>(a, st) : launch_tiled<32>(a, st);
-    if (a.pout) return hipErrorInvalidValue;   // pooled output needs the tiled kernels
+    if (a.pout || a.head_out) return hipErrorInvalidValue;   // only the tiled kernels fuse
     const int P = a.B * a.H * a.W;
     hipLaunchKernelGGL(k_conv3x3, dim3((P + 255) / 256, (a.Cout + 31) / 32), dim3(256), 0, st, a);
     return hipGetLastError();
