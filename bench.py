@@ -60,7 +60,7 @@ def parse_args():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other storage mode and the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--sur-train-steps", type=int, default=2000)
+    ap.add_argument("--sur-train-steps", type=int, default=6000)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-profile", action="store_true",
                     help="only run 3 surrogate forward passes at batch 32 and 2 training steps "
@@ -224,7 +224,8 @@ def surrogate_block(train_steps):
                 lst.append(sm)
         torch.cuda.synchronize()
         t0 = time.time()
-        nf = sur.advance_guarded(a, 8, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=4)
+        nf = sur.advance_guarded(a, 8, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=4,
+                                 u_max=0.1)
         torch.cuda.synchronize()
         g_ms = (time.time() - t0) * 1e3
         t0 = time.time()
@@ -232,15 +233,24 @@ def surrogate_block(train_steps):
             sm.step(128)
         torch.cuda.synchronize()
         p_ms = (time.time() - t0) * 1e3
-        dphi = max((x.read(("phi",))["phi"] - y.read(("phi",))["phi"]).abs().max().item()
-                   for x, y in zip(a, b))
-        guarded[f"batch{nb}"] = {"contexts": nb, "windows": 8, "check_every": 4,
+        # phi error after 128 steps against the plain solver: the max-norm is set by the
+        # worst interface (a sub-site shift of a steep profile), so the mean and the share
+        # of sites off by more than 0.1 are reported beside it
+        diffs = torch.stack([(x.read(("phi",))["phi"] - y.read(("phi",))["phi"]).abs()
+                             for x, y in zip(a, b)])
+        dphi = diffs.max().item()
+        mphi = diffs.mean().item()
+        frac = (diffs > 0.1).float().mean().item()
+        guarded[f"batch{nb}"] = {"contexts": nb, "windows": 8, "check_every": 4, "u_max": 0.1,
                                  "fallbacks": nf, "fallback_rate": round(nf / (8 * nb), 4),
                                  "wall_ms": round(g_ms, 3), "plain_lb_ms": round(p_ms, 3),
                                  "speedup": round(p_ms / g_ms, 3),
-                                 "max_abs_dphi_vs_lb_after_128_steps": dphi}
+                                 "max_abs_dphi_vs_lb_after_128_steps": dphi,
+                                 "mean_abs_dphi_vs_lb_after_128_steps": mphi,
+                                 "share_of_sites_abs_dphi_over_0.1": frac}
         print(f"[bench] guarded batch {nb}: {g_ms:.1f} ms vs plain {p_ms:.1f} ms, fallbacks "
-              f"{nf}/{8 * nb}, max|dphi| {dphi:.3e}", file=sys.stderr, flush=True)
+              f"{nf}/{8 * nb}, max|dphi| {dphi:.3e}, mean|dphi| {mphi:.2e}, "
+              f"sites |dphi|>0.1 {frac:.2e}", file=sys.stderr, flush=True)
         del a, b
     ach = flops * 32 / (fwd[32] * 1e-3) / 1e12
     return {

@@ -105,10 +105,13 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
 /* Guarded advance of a batch of D2Q9 lattice Boltzmann contexts by `windows` x 16 steps.
  * For each window the surrogate predicts, in one batched forward pass, the state 16
  * steps ahead of every context; the prediction for context k is accepted when
- * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)| and, on every
+ * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)|, when its largest speed
+ * max |J| / (rho_L + phi (rho_H - rho_L)) is at most u_max (a state handed over with an
+ * unphysical speed would make the plain steps after it unstable) and, on every
  * check_every-th window (0: never), when max|phi_out - phi_LB| <= phi_tol against 16
  * plain steps taken from the same state.  An accepted prediction becomes the context's
- * new state (pflb_reconstruct); otherwise the 16 plain steps are taken.
+ * new state (pflb_reconstruct); otherwise the 16 plain steps are taken.  A context whose
+ * state is non-finite at the start of a window ends the call with PFLB_ERR_NONFINITE.
  *   lbs[batch]  contexts (periodic, nx = W, ny = H), batch <= max_batch
  *   lrr[batch]  host array of log10(rho_H/rho_L) per context
  *   work        pfsur_guard_work_bytes(cfg, batch) bytes of device memory, 256-aligned
@@ -118,14 +121,14 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
  * between contexts. */
 size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch);
 int pflb_advance_guarded(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int windows,
-                         const double* lrr, double mass_tol, double phi_tol, int check_every,
-                         int* n_fallback, void* work, void* stream);
+                         const double* lrr, double mass_tol, double phi_tol, double u_max,
+                         int check_every, int* n_fallback, void* work, void* stream);
 
 /* The accept rule of pflb_advance_guarded, a pure host function (1 accept, 0 reject):
- * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums) and,
- * when checked != 0, phi_err <= phi_tol. */
-int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, int checked,
-                       double phi_err, double phi_tol);
+ * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums),
+ * speed <= u_max (false if non-finite) and, when checked != 0, phi_err <= phi_tol. */
+int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, double speed,
+                       double u_max, int checked, double phi_err, double phi_tol);
 
 /* Building blocks, stateless (no context): one circular-padded 3x3 convolution as the
  * network computes it, for testing and reuse.

@@ -83,10 +83,11 @@ _SIGS = {
     "pfsur_guard_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int]),
     "pflb_advance_guarded": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_double), ctypes.c_double,
-                                            ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int), _vp, _vp]),
     "pfsur_guard_accept": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_double]),
     "pfsur_conv_fwd": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
                                       _vp, _vp]),

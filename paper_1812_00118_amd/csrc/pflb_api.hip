@@ -440,6 +440,8 @@ int pflb_ctx_info(const pflb_ctx* c, CtxInfo* out) {
     for (int a = 0; a < 3; ++a) out->bc[a] = c->p.bc[a];
     out->N = c->N;
     out->bound = c->bound;
+    out->rho_L = c->p.rho_L;
+    out->rho_H = c->p.rho_H;
     return PFLB_OK;
 }
 

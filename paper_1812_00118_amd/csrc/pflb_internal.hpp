@@ -43,6 +43,7 @@ struct CtxInfo {
     int bc[3];
     uint32_t N;
     bool bound;
+    double rho_L, rho_H;
 };
 size_t mass_scratch_bytes();
 size_t mass_result_offset();

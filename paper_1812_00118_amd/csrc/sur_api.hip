@@ -578,10 +578,11 @@ int pfsur_gradients(pfsur_ctx* c, const void* x, const float* y, int batch, floa
     return PFLB_OK;
 }
 
-int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, int checked,
-                       double phi_err, double phi_tol) {
+int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, double speed,
+                       double u_max, int checked, double phi_err, double phi_tol) {
     if (!isfinite(sum_in) || !isfinite(sum_out)) return 0;
     if (!(fabs(sum_out - sum_in) <= mass_tol * fabs(sum_in))) return 0;
+    if (!(speed <= u_max)) return 0;
     if (checked && !(phi_err <= phi_tol)) return 0;
     return 1;
 }
@@ -593,12 +594,13 @@ namespace {
 constexpr int GUARD_BLOCKS = 256;
 
 struct GuardPlan {
-    size_t phi, P, J, phi_lb, x, out, ws, recon, dpart, fpart, total;
+    size_t phi, P, J, phi_lb, x, out, ws, recon, dpart, fpart, upart, total;
 };
 
-// dpart holds the per-block sums before and after the prediction ([2][n][blocks]) and
-// fpart the per-block phi differences of checked windows ([n][blocks]), so that one
-// read-back per window serves every decision
+// dpart holds the per-block sums before and after the prediction ([2][n][blocks]), fpart
+// the per-block phi differences of checked windows and upart the per-block largest
+// predicted speeds (both [n][blocks]), so that one read-back per window serves every
+// decision
 GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     GuardPlan g;
     const size_t HW = (size_t)cfg->H * cfg->W;
@@ -618,6 +620,7 @@ GuardPlan guard_plan(const pfsur_cfg* cfg, int n) {
     g.recon = take((size_t)std::min(n, pflb::BATCH_MAX) * 2 * 9 * HW * 4);
     g.dpart = take((size_t)2 * n * GUARD_BLOCKS * 8);
     g.fpart = take((size_t)n * GUARD_BLOCKS * 4);
+    g.upart = take((size_t)n * GUARD_BLOCKS * 4);
     g.total = o;
     return g;
 }
@@ -632,13 +635,14 @@ size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch) {
 }
 
 int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
-                         const double* lrr, double mass_tol, double phi_tol, int check_every,
-                         int* n_fallback, void* work, void* stream) {
+                         const double* lrr, double mass_tol, double phi_tol, double u_max,
+                         int check_every, int* n_fallback, void* work, void* stream) {
     if (!c) return PFLB_ERR_PARAM;
     if (!lbs || !lrr || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
     if (n < 1 || n > c->cfg.max_batch) return fail(c, PFLB_ERR_PARAM, "batch must be in [1, max_batch]");
     if (((uintptr_t)work & 255u)) return fail(c, PFLB_ERR_ALIGN, "work must be 256-byte aligned");
     if (windows < 0 || check_every < 0) return fail(c, PFLB_ERR_PARAM, "negative count");
+    std::vector<RhoTab> rho((n + LRR_MAX - 1) / LRR_MAX);
     for (int k = 0; k < n; ++k) {
         pflb::CtxInfo info;
         if (!lbs[k] || pflb_ctx_info(lbs[k], &info) != PFLB_OK || !info.bound)
@@ -646,6 +650,8 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if (info.q != 9 || info.nx != c->cfg.W || info.ny != c->cfg.H ||
             info.bc[0] != PFLB_BC_PERIODIC || info.bc[1] != PFLB_BC_PERIODIC)
             return fail(c, PFLB_ERR_PARAM, "lattices must be D2Q9, periodic, nx = W, ny = H");
+        rho[k / LRR_MAX].rl[k % LRR_MAX] = (float)info.rho_L;
+        rho[k / LRR_MAX].rd[k % LRR_MAX] = (float)(info.rho_H - info.rho_L);
     }
     hipStream_t st = (hipStream_t)stream;
     const GuardPlan g = guard_plan(&c->cfg, n);
@@ -658,9 +664,10 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
     float* out = reinterpret_cast<float*>(w + g.out);
     double* dpart = reinterpret_cast<double*>(w + g.dpart);
     float* fpart = reinterpret_cast<float*>(w + g.fpart);
+    float* upart = reinterpret_cast<float*>(w + g.upart);
     const size_t nb = (size_t)n * GUARD_BLOCKS;
     std::vector<double> hd(2 * nb);
-    std::vector<float> hf(nb);
+    std::vector<float> hf(nb), hu(nb);
     // per-context field pointers of the batched read-out and hand-over
     std::vector<float*> fphi(n), fP(n), fJ(n), flb(n);
     for (int k = 0; k < n; ++k) {
@@ -684,6 +691,13 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if ((r = run_forward(c, w + g.x, out, n, w + g.ws, false, st))) return r;
         if ((r = pfsur_apply(c, out, phi, P, J, n, st))) return r;
         SUR_TRY(sum_field(phi, n, HW, dpart + nb, GUARD_BLOCKS, st), "field sum");
+        for (int k0 = 0; k0 < n; k0 += LRR_MAX)
+            SUR_TRY(maxspeed(phi + k0 * HW, J + 2 * k0 * HW, rho[k0 / LRR_MAX],
+                             std::min(LRR_MAX, n - k0), HW, upart + (size_t)k0 * GUARD_BLOCKS,
+                             GUARD_BLOCKS, st),
+                    "speed check");
+        SUR_TRY(hipMemcpyAsync(hu.data(), upart, nb * 4, hipMemcpyDeviceToHost, st),
+                "speed check");
         const bool checked = check_every > 0 && (win + 1) % check_every == 0;
         if (checked) {
             // the plain steps from the same states are the reference; if a prediction
@@ -700,17 +714,28 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         SUR_TRY(hipMemcpyAsync(hd.data(), dpart, 2 * nb * 8, hipMemcpyDeviceToHost, st),
                 "field sums");
         SUR_TRY(hipStreamSynchronize(st), "guard read-back");
+        // a context whose state went non-finite ends the call before any context changes
+        for (int k = 0; k < n; ++k) {
+            double s_in = 0.0;
+            for (int b = 0; b < GUARD_BLOCKS; ++b) s_in += hd[(size_t)k * GUARD_BLOCKS + b];
+            if (!isfinite(s_in))
+                return fail(c, PFLB_ERR_NONFINITE,
+                            "lattice state of context " + std::to_string(k) + " is non-finite");
+        }
         acc_ctx.clear();
         acc_phi.clear();
         acc_P.clear();
         acc_J.clear();
         for (int k = 0; k < n; ++k) {
             // fixed-order host sums of the per-block partials (deterministic)
-            double s_in = 0.0, s_out = 0.0, err = 0.0;
+            double s_in = 0.0, s_out = 0.0, err = 0.0, speed = 0.0;
             for (int b = 0; b < GUARD_BLOCKS; ++b) {
                 s_in += hd[(size_t)k * GUARD_BLOCKS + b];
                 s_out += hd[nb + (size_t)k * GUARD_BLOCKS + b];
+                const float e = hu[(size_t)k * GUARD_BLOCKS + b];
+                speed = e > speed || e != e ? e : speed;
             }
+            if (speed != speed) speed = INFINITY;
             if (checked) {
                 for (int b = 0; b < GUARD_BLOCKS; ++b) {
                     const float e = hf[(size_t)k * GUARD_BLOCKS + b];
@@ -718,7 +743,7 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
                 }
                 if (err != err) err = INFINITY;
             }
-            if (pfsur_guard_accept(s_in, s_out, mass_tol, checked, err, phi_tol)) {
+            if (pfsur_guard_accept(s_in, s_out, mass_tol, speed, u_max, checked, err, phi_tol)) {
                 acc_ctx.push_back(lbs[k]);
                 acc_phi.push_back(fphi[k]);
                 acc_P.push_back(fP[k]);

@@ -63,6 +63,10 @@ constexpr int LRR_MAX = 64;
 struct LrrTab {
     float v[LRR_MAX];
 };
+// per-sample densities rho = rl + phi rd of one speed-check launch
+struct RhoTab {
+    float rl[LRR_MAX], rd[LRR_MAX];
+};
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st);
 hipError_t wgrad(const WgradP& a, hipStream_t st);
@@ -97,5 +101,9 @@ hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi,
 hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part, int nblk,
                    hipStream_t st);
 hipError_t sum_field(const float* a, int B, size_t n, double* part, int nblk, hipStream_t st);
+// per block, max over sites of |J| / (rl + phi rd) for sample blockIdx.y of B <= LRR_MAX
+// (phi [B][n], J [B][2][n]): part[sample][block]
+hipError_t maxspeed(const float* phi, const float* J, const RhoTab& rho, int B, size_t n,
+                    float* part, int nblk, hipStream_t st);
 
 }  // namespace pfsur

@@ -993,21 +993,52 @@ __global__ void k_apply(const float* __restrict__ out, Norm nm, int B, size_t HW
 }
 
 // max |a - b| per block for sample blockIdx.y of a batch of fields of n values:
-// part[sample][block]
+// part[sample][block]; a non-finite difference propagates (fmaxf would drop it)
 __global__ void __launch_bounds__(256) k_maxdiff(const float* __restrict__ a, const float* __restrict__ b,
                                                  size_t n, float* __restrict__ part) {
     __shared__ float sred[256];
     const size_t off = (size_t)blockIdx.y * n;
     float m = 0.f;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-        m = fmaxf(m, fabsf(a[off + i] - b[off + i]));
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float d = fabsf(a[off + i] - b[off + i]);
+        m = d > m || d != d ? d : m;
+    }
     sred[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < (unsigned)w) sred[threadIdx.x] = fmaxf(sred[threadIdx.x], sred[threadIdx.x + w]);
+        if (threadIdx.x < (unsigned)w) {
+            const float o = sred[threadIdx.x + w];
+            if (o > sred[threadIdx.x] || o != o) sred[threadIdx.x] = o;
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sred[0];
+}
+
+// largest speed |J| / rho(phi) per block for sample blockIdx.y (phi [B][n], J [B][2][n]):
+// part[sample][block]; a non-finite speed propagates
+__global__ void __launch_bounds__(256) k_maxspeed(const float* __restrict__ phi,
+                                                  const float* __restrict__ J, RhoTab rho,
+                                                  size_t n, float* __restrict__ part) {
+    __shared__ float sred[256];
+    const size_t b = blockIdx.y;
+    const float rl = rho.rl[b], rd = rho.rd[b];
+    float m = 0.f;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float jx = J[2 * b * n + i], jy = J[(2 * b + 1) * n + i];
+        const float u = sqrtf(jx * jx + jy * jy) / fmaf(phi[b * n + i], rd, rl);
+        m = u > m || u != u ? u : m;
+    }
+    sred[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) {
+            const float o = sred[threadIdx.x + w];
+            if (o > sred[threadIdx.x] || o != o) sred[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = sred[0];
 }
 
 // sum of a float field in float64, per block, for sample blockIdx.y of a batch of
@@ -1216,6 +1247,13 @@ hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part,
         hipLaunchKernelGGL(k_maxdiff, dim3(nblk, nb), dim3(256), 0, st, a + b0 * n, b + b0 * n, n,
                            part + (size_t)b0 * nblk);
     }
+    return hipGetLastError();
+}
+
+hipError_t maxspeed(const float* phi, const float* J, const RhoTab& rho, int B, size_t n,
+                    float* part, int nblk, hipStream_t st) {
+    if (B < 1 || B > LRR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_maxspeed, dim3(nblk, B), dim3(256), 0, st, phi, J, rho, n, part);
     return hipGetLastError();
 }
 

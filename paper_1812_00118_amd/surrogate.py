@@ -179,10 +179,14 @@ class Surrogate:
         return g, float(loss.value)
 
     # ------------------------------------------------------------------ hand-over
-    def advance_guarded(self, sims, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0):
+    def advance_guarded(self, sims, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0,
+                        u_max=0.1):
         """Advance D2Q9 periodic Sims (one, or a list of at most max_batch) by windows x 16
         steps with one batched forward pass per window; returns the number of (window,
-        sim) pairs that fell back to the plain steps."""
+        sim) pairs that fell back to the plain steps.  A prediction is rejected when it
+        changes sum(phi) by more than mass_tol (relative), when its largest speed exceeds
+        u_max, or (on every check_every-th window) when it is more than phi_tol from the
+        plain steps."""
         if not isinstance(sims, (list, tuple)):
             sims, lrr = [sims], [lrr]
         n = len(sims)
@@ -195,7 +199,7 @@ class Surrogate:
         lr = (ctypes.c_double * n)(*[float(v) for v in lrr])
         nf = ctypes.c_int()
         self._check(self.L.pflb_advance_guarded(ctxs, n, self.ctx, int(windows), lr,
-                                                float(mass_tol), float(phi_tol),
+                                                float(mass_tol), float(phi_tol), float(u_max),
                                                 int(check_every), ctypes.byref(nf), wp,
                                                 _stream(self.device)))
         return int(nf.value)

@@ -336,12 +336,40 @@ def test_guard_forced_fallback_equals_plain_steps(sur_mod):
     assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
 
 
+def test_guard_speed_check_forces_fallback(sur_mod):
+    """A bound on the predicted speed below what the flow reaches rejects every window
+    (mass and phi checks open): the result is exactly the plain steps."""
+    s = _net(sur_mod, 64)
+    a, cfg = _drops_sim()
+    b, _ = _drops_sim()
+    lrr = float(np.log10(cfg["rho_H"]))
+    nf = s.advance_guarded(a, 2, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0, u_max=1e-9)
+    b.step(32)
+    assert nf == 2 and a.steps == 32
+    assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+
+
+def test_guard_stops_on_a_non_finite_state(sur_mod):
+    """A NaN written into one population from the host: the guarded advance reports
+    PFLB_ERR_NONFINITE instead of carrying the state on."""
+    from paper_1812_00118_amd._lib import PflbError
+    s = _net(sur_mod, 64)
+    a, cfg = _drops_sim()
+    h, g = (t.clone() for t in a.get_state())
+    h[3, 0, 10, 20] = float("nan")
+    a.set_state(h, g)
+    with pytest.raises(PflbError) as e:
+        s.advance_guarded(a, 1, float(np.log10(cfg["rho_H"])))
+    assert e.value.code == -5
+
+
 def test_guard_accepts_and_hands_over_the_prediction(sur_mod):
     s = _net(sur_mod, 64)
     a, cfg = _drops_sim()
     b, _ = _drops_sim()
     lrr = float(np.log10(cfg["rho_H"]))
-    nf = s.advance_guarded(a, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0)
+    nf = s.advance_guarded(a, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0,
+                           u_max=1e30)
     assert nf == 0 and a.steps == 16
     f = b.read(("phi", "P", "J"))
     phi, P, J = f["phi"].reshape(1, 64, 64), f["P"].reshape(1, 64, 64), f["J"].reshape(1, 2, 64, 64)
@@ -351,7 +379,8 @@ def test_guard_accepts_and_hands_over_the_prediction(sur_mod):
     assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
     # with a check every window the accepted state is the same prediction
     c, _ = _drops_sim()
-    nf = s.advance_guarded(c, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=1)
+    nf = s.advance_guarded(c, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=1,
+                           u_max=1e30)
     assert nf == 0 and c.steps == 16
     assert torch.equal(a.read(("phi",))["phi"], c.read(("phi",))["phi"])
 
@@ -364,11 +393,12 @@ def test_batched_guard_matches_single_context_guard(sur_mod):
     cfgs = [pfinputs_drops(k) for k in seeds]
     lrr = [float(np.log10(c["rho_H"])) for c in cfgs]
     batch = [_drops_sim(seed=k)[0] for k in seeds]
-    nf = s.advance_guarded(batch, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0)
+    nf = s.advance_guarded(batch, 1, lrr, mass_tol=1e30, phi_tol=1e30, check_every=0,
+                           u_max=1e30)
     assert nf == 0
     for k, seed in enumerate(seeds):
         one, _ = _drops_sim(seed=seed)
-        assert s.advance_guarded(one, 1, lrr[k], mass_tol=1e30, phi_tol=1e30) == 0
+        assert s.advance_guarded(one, 1, lrr[k], mass_tol=1e30, phi_tol=1e30, u_max=1e30) == 0
         assert torch.equal(batch[k].read(("phi",))["phi"], one.read(("phi",))["phi"])
     plain = [_drops_sim(seed=k)[0] for k in seeds]
     fb = [_drops_sim(seed=k)[0] for k in seeds]
@@ -394,12 +424,12 @@ def test_batched_guard_over_more_contexts_than_one_launch_holds(sur_mod):
     for check_every in (0, 1):
         batch = [_drops_sim(n=n, seed=k)[0] for k in seeds]
         nf = s.advance_guarded(batch, 1, lrr, mass_tol=1e30, phi_tol=1e30,
-                               check_every=check_every)
+                               check_every=check_every, u_max=1e30)
         assert nf == 0
         for k in (0, 15, 16):
             one, _ = _drops_sim(n=n, seed=seeds[k])
             assert s.advance_guarded(one, 1, lrr[k], mass_tol=1e30, phi_tol=1e30,
-                                     check_every=check_every) == 0
+                                     check_every=check_every, u_max=1e30) == 0
             assert batch[k].steps == one.steps == 16
             assert torch.equal(batch[k].read(("phi",))["phi"], one.read(("phi",))["phi"])
             assert torch.equal(batch[k].read(("J",))["J"], one.read(("J",))["J"])

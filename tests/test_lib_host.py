@@ -68,8 +68,11 @@ def test_surrogate_workspace_planning(L):
 
 def test_guard_accept_rule(L):
     """The fallback decision is a pure host function of two sums, the relative mass
-    tolerance and an optional phi error: forced from the host with synthetic values."""
-    acc = L.pfsur_guard_accept
+    tolerance, the largest predicted speed and an optional phi error: forced from the
+    host with synthetic values."""
+    a = L.pfsur_guard_accept
+    acc = lambda s_in, s_out, tol, chk, err, phi_tol, speed=0.02, u_max=0.1: a(
+        s_in, s_out, tol, speed, u_max, chk, err, phi_tol)
     s = 4096.0
     assert acc(s, s * (1 + 0.9e-3), 1e-3, 0, 0.0, 0.0) == 1
     assert acc(s, s * (1 + 1e-2), 1e-3, 0, 0.0, 0.0) == 0           # injected +1e-2 sum(phi)
@@ -81,6 +84,10 @@ def test_guard_accept_rule(L):
     assert acc(s, s, 1e-3, 1, float("nan"), 0.05) == 0
     assert acc(s, s, 1e-3, 0, float("nan"), 0.05) == 1              # unchecked: error unused
     assert acc(s, s + 1e-9, 0.0, 0, 0.0, 0.0) == 0                  # zero tolerance
+    assert acc(s, s, 1e-3, 0, 0.0, 0.0, speed=0.11) == 0            # unphysical speed
+    assert acc(s, s, 1e-3, 0, 0.0, 0.0, speed=float("inf")) == 0
+    assert acc(s, s, 1e-3, 0, 0.0, 0.0, speed=float("nan")) == 0
+    assert acc(s, s, 1e-3, 0, 0.0, 0.0, speed=0.1) == 1             # at the bound
 
 
 def test_conv_primitives_reject_bad_shapes(L):
