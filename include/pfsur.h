@@ -69,27 +69,32 @@ int pfsur_get_params(pfsur_ctx* ctx, float* host);
  * activations plus the backward buffers). */
 size_t pfsur_workspace_bytes(const pfsur_cfg* cfg, int batch, int training);
 
-/* Pack a batch of solver fields into the network input x (BF16 NHWC, PFSUR_IN_CH):
+/* Pack a batch of solver fields into the network input x (BF16 NHWC, PFSUR_IN_CH).  The
+ * network works with the velocity u = J / rho(phi), rho(phi) = rho_L + clamp(phi, 0, 1)
+ * (rho_H - rho_L), not with the momentum J, whose values span the density ratio: channels
+ * (phi - s0) k0, (P - s1) k1, (u_x - s2) k2, (u_y - s3) k3 (s = in_shift, k = in_scale),
+ * log10(rho_H/rho_L) lrr_scale, then zeros.
  *   phi, P [batch][H][W], J [batch][2][H][W] (the pflb_read layout per sample),
- *   lrr[batch] host array of log10(rho_H/rho_L). */
+ *   rho[batch][2] host array of (rho_L, rho_H) per sample, finite and > 0. */
 int pfsur_pack(pfsur_ctx* ctx, const float* phi, const float* P, const float* J,
-               const double* lrr, int batch, void* x, void* stream);
+               const double* rho, int batch, void* x, void* stream);
 
 /* Training target from two solver states of the same batch, 16 steps apart:
- * y [batch][H][W][4] FP32, y_c = (field1_c - field0_c) / out_scale[c] (layouts as in
- * pfsur_pack). */
+ * y [batch][H][W][4] FP32, y_c = (f1_c - f0_c) / out_scale[c] for f = (phi, P, u_x, u_y)
+ * (layouts and rho as in pfsur_pack). */
 int pfsur_pack_target(pfsur_ctx* ctx, const float* phi0, const float* P0, const float* J0,
-                      const float* phi1, const float* P1, const float* J1, int batch, float* y,
-                      void* stream);
+                      const float* phi1, const float* P1, const float* J1, const double* rho,
+                      int batch, float* y, void* stream);
 
 /* out [batch][H][W][4] FP32 = network(x) (x: BF16 NHWC [batch][H][W][8]). */
 int pfsur_forward(pfsur_ctx* ctx, const void* x, float* out, int batch, void* workspace,
                   void* stream);
 
-/* Apply a predicted residual: field_c += out_c * out_scale[c] in place, for
- * phi, P [batch][H][W] and J [batch][2][H][W]. */
-int pfsur_apply(pfsur_ctx* ctx, const float* out, float* phi, float* P, float* J, int batch,
-                void* stream);
+/* Apply a predicted residual in place: phi and P advance by out_c * out_scale[c], the
+ * velocity J / rho(phi) likewise, and J becomes rho(phi_new) u_new (phi, P [batch][H][W],
+ * J [batch][2][H][W]; rho as in pfsur_pack). */
+int pfsur_apply(pfsur_ctx* ctx, const float* out, float* phi, float* P, float* J,
+                const double* rho, int batch, void* stream);
 
 /* One training step on (x, y): forward, MSE loss against y [batch][H][W][4] FP32,
  * backward, Adam with learning rate lr (beta1 0.9, beta2 0.999, eps 1e-8).  *loss
@@ -102,18 +107,20 @@ int pfsur_train_step(pfsur_ctx* ctx, const void* x, const float* y, int batch, f
 int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, float* host_grad,
                     float* loss, void* workspace, void* stream);
 
-/* Guarded advance of a batch of D2Q9 lattice Boltzmann contexts by `windows` x 16 steps.
+/* Guarded advance of a batch of D2Q9 lattice Boltzmann contexts by `windows` x 16 steps
+ * (the surrogate's densities per context are the contexts' own rho_L, rho_H).
  * For each window the surrogate predicts, in one batched forward pass, the state 16
  * steps ahead of every context; the prediction for context k is accepted when
- * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)|, when its largest speed
- * max |J| / (rho_L + phi (rho_H - rho_L)) is at most u_max (a state handed over with an
- * unphysical speed would make the plain steps after it unstable) and, on every
+ * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)|, when the largest speed the
+ * hand-over would give, max |J| / rho' with rho' = rho_L + phi (rho_H - rho_L) +
+ * rho_dif lap(phi) / 4 (Eq. 13's density where the context uses it; rho' <= 0 counts as
+ * infinite), is at most u_max (a state handed over with an unphysical speed would make
+ * the plain steps after it unstable) and, on every
  * check_every-th window (0: never), when max|phi_out - phi_LB| <= phi_tol against 16
  * plain steps taken from the same state.  An accepted prediction becomes the context's
  * new state (pflb_reconstruct); otherwise the 16 plain steps are taken.  A context whose
  * state is non-finite at the start of a window ends the call with PFLB_ERR_NONFINITE.
  *   lbs[batch]  contexts (periodic, nx = W, ny = H), batch <= max_batch
- *   lrr[batch]  host array of log10(rho_H/rho_L) per context
  *   work        pfsur_guard_work_bytes(cfg, batch) bytes of device memory, 256-aligned
  *   *n_fallback (host) number of (window, context) pairs that fell back.
  * Synchronous.  If an error is returned part-way, each context holds a valid state (the
@@ -121,8 +128,8 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
  * between contexts. */
 size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch);
 int pflb_advance_guarded(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int windows,
-                         const double* lrr, double mass_tol, double phi_tol, double u_max,
-                         int check_every, int* n_fallback, void* work, void* stream);
+                         double mass_tol, double phi_tol, double u_max, int check_every,
+                         int* n_fallback, void* work, void* stream);
 
 /* The accept rule of pflb_advance_guarded, a pure host function (1 accept, 0 reject):
  * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums),

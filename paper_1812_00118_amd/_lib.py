@@ -73,17 +73,19 @@ _SIGS = {
     "pfsur_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int, ctypes.c_int]),
     "pfsur_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_int, _vp, _vp]),
-    "pfsur_pack_target": (ctypes.c_int, [_vp] * 7 + [ctypes.c_int, _vp, _vp]),
+    "pfsur_pack_target": (ctypes.c_int, [_vp] * 7 + [ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.c_int, _vp, _vp]),
     "pfsur_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
-    "pfsur_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "pfsur_apply": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_int, _vp]),
     "pfsur_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
                                         ctypes.POINTER(ctypes.c_float), _vp, _vp]),
     "pfsur_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp,
                                        ctypes.POINTER(ctypes.c_float), _vp, _vp]),
     "pfsur_guard_work_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int]),
     "pflb_advance_guarded": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int,
-                                            ctypes.POINTER(ctypes.c_double), ctypes.c_double,
-                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int), _vp, _vp]),
     "pfsur_guard_accept": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int,

@@ -442,6 +442,7 @@ int pflb_ctx_info(const pflb_ctx* c, CtxInfo* out) {
     out->bound = c->bound;
     out->rho_L = c->p.rho_L;
     out->rho_H = c->p.rho_H;
+    out->hoc = c->p.hoc;
     return PFLB_OK;
 }
 

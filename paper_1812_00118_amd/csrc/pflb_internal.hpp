@@ -44,6 +44,7 @@ struct CtxInfo {
     uint32_t N;
     bool bound;
     double rho_L, rho_H;
+    int hoc;
 };
 size_t mass_scratch_bytes();
 size_t mass_result_offset();

@@ -373,6 +373,27 @@ int check_batch(pfsur_ctx* c, int batch) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+// (rho_L, rho_H) per sample, host array [n][2]: finite and positive
+bool dens_ok(const double* rho, int n) {
+    for (int k = 0; k < 2 * n; ++k)
+        if (!(isfinite(rho[k]) && rho[k] > 0.0)) return false;
+    return true;
+}
+
+// densities of samples [b0, b0 + nb) for one launch
+DensTab dens_tab(const double* rho, int b0, int nb) {
+    DensTab d;
+    for (int k = 0; k < LRR_MAX; ++k) {
+        const double rl = k < nb ? rho[2 * (b0 + k)] : 1.0;
+        const double rh = k < nb ? rho[2 * (b0 + k) + 1] : 1.0;
+        d.rl[k] = (float)rl;
+        d.rd[k] = (float)(rh - rl);
+        d.lrr[k] = (float)log10(rh / rl);
+        d.beta[k] = 0.0f;
+    }
+    return d;
+}
+
 // forward + backward; *loss (host) = mean squared error of the forward pass
 int forward_backward(pfsur_ctx* c, const void* x, const float* y, int batch, float* loss,
                      char* ws, hipStream_t st) {
@@ -490,39 +511,42 @@ size_t pfsur_workspace_bytes(const pfsur_cfg* cfg, int batch, int training) {
     return make_plan(cfg->H, cfg->W, batch, training != 0).total;
 }
 
-int pfsur_pack(pfsur_ctx* c, const float* phi, const float* P, const float* J, const double* lrr,
+int pfsur_pack(pfsur_ctx* c, const float* phi, const float* P, const float* J, const double* rho,
                int batch, void* x, void* stream) {
     int r = check_batch(c, batch);
     if (r) return r;
-    if (!phi || !P || !J || !lrr || !x) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
+    if (!phi || !P || !J || !rho || !x) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
     if (!aligned16(x)) return fail(c, PFLB_ERR_ALIGN, "x must be 16-byte aligned");
+    if (!dens_ok(rho, batch)) return fail(c, PFLB_ERR_PARAM, "densities must be finite and > 0");
     const size_t HW = (size_t)c->cfg.H * c->cfg.W;
     hipStream_t st = (hipStream_t)stream;
     for (int b0 = 0; b0 < batch; b0 += LRR_MAX) {
         const int nb = std::min(LRR_MAX, batch - b0);
-        LrrTab tab;
-        for (int k = 0; k < LRR_MAX; ++k) tab.v[k] = k < nb ? (float)lrr[b0 + k] : 0.0f;
-        SUR_TRY(pack(phi + b0 * HW, P + b0 * HW, J + 2 * b0 * HW, tab, nb, c->nm, HW,
-                     static_cast<__bf16*>(x) + b0 * HW * PFSUR_IN_CH, st),
+        SUR_TRY(pack(phi + b0 * HW, P + b0 * HW, J + 2 * b0 * HW, dens_tab(rho, b0, nb), nb,
+                     c->nm, HW, static_cast<__bf16*>(x) + b0 * HW * PFSUR_IN_CH, st),
                 "pack");
     }
     return PFLB_OK;
 }
 
 int pfsur_pack_target(pfsur_ctx* c, const float* phi0, const float* P0, const float* J0,
-                      const float* phi1, const float* P1, const float* J1, int batch, float* y,
-                      void* stream) {
+                      const float* phi1, const float* P1, const float* J1, const double* rho,
+                      int batch, float* y, void* stream) {
     int r = check_batch(c, batch);
     if (r) return r;
-    if (!phi0 || !P0 || !J0 || !phi1 || !P1 || !J1 || !y)
+    if (!phi0 || !P0 || !J0 || !phi1 || !P1 || !J1 || !rho || !y)
         return fail(c, PFLB_ERR_PARAM, "NULL pointer");
     if (!aligned16(y)) return fail(c, PFLB_ERR_ALIGN, "y must be 16-byte aligned");
+    if (!dens_ok(rho, batch)) return fail(c, PFLB_ERR_PARAM, "densities must be finite and > 0");
     const size_t HW = (size_t)c->cfg.H * c->cfg.W;
     hipStream_t st = (hipStream_t)stream;
-    for (int b = 0; b < batch; ++b)
-        SUR_TRY(pack_target(phi0 + b * HW, P0 + b * HW, J0 + 2 * b * HW, phi1 + b * HW,
-                            P1 + b * HW, J1 + 2 * b * HW, c->nm, HW, y + b * HW * PFSUR_OUT_CH, st),
+    for (int b0 = 0; b0 < batch; b0 += LRR_MAX) {
+        const int nb = std::min(LRR_MAX, batch - b0);
+        SUR_TRY(pack_target(phi0 + b0 * HW, P0 + b0 * HW, J0 + 2 * b0 * HW, phi1 + b0 * HW,
+                            P1 + b0 * HW, J1 + 2 * b0 * HW, dens_tab(rho, b0, nb), nb, c->nm, HW,
+                            y + b0 * HW * PFSUR_OUT_CH, st),
                 "pack target");
+    }
     return PFLB_OK;
 }
 
@@ -536,13 +560,19 @@ int pfsur_forward(pfsur_ctx* c, const void* x, float* out, int batch, void* work
                        (hipStream_t)stream);
 }
 
-int pfsur_apply(pfsur_ctx* c, const float* out, float* phi, float* P, float* J, int batch,
-                void* stream) {
+int pfsur_apply(pfsur_ctx* c, const float* out, float* phi, float* P, float* J,
+                const double* rho, int batch, void* stream) {
     int r = check_batch(c, batch);
     if (r) return r;
-    if (!out || !phi || !P || !J) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
-    SUR_TRY(apply(out, c->nm, batch, (size_t)c->cfg.H * c->cfg.W, phi, P, J, (hipStream_t)stream),
-            "apply");
+    if (!out || !phi || !P || !J || !rho) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
+    if (!dens_ok(rho, batch)) return fail(c, PFLB_ERR_PARAM, "densities must be finite and > 0");
+    const size_t HW = (size_t)c->cfg.H * c->cfg.W;
+    for (int b0 = 0; b0 < batch; b0 += LRR_MAX) {
+        const int nb = std::min(LRR_MAX, batch - b0);
+        SUR_TRY(apply(out + b0 * HW * PFSUR_OUT_CH, c->nm, dens_tab(rho, b0, nb), nb, HW,
+                      phi + b0 * HW, P + b0 * HW, J + 2 * b0 * HW, (hipStream_t)stream),
+                "apply");
+    }
     return PFLB_OK;
 }
 
@@ -635,14 +665,15 @@ size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch) {
 }
 
 int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
-                         const double* lrr, double mass_tol, double phi_tol, double u_max,
-                         int check_every, int* n_fallback, void* work, void* stream) {
+                         double mass_tol, double phi_tol, double u_max, int check_every,
+                         int* n_fallback, void* work, void* stream) {
     if (!c) return PFLB_ERR_PARAM;
-    if (!lbs || !lrr || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
+    if (!lbs || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
     if (n < 1 || n > c->cfg.max_batch) return fail(c, PFLB_ERR_PARAM, "batch must be in [1, max_batch]");
     if (((uintptr_t)work & 255u)) return fail(c, PFLB_ERR_ALIGN, "work must be 256-byte aligned");
     if (windows < 0 || check_every < 0) return fail(c, PFLB_ERR_PARAM, "negative count");
-    std::vector<RhoTab> rho((n + LRR_MAX - 1) / LRR_MAX);
+    std::vector<double> rho(2 * (size_t)n);   // (rho_L, rho_H) of each context
+    std::vector<float> beta(n);               // 1 where the context uses Eq. 13
     for (int k = 0; k < n; ++k) {
         pflb::CtxInfo info;
         if (!lbs[k] || pflb_ctx_info(lbs[k], &info) != PFLB_OK || !info.bound)
@@ -650,8 +681,9 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if (info.q != 9 || info.nx != c->cfg.W || info.ny != c->cfg.H ||
             info.bc[0] != PFLB_BC_PERIODIC || info.bc[1] != PFLB_BC_PERIODIC)
             return fail(c, PFLB_ERR_PARAM, "lattices must be D2Q9, periodic, nx = W, ny = H");
-        rho[k / LRR_MAX].rl[k % LRR_MAX] = (float)info.rho_L;
-        rho[k / LRR_MAX].rd[k % LRR_MAX] = (float)(info.rho_H - info.rho_L);
+        rho[2 * k] = info.rho_L;
+        rho[2 * k + 1] = info.rho_H;
+        beta[k] = info.hoc ? 1.0f : 0.0f;
     }
     hipStream_t st = (hipStream_t)stream;
     const GuardPlan g = guard_plan(&c->cfg, n);
@@ -687,15 +719,19 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if ((r = pflb_read_many(lbs, n, fphi.data(), fP.data(), fJ.data(), st)))
             return lb_fail(r, lbs[0], "lattice read: ");
         SUR_TRY(sum_field(phi, n, HW, dpart, GUARD_BLOCKS, st), "field sum");
-        if ((r = pfsur_pack(c, phi, P, J, lrr, n, w + g.x, st))) return r;
+        if ((r = pfsur_pack(c, phi, P, J, rho.data(), n, w + g.x, st))) return r;
         if ((r = run_forward(c, w + g.x, out, n, w + g.ws, false, st))) return r;
-        if ((r = pfsur_apply(c, out, phi, P, J, n, st))) return r;
+        if ((r = pfsur_apply(c, out, phi, P, J, rho.data(), n, st))) return r;
         SUR_TRY(sum_field(phi, n, HW, dpart + nb, GUARD_BLOCKS, st), "field sum");
-        for (int k0 = 0; k0 < n; k0 += LRR_MAX)
-            SUR_TRY(maxspeed(phi + k0 * HW, J + 2 * k0 * HW, rho[k0 / LRR_MAX],
-                             std::min(LRR_MAX, n - k0), HW, upart + (size_t)k0 * GUARD_BLOCKS,
-                             GUARD_BLOCKS, st),
+        for (int k0 = 0; k0 < n; k0 += LRR_MAX) {
+            // the speed the hand-over would give (u = J / rho', rho' of Eq. 13)
+            const int nk = std::min(LRR_MAX, n - k0);
+            DensTab d = dens_tab(rho.data(), k0, nk);
+            for (int k = 0; k < nk; ++k) d.beta[k] = beta[k0 + k];
+            SUR_TRY(maxspeed(phi + k0 * HW, J + 2 * k0 * HW, d, nk, c->cfg.H, c->cfg.W,
+                             upart + (size_t)k0 * GUARD_BLOCKS, GUARD_BLOCKS, st),
                     "speed check");
+        }
         SUR_TRY(hipMemcpyAsync(hu.data(), upart, nb * 4, hipMemcpyDeviceToHost, st),
                 "speed check");
         const bool checked = check_every > 0 && (win + 1) % check_every == 0;

@@ -58,14 +58,13 @@ struct Norm {
     float shift[4], scale[4], out_scale[4], lrr_scale;
 };
 
-// per-sample log10 density ratios of one packing launch (at most LRR_MAX samples)
+// per-sample densities of one launch over at most LRR_MAX samples: rho(phi) = rl +
+// clamp(phi, 0, 1) rd, and lrr = log10(rho_H / rho_L).  The network sees and predicts
+// the velocity J / rho(phi) rather than the momentum J, which spans the density ratio.
 constexpr int LRR_MAX = 64;
-struct LrrTab {
-    float v[LRR_MAX];
-};
-// per-sample densities rho = rl + phi rd of one speed-check launch
-struct RhoTab {
-    float rl[LRR_MAX], rd[LRR_MAX];
+struct DensTab {
+    float rl[LRR_MAX], rd[LRR_MAX], lrr[LRR_MAX];
+    float beta[LRR_MAX];   // speed check: 1 if the solver uses Eq. 13's modified density
 };
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st);
@@ -91,19 +90,22 @@ unsigned mse_blocks(size_t n);
 hipError_t adam(float* w, const float* g, float* m, float* v, size_t n, float lr, int t,
                 hipStream_t st);
 hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* wt, hipStream_t st);
-hipError_t pack(const float* phi, const float* P, const float* J, const LrrTab& lrr, int B,
+// B <= LRR_MAX samples each (fields per sample: phi, P [HW], J [2][HW])
+hipError_t pack(const float* phi, const float* P, const float* J, const DensTab& d, int B,
                 const Norm& nm, size_t HW, __bf16* x, hipStream_t st);
 hipError_t pack_target(const float* phi0, const float* P0, const float* J0, const float* phi1,
-                       const float* P1, const float* J1, const Norm& nm, size_t HW, float* y,
-                       hipStream_t st);
-hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi, float* P, float* J,
-                 hipStream_t st);
+                       const float* P1, const float* J1, const DensTab& d, int B, const Norm& nm,
+                       size_t HW, float* y, hipStream_t st);
+hipError_t apply(const float* out, const Norm& nm, const DensTab& d, int B, size_t HW, float* phi,
+                 float* P, float* J, hipStream_t st);
 hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part, int nblk,
                    hipStream_t st);
 hipError_t sum_field(const float* a, int B, size_t n, double* part, int nblk, hipStream_t st);
-// per block, max over sites of |J| / (rl + phi rd) for sample blockIdx.y of B <= LRR_MAX
-// (phi [B][n], J [B][2][n]): part[sample][block]
-hipError_t maxspeed(const float* phi, const float* J, const RhoTab& rho, int B, size_t n,
+// per block, max over sites of the speed a hand-over to a D2Q9 solver would give,
+// |J| / rho'(phi) with rho' = rho_L + phi rho_dif + beta rho_dif lap(phi) / 4 (periodic
+// central Laplacian; rho' <= 0 counts as infinite), for sample blockIdx.y of
+// B <= LRR_MAX (phi [B][H][W], J [B][2][H][W]): part[sample][block]
+hipError_t maxspeed(const float* phi, const float* J, const DensTab& d, int B, int H, int W,
                     float* part, int nblk, hipStream_t st);
 
 }  // namespace pfsur

@@ -948,48 +948,68 @@ __global__ void k_weights_bf16(const float* __restrict__ w, int Cout, int Cin, _
     if (wt) wt[((size_t)ci * 9 + (8 - tap)) * Cout + co] = (__bf16)w[i];
 }
 
+// density of sample b at order parameter phi (clamped: phi overshoots [0, 1] slightly and
+// rho must stay positive for the velocity conversion)
+__device__ __forceinline__ float dens(const DensTab& d, size_t b, float phi) {
+    return fmaf(fminf(fmaxf(phi, 0.0f), 1.0f), d.rd[b], d.rl[b]);
+}
+
 // network input from solver fields, sample b = blockIdx.y of the batch:
-// x[b, y, x, :] = ((phi - s0) k0, (P - s1) k1, (Jx - s2) k2, (Jy - s3) k3,
-// lrr_b lrr_scale, 0, 0, 0)
+// x[b, y, x, :] = ((phi - s0) k0, (P - s1) k1, (u_x - s2) k2, (u_y - s3) k3,
+// lrr_b lrr_scale, 0, 0, 0) with u = J / rho(phi)
 __global__ void k_pack(const float* __restrict__ phi, const float* __restrict__ P,
-                       const float* __restrict__ J, LrrTab lrr, Norm nm, size_t HW,
+                       const float* __restrict__ J, DensTab d, Norm nm, size_t HW,
                        __bf16* __restrict__ x) {
     const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= HW) return;
     const size_t b = blockIdx.y;
     const size_t i = b * HW + s;
-    const float f[4] = {phi[i], P[i], J[2 * b * HW + s], J[(2 * b + 1) * HW + s]};
+    const float rho = dens(d, b, phi[i]);
+    const float f[4] = {phi[i], P[i], J[2 * b * HW + s] / rho, J[(2 * b + 1) * HW + s] / rho};
     bf16x8 v;
     for (int c = 0; c < 4; ++c) v[c] = (__bf16)((f[c] - nm.shift[c]) * nm.scale[c]);
-    v[4] = (__bf16)(lrr.v[b] * nm.lrr_scale);
+    v[4] = (__bf16)(d.lrr[b] * nm.lrr_scale);
     v[5] = v[6] = v[7] = (__bf16)0.0f;
     *reinterpret_cast<bf16x8*>(x + i * 8) = v;
 }
 
-// training target of one sample: y[s, c] = (f1_c - f0_c) / out_scale[c]
+// training target of sample b = blockIdx.y: y[s, c] = (f1_c - f0_c) / out_scale[c] for
+// (phi, P, u_x, u_y)
 __global__ void k_pack_target(const float* __restrict__ phi0, const float* __restrict__ P0,
                               const float* __restrict__ J0, const float* __restrict__ phi1,
-                              const float* __restrict__ P1, const float* __restrict__ J1, Norm nm,
-                              size_t HW, float* __restrict__ y) {
+                              const float* __restrict__ P1, const float* __restrict__ J1, DensTab d,
+                              Norm nm, size_t HW, float* __restrict__ y) {
     const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= HW) return;
+    const size_t b = blockIdx.y;
+    const size_t i = b * HW + s, jx = 2 * b * HW + s, jy = (2 * b + 1) * HW + s;
+    const float r0 = dens(d, b, phi0[i]), r1 = dens(d, b, phi1[i]);
     float4 v;
-    v.x = (phi1[s] - phi0[s]) / nm.out_scale[0];
-    v.y = (P1[s] - P0[s]) / nm.out_scale[1];
-    v.z = (J1[s] - J0[s]) / nm.out_scale[2];
-    v.w = (J1[HW + s] - J0[HW + s]) / nm.out_scale[3];
-    reinterpret_cast<float4*>(y)[s] = v;
+    v.x = (phi1[i] - phi0[i]) / nm.out_scale[0];
+    v.y = (P1[i] - P0[i]) / nm.out_scale[1];
+    v.z = (J1[jx] / r1 - J0[jx] / r0) / nm.out_scale[2];
+    v.w = (J1[jy] / r1 - J0[jy] / r0) / nm.out_scale[3];
+    reinterpret_cast<float4*>(y)[i] = v;
 }
 
-__global__ void k_apply(const float* __restrict__ out, Norm nm, int B, size_t HW,
+// a predicted residual applied to sample b = blockIdx.y in place: phi and P advance by
+// out * out_scale, the velocity J / rho(phi) likewise, and J = rho(phi_new) u_new
+__global__ void k_apply(const float* __restrict__ out, Norm nm, DensTab d, size_t HW,
                         float* __restrict__ phi, float* __restrict__ P, float* __restrict__ J) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (size_t)B * HW) return;
-    const size_t b = i / HW, s = i - b * HW;
-    phi[i] += out[i * 4 + 0] * nm.out_scale[0];
-    P[i] += out[i * 4 + 1] * nm.out_scale[1];
-    J[(b * 2) * HW + s] += out[i * 4 + 2] * nm.out_scale[2];
-    J[(b * 2 + 1) * HW + s] += out[i * 4 + 3] * nm.out_scale[3];
+    const size_t s = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= HW) return;
+    const size_t b = blockIdx.y;
+    const size_t i = b * HW + s, jx = 2 * b * HW + s, jy = (2 * b + 1) * HW + s;
+    const float4 o = reinterpret_cast<const float4*>(out)[i];
+    const float r0 = dens(d, b, phi[i]);
+    const float ux = J[jx] / r0 + o.z * nm.out_scale[2];
+    const float uy = J[jy] / r0 + o.w * nm.out_scale[3];
+    const float ph = phi[i] + o.x * nm.out_scale[0];
+    const float r1 = dens(d, b, ph);
+    phi[i] = ph;
+    P[i] += o.y * nm.out_scale[1];
+    J[jx] = r1 * ux;
+    J[jy] = r1 * uy;
 }
 
 // max |a - b| per block for sample blockIdx.y of a batch of fields of n values:
@@ -1015,18 +1035,31 @@ __global__ void __launch_bounds__(256) k_maxdiff(const float* __restrict__ a, co
     if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = sred[0];
 }
 
-// largest speed |J| / rho(phi) per block for sample blockIdx.y (phi [B][n], J [B][2][n]):
+// largest hand-over speed |J| / rho'(phi) per block for sample blockIdx.y (see maxspeed):
 // part[sample][block]; a non-finite speed propagates
 __global__ void __launch_bounds__(256) k_maxspeed(const float* __restrict__ phi,
-                                                  const float* __restrict__ J, RhoTab rho,
-                                                  size_t n, float* __restrict__ part) {
+                                                  const float* __restrict__ J, DensTab d, int H,
+                                                  int W, float* __restrict__ part) {
     __shared__ float sred[256];
     const size_t b = blockIdx.y;
-    const float rl = rho.rl[b], rd = rho.rd[b];
+    const size_t n = (size_t)H * W;
+    const float* ph = phi + b * n;
     float m = 0.f;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const int y = (int)(i / W), x = (int)(i - (size_t)y * W);
+        const int xm = x == 0 ? W - 1 : x - 1, xp = x == W - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? H - 1 : y - 1, yp = y == H - 1 ? 0 : y + 1;
+        const float c = ph[i];
+        // (2/T) sum_i w_i (phi(x + c_i) - phi(x)), D2Q9 weights 1/9 (axes) and 1/36
+        const float ax = (ph[(size_t)y * W + xm] - c) + (ph[(size_t)y * W + xp] - c) +
+                         (ph[(size_t)ym * W + x] - c) + (ph[(size_t)yp * W + x] - c);
+        const float dg = (ph[(size_t)ym * W + xm] - c) + (ph[(size_t)ym * W + xp] - c) +
+                         (ph[(size_t)yp * W + xm] - c) + (ph[(size_t)yp * W + xp] - c);
+        const float lap = 6.0f * fmaf(1.0f / 36.0f, dg, (1.0f / 9.0f) * ax);
+        const float rho = fmaf(c, d.rd[b], d.rl[b]);
+        const float rp = fmaf(d.beta[b] * 0.25f * d.rd[b], lap, rho);
         const float jx = J[2 * b * n + i], jy = J[(2 * b + 1) * n + i];
-        const float u = sqrtf(jx * jx + jy * jy) / fmaf(phi[b * n + i], rd, rl);
+        const float u = rp > 0.0f ? sqrtf(jx * jx + jy * jy) / rp : INFINITY;
         m = u > m || u != u ? u : m;
     }
     sred[threadIdx.x] = m;
@@ -1216,24 +1249,26 @@ hipError_t weights_bf16(const float* w, int Cout, int Cin, __bf16* wf, __bf16* w
     return hipGetLastError();
 }
 
-hipError_t pack(const float* phi, const float* P, const float* J, const LrrTab& lrr, int B,
+hipError_t pack(const float* phi, const float* P, const float* J, const DensTab& d, int B,
                 const Norm& nm, size_t HW, __bf16* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_pack, dim3(blocks(HW), B), dim3(256), 0, st, phi, P, J, lrr, nm, HW, x);
+    if (B < 1 || B > LRR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack, dim3(blocks(HW), B), dim3(256), 0, st, phi, P, J, d, nm, HW, x);
     return hipGetLastError();
 }
 
 hipError_t pack_target(const float* phi0, const float* P0, const float* J0, const float* phi1,
-                       const float* P1, const float* J1, const Norm& nm, size_t HW, float* y,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_pack_target, dim3(blocks(HW)), dim3(256), 0, st, phi0, P0, J0, phi1, P1,
-                       J1, nm, HW, y);
+                       const float* P1, const float* J1, const DensTab& d, int B, const Norm& nm,
+                       size_t HW, float* y, hipStream_t st) {
+    if (B < 1 || B > LRR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_target, dim3(blocks(HW), B), dim3(256), 0, st, phi0, P0, J0, phi1,
+                       P1, J1, d, nm, HW, y);
     return hipGetLastError();
 }
 
-hipError_t apply(const float* out, const Norm& nm, int B, size_t HW, float* phi, float* P, float* J,
-                 hipStream_t st) {
-    hipLaunchKernelGGL(k_apply, dim3(blocks((size_t)B * HW)), dim3(256), 0, st, out, nm, B, HW, phi,
-                       P, J);
+hipError_t apply(const float* out, const Norm& nm, const DensTab& d, int B, size_t HW, float* phi,
+                 float* P, float* J, hipStream_t st) {
+    if (B < 1 || B > LRR_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_apply, dim3(blocks(HW), B), dim3(256), 0, st, out, nm, d, HW, phi, P, J);
     return hipGetLastError();
 }
 
@@ -1250,10 +1285,10 @@ hipError_t maxdiff(const float* a, const float* b, int B, size_t n, float* part,
     return hipGetLastError();
 }
 
-hipError_t maxspeed(const float* phi, const float* J, const RhoTab& rho, int B, size_t n,
+hipError_t maxspeed(const float* phi, const float* J, const DensTab& d, int B, int H, int W,
                     float* part, int nblk, hipStream_t st) {
-    if (B < 1 || B > LRR_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_maxspeed, dim3(nblk, B), dim3(256), 0, st, phi, J, rho, n, part);
+    if (B < 1 || B > LRR_MAX || H < 1 || W < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_maxspeed, dim3(nblk, B), dim3(256), 0, st, phi, J, d, H, W, part);
     return hipGetLastError();
 }
 

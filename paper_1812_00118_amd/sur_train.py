@@ -42,7 +42,7 @@ class Dataset:
 
     def __init__(self, seeds, make_cfg, t0=64, n_states=9, log=None):
         import pfinputs as I
-        phi, P, J, lrr, pairs = [], [], [], [], []
+        phi, P, J, rho, pairs = [], [], [], [], []
         base = 0
         t = time.time()
         for s in seeds:
@@ -52,13 +52,14 @@ class Dataset:
             phi.append(a)
             P.append(b)
             J.append(c)
-            lrr += [math.log10(cfg["rho_H"] / cfg["rho_L"])] * n_states
+            rho += [(cfg["rho_L"], cfg["rho_H"])] * n_states
             pairs += [(base + k, base + k + 1) for k in range(n_states - 1)]
             base += n_states
         self.phi = torch.cat(phi)
         self.P = torch.cat(P)
         self.J = torch.cat(J)
-        self.lrr = np.asarray(lrr)
+        self.rho = np.asarray(rho, dtype=np.float64)           # (rho_L, rho_H) per state
+        self.lrr = np.log10(self.rho[:, 1] / self.rho[:, 0])
         self.pairs = np.asarray(pairs, dtype=np.int64)
         self.seconds = time.time() - t
         if log:
@@ -74,9 +75,19 @@ class Dataset:
                 self.J.index_select(0, i).contiguous())
 
 
+def velocity(ds):
+    """u = J / rho(phi) per state, rho(phi) = rho_L + clamp(phi, 0, 1) (rho_H - rho_L):
+    the quantity the network sees and predicts in place of J."""
+    r = torch.as_tensor(ds.rho, dtype=torch.float32, device=ds.phi.device)
+    rho = r[:, 0, None, None] + ds.phi.clamp(0.0, 1.0) * (r[:, 1] - r[:, 0])[:, None, None]
+    return ds.J / rho[:, None]
+
+
 def normalisation(ds):
-    """Per-channel standardisation of the inputs and of the 16-step residuals."""
-    f0 = [ds.phi, ds.P, ds.J[:, 0], ds.J[:, 1]]
+    """Per-channel standardisation of the inputs (phi, P, u_x, u_y) and of their 16-step
+    residuals."""
+    u = velocity(ds)
+    f0 = [ds.phi, ds.P, u[:, 0], u[:, 1]]
     a = torch.as_tensor(ds.pairs[:, 0], device=ds.phi.device)
     b = torch.as_tensor(ds.pairs[:, 1], device=ds.phi.device)
     shift, scale, out = [], [], []
@@ -93,8 +104,9 @@ def batch(sur, ds, idx):
     p = ds.pairs[idx]
     f0 = ds.fields(p[:, 0])
     f1 = ds.fields(p[:, 1])
-    x = sur.pack(*f0, ds.lrr[p[:, 0]])
-    y = sur.pack_target(f0, f1)
+    rho = ds.rho[p[:, 0]]
+    x = sur.pack(*f0, rho)
+    y = sur.pack_target(f0, f1, rho)
     return x, y
 
 
@@ -124,14 +136,15 @@ def evaluate(sur, ds, batch_size=8):
         p = ds.pairs[idx]
         f0 = ds.fields(p[:, 0])
         f1 = ds.fields(p[:, 1])
-        x = sur.pack(*f0, ds.lrr[p[:, 0]])
-        y = sur.pack_target(f0, f1)
+        rho = ds.rho[p[:, 0]]
+        x = sur.pack(*f0, rho)
+        y = sur.pack_target(f0, f1, rho)
         out = sur.forward(x)
         se_net += float(((out - y) ** 2).sum())
         se_pers += float((y ** 2).sum())
         n += y.numel()
         phi, P, J = (t.clone() for t in f0)
-        sur.apply(out, phi, P, J)
+        sur.apply(out, phi, P, J, rho)
         err_net = max(err_net, float((phi - f1[0]).abs().max()))
         err_pers = max(err_pers, float((f0[0] - f1[0]).abs().max()))
     return dict(mse=se_net / n, mse_persistence=se_pers / n, phi_err=err_net,

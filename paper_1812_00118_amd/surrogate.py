@@ -122,27 +122,36 @@ class Surrogate:
         t = torch.as_tensor(t).to(device=self.device, dtype=torch.float32).contiguous()
         return t.reshape(shape)
 
-    def pack(self, phi, P, J, lrr):
-        """phi, P (B, H, W); J (B, 2, H, W); lrr: B values of log10(rho_H/rho_L)."""
-        B = len(lrr)
+    @staticmethod
+    def _rho(rho, B):
+        """(rho_L, rho_H) per sample -> host double array [B][2]."""
+        r = np.asarray(rho, dtype=np.float64).reshape(-1, 2)
+        if len(r) != B:
+            raise ValueError(f"expected {B} (rho_L, rho_H) pairs, got {len(r)}")
+        return (ctypes.c_double * (2 * B))(*r.ravel().tolist())
+
+    def pack(self, phi, P, J, rho):
+        """phi, P (B, H, W); J (B, 2, H, W); rho: B pairs (rho_L, rho_H).  The network
+        input carries the velocity J / rho(phi) (include/pfsur.h)."""
+        B = len(np.asarray(rho, dtype=np.float64).reshape(-1, 2))
         phi = self._f32(phi, (B, self.H, self.W))
         P = self._f32(P, (B, self.H, self.W))
         J = self._f32(J, (B, 2, self.H, self.W))
         x = torch.empty((B, self.H, self.W, IN_CH), dtype=torch.bfloat16, device=self.device)
-        arr = (ctypes.c_double * B)(*[float(v) for v in lrr])
-        self._check(self.L.pfsur_pack(self.ctx, _ptr(phi), _ptr(P), _ptr(J), arr, B, _ptr(x),
-                                      _stream(self.device)))
+        self._check(self.L.pfsur_pack(self.ctx, _ptr(phi), _ptr(P), _ptr(J), self._rho(rho, B),
+                                      B, _ptr(x), _stream(self.device)))
         return x
 
-    def pack_target(self, f0, f1):
-        """f0, f1: (phi, P, J) of the same batch 16 steps apart -> y FP32 (B, H, W, 4)."""
+    def pack_target(self, f0, f1, rho):
+        """f0, f1: (phi, P, J) of the same batch 16 steps apart; rho: B pairs (rho_L,
+        rho_H) -> y FP32 (B, H, W, 4), the normalised residual of (phi, P, u_x, u_y)."""
         B = f0[0].shape[0]
         a = [self._f32(f0[0], (B, self.H, self.W)), self._f32(f0[1], (B, self.H, self.W)),
              self._f32(f0[2], (B, 2, self.H, self.W)), self._f32(f1[0], (B, self.H, self.W)),
              self._f32(f1[1], (B, self.H, self.W)), self._f32(f1[2], (B, 2, self.H, self.W))]
         y = torch.empty((B, self.H, self.W, OUT_CH), dtype=torch.float32, device=self.device)
-        self._check(self.L.pfsur_pack_target(self.ctx, *[_ptr(t) for t in a], B, _ptr(y),
-                                             _stream(self.device)))
+        self._check(self.L.pfsur_pack_target(self.ctx, *[_ptr(t) for t in a], self._rho(rho, B),
+                                             B, _ptr(y), _stream(self.device)))
         return y
 
     def forward(self, x):
@@ -152,14 +161,15 @@ class Surrogate:
                                          self.workspace(B, False), _stream(self.device)))
         return out
 
-    def apply(self, out, phi, P, J):
-        """In place: field += out * out_scale (phi, P, J: contiguous float32 device
-        tensors (B, H, W), (B, H, W), (B, 2, H, W))."""
+    def apply(self, out, phi, P, J, rho):
+        """In place: phi, P and the velocity J / rho(phi) advance by out * out_scale, J is
+        rebuilt from the new phi (phi, P, J: contiguous float32 device tensors (B, H, W),
+        (B, H, W), (B, 2, H, W); rho: B pairs (rho_L, rho_H))."""
         B = out.shape[0]
         for t in (phi, P, J):
             assert t.is_contiguous() and t.dtype == torch.float32
-        self._check(self.L.pfsur_apply(self.ctx, _ptr(out), _ptr(phi), _ptr(P), _ptr(J), B,
-                                       _stream(self.device)))
+        self._check(self.L.pfsur_apply(self.ctx, _ptr(out), _ptr(phi), _ptr(P), _ptr(J),
+                                       self._rho(rho, B), B, _stream(self.device)))
 
     def train_step(self, x, y, lr):
         B = x.shape[0]
@@ -179,7 +189,7 @@ class Surrogate:
         return g, float(loss.value)
 
     # ------------------------------------------------------------------ hand-over
-    def advance_guarded(self, sims, windows, lrr, mass_tol=1e-3, phi_tol=0.05, check_every=0,
+    def advance_guarded(self, sims, windows, mass_tol=1e-3, phi_tol=0.05, check_every=0,
                         u_max=0.1):
         """Advance D2Q9 periodic Sims (one, or a list of at most max_batch) by windows x 16
         steps with one batched forward pass per window; returns the number of (window,
@@ -188,7 +198,7 @@ class Surrogate:
         u_max, or (on every check_every-th window) when it is more than phi_tol from the
         plain steps."""
         if not isinstance(sims, (list, tuple)):
-            sims, lrr = [sims], [lrr]
+            sims = [sims]
         n = len(sims)
         nb = int(self.L.pfsur_guard_work_bytes(ctypes.byref(self.cfg), n))
         if nb == 0:
@@ -196,9 +206,8 @@ class Surrogate:
         work = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
         ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in sims])
-        lr = (ctypes.c_double * n)(*[float(v) for v in lrr])
         nf = ctypes.c_int()
-        self._check(self.L.pflb_advance_guarded(ctxs, n, self.ctx, int(windows), lr,
+        self._check(self.L.pflb_advance_guarded(ctxs, n, self.ctx, int(windows),
                                                 float(mass_tol), float(phi_tol), float(u_max),
                                                 int(check_every), ctypes.byref(nf), wp,
                                                 _stream(self.device)))
