@@ -147,9 +147,38 @@ def cpu_baseline(seconds):
         if el >= seconds:
             break
     sites = 48 ** 3
-    return {"value": sites * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"rising bubble sub-box 48^3 (R 6, same fluid parameters), {n} "
-                      f"whole-domain FP64 steps in {el:.1f} s, numpy single thread"}
+    out = {"value": sites * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "sample": f"rising bubble sub-box 48^3 (R 6, same fluid parameters), {n} "
+                     f"whole-domain FP64 steps in {el:.1f} s, numpy single thread"}
+    # the host, and the oracle on the two D2Q9 workloads (a few seconds each)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         "")
+    except OSError:
+        pass
+    out["host"] = {"cpu_model": model, "logical_cpus": os.cpu_count()}
+    d2 = {}
+    for name, cfg2, budget in (("static_droplet D2Q9 64x64", pfinputs.static_droplet(), 3.0),
+                               ("rayleigh_taylor D2Q9 256x1024",
+                                pfinputs.rayleigh_taylor(), 6.0)):
+        prm2 = O.Params.from_dict(pfinputs.model_params(cfg2))
+        f2 = pfinputs.fields(cfg2)
+        h2, g2 = O.init(prm2, *(a.astype(np.float64) for a in f2))
+        h2, g2 = O.step(prm2, h2, g2)
+        k, t1 = 0, time.perf_counter()
+        while True:
+            h2, g2 = O.step(prm2, h2, g2)
+            k += 1
+            e2 = time.perf_counter() - t1
+            if e2 >= budget:
+                break
+        nx, ny, nz = cfg2["shape"]
+        d2[name] = {"mlups": round(nx * ny * nz * k / e2 / 1e6, 3), "steps": k,
+                    "seconds": round(e2, 2)}
+    out["d2q9_oracle"] = d2
+    return out
 
 
 def _events_ms(fn, reps):
