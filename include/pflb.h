@@ -166,6 +166,15 @@ int pflb_reconstruct(pflb_ctx* ctx, const float* phi, const float* P, const floa
  * the central differences of Section 2).  Returns launch errors only. */
 int pflb_step(pflb_ctx* ctx, int nsteps, void* stream);
 
+/* The same steps for n contexts at once (an ensemble of small domains fills the GPU
+ * where one alone is launch-bound): each step is one launch per 16 contexts; a context
+ * with a moving wall is stepped on its own, as by pflb_step.  The contexts must be
+ * distinct, bound and share lattice, storage, sizes and walls; their physical parameters
+ * and wall velocities may differ.  Each context ends exactly as
+ * pflb_step(ctx[k], nsteps) would leave it, bit for bit.  Asynchronous on stream;
+ * errors (PFLB_ERR_PARAM, PFLB_ERR_UNBOUND, PFLB_ERR_DEVICE) are reported on ctx[0]. */
+int pflb_step_many(pflb_ctx* const* ctx, int n, int nsteps, void* stream);
+
 /* Macroscopic fields of the current state (end of Section 2):
  *   phi [N]   = sum_i h_i                           (required; also used as input
  *                                                    of the second pass)

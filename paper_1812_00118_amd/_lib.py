@@ -57,6 +57,7 @@ _SIGS = {
     "pflb_init_fields": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pflb_reconstruct": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "pflb_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "pflb_step_many": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
     "pflb_read": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pflb_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int), _vp]),

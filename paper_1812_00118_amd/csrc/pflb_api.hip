@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,27 @@ size_t scratch_bytes() {
 
 uint32_t sites(const pflb_params* p) { return (uint32_t)p->nx * p->ny * p->nz; }
 
+// Planes per workgroup of the fused step for nctx contexts of one launch: long z-marches
+// (each chunk re-gathers two extra planes of h) with about two 4-wave workgroups per CU
+// (8 one-wave workgroups for D2Q9) over the whole launch.  Measured: D3Q19 256x256x128
+// droplet impact, 64 planes beat 32 and 16 (and never below 8); D2Q9 256x1024
+// Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8), and a lone 256x256 domain
+// runs best with 1: small 2-D domains need the parallelism more than they lose to the
+// re-gathered planes.
+int pick_bz(const Geom& G, int lattice, int nctx) {
+    const long cols = (long)((G.nx + 63) / 64) * (lattice == 19 ? (G.ny + 3) / 4 : 1) * nctx;
+    const long want_wgs = lattice == 19 ? 512 : 2048;
+    long chunks = (want_wgs + cols - 1) / cols;
+    if (chunks < 1) chunks = 1;
+    long bz = (G.nz + chunks - 1) / chunks;
+    const long bz_min = lattice == 19 ? 8 : 1;
+    if (bz < bz_min) bz = bz_min;
+    if (bz > G.nz) bz = G.nz;
+    const char* env = getenv("PFLB_BZ");
+    if (env && atoi(env) > 0) bz = atoi(env);
+    return (int)bz;
+}
+
 void derive(pflb_ctx* c) {
     const pflb_params& p = c->p;
     c->Q = p.lattice;
@@ -149,23 +171,7 @@ void derive(pflb_ctx* c) {
     c->L.tile = 0;
     const char* tenv = getenv("PFLB_TILE");
     if (tenv && atoi(tenv) >= 0 && atoi(tenv) <= 3) c->L.tile = atoi(tenv);
-    // planes per workgroup: long z-marches (each chunk re-gathers two extra planes of h)
-    // with about two 4-wave workgroups per CU (8 one-wave workgroups for D2Q9).  Measured:
-    // D3Q19 256x256x128 droplet impact, 64 planes beat 32 and 16 (and never below 8);
-    // D2Q9 256x1024 Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8), and a
-    // 256x256 domain runs best with 1: small 2-D domains need the parallelism more than
-    // they lose to the re-gathered planes
-    const long cols = (long)((G.nx + 63) / 64) * (p.lattice == 19 ? (G.ny + 3) / 4 : 1);
-    const long want_wgs = p.lattice == 19 ? 512 : 2048;
-    long chunks = (want_wgs + cols - 1) / cols;
-    if (chunks < 1) chunks = 1;
-    long bz = (G.nz + chunks - 1) / chunks;
-    const long bz_min = p.lattice == 19 ? 8 : 1;
-    if (bz < bz_min) bz = bz_min;
-    if (bz > G.nz) bz = G.nz;
-    const char* env = getenv("PFLB_BZ");
-    if (env && atoi(env) > 0) bz = atoi(env);
-    c->L.bz = (int)bz;
+    c->L.bz = pick_bz(G, p.lattice, 1);
 }
 
 int fail(pflb_ctx* c, int code, const std::string& what) {
@@ -530,6 +536,56 @@ int pflb_reconstruct_many(pflb_ctx* const* c, int n, const float* const* phi,
         hipError_t e = launch_reconstruct_batch(a, c[0]->N, bt, nb);
         if (e != hipSuccess) return hip_fail(c[0], e, "batched hand-over launch");
         for (int j = 0; j < nb; ++j) c[k0 + j]->steps += advance;
+    }
+    return PFLB_OK;
+}
+
+extern "C" int pflb_step_many(pflb_ctx* const* c, int n, int nsteps, void* stream) {
+    int r = check_many(c, n);
+    if (r) return r;
+    if (nsteps < 0) return fail(c[0], PFLB_ERR_PARAM, "nsteps < 0");
+    // a context listed twice would be stepped twice from the same state into the same
+    // buffer within one launch
+    std::vector<pflb_ctx*> sorted(c, c + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(c[0], PFLB_ERR_PARAM, "a context appears twice in a batch");
+    // Contexts with moving walls take their own launches: the batched kernel has no
+    // moving-wall variant, and each context must run the arithmetic its own pflb_step
+    // runs (separately compiled kernel variants may contract and round differently).
+    std::vector<pflb_ctx*> gr;
+    for (int k = 0; k < n; ++k) {
+        if (!c[k]->L.m.moving) {
+            gr.push_back(c[k]);
+        } else if ((r = pflb_step(c[k], nsteps, stream))) {
+            if (c[k] != c[0]) fail(c[0], r, pflb_last_error(c[k]));
+            return r;
+        }
+    }
+    const int ng = (int)gr.size();
+    for (int k0 = 0; k0 < ng; k0 += BATCH_MAX) {
+        const int nb = ng - k0 < BATCH_MAX ? ng - k0 : BATCH_MAX;
+        Launch a = gr[k0]->L;
+        a.stream = (hipStream_t)stream;
+        a.bz = pick_bz(a.G, a.q, nb);
+        StepBatch bt;
+        memset(&bt, 0, sizeof(bt));
+        for (int s = 0; s < nsteps; ++s) {
+            for (int j = 0; j < nb; ++j) {
+                pflb_ctx* ck = gr[k0 + j];
+                StepEnt& e = bt.e[j];
+                e.src = static_cast<const char*>(state(ck));
+                e.dst = static_cast<char*>(other(ck));
+                e.m = ck->L.m;
+                e.cd = ck->L.cd;
+            }
+            hipError_t e = launch_step_batch(a, bt, nb);
+            if (e != hipSuccess) return hip_fail(c[0], e, "batched step launch");
+            for (int j = 0; j < nb; ++j) {
+                gr[k0 + j]->cur ^= 1;
+                gr[k0 + j]->steps += 1;
+            }
+        }
     }
     return PFLB_OK;
 }

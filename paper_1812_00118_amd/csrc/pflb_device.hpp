@@ -142,6 +142,17 @@ struct Batch {
     BatchEnt e[BATCH_MAX];
 };
 
+// One context of a batched step: its current and next state buffers and its parameters.
+struct StepEnt {
+    const char* src;
+    char* dst;
+    Model m;
+    Codec cd;
+};
+struct StepBatch {
+    StepEnt e[BATCH_MAX];
+};
+
 // ---------------------------------------------------------------------------
 // storage codecs.  One state buffer holds both sets, interleaved per population so
 // that one load brings h_i and g_i of a slot:

@@ -1,6 +1,7 @@
 // HIP kernels of the phase-field lattice Boltzmann library (gfx950).
 //
 //   k_step         one fused pull-stream + collide pass for both sets (Eqs. 1, 10)
+//   k_step_b       the same over a batch of contexts
 //   k_equilibrium  pre-collision equilibria from (phi, u, P); *_j_b: from (phi, J, P)
 //   k_set_state    pre-collision distributions -> pull storage
 //   k_get_state    pull storage -> pre-collision distributions
@@ -41,9 +42,10 @@ __device__ __forceinline__ void lds_barrier() {
 // MOVING: the variant for moving walls (momentum-corrected bounce-back, WallWriter),
 // kept apart so that the other variants carry none of its registers.
 template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
-__global__ void __launch_bounds__(TX * TY)
-k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
-       const char* __restrict__ src, char* __restrict__ dst) {
+__device__ __forceinline__ void step_tile(const Geom& G, const Model& m, const Codec& cd, int BZ,
+                                          int ntx, int nty, int nblk,
+                                          const char* __restrict__ src,
+                                          char* __restrict__ dst) {
     constexpr int Q = L::Q;
     constexpr int HX = TX + 2;
     constexpr int HY = L::USES_Y ? TY + 2 : 1;
@@ -130,6 +132,24 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         plane(z, hA, gA, loA, hB, gB, loB);
         if (z + 1 < zend) plane(z + 1, hB, gB, loB, hA, gA, loA);
     }
+}
+
+template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
+__global__ void __launch_bounds__(TX * TY)
+k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
+       const char* __restrict__ src, char* __restrict__ dst) {
+    step_tile<L, ST, TX, TY, WALLS, MOVING>(G, m, cd, BZ, ntx, nty, nblk, src, dst);
+}
+
+// The same step over a batch of resting-wall contexts that share lattice, storage and
+// geometry: blockIdx.y picks the context (its buffers and physical parameters),
+// blockIdx.x the tile.
+template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
+__global__ void __launch_bounds__(TX * TY)
+k_step_b(Geom G, int BZ, int ntx, int nty, int nblk, StepBatch bt) {
+    static_assert(!MOVING, "moving-wall contexts are stepped one by one");
+    const StepEnt& e = bt.e[blockIdx.y];
+    step_tile<L, ST, TX, TY, WALLS, false>(G, e.m, e.cd, BZ, ntx, nty, nblk, e.src, e.dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,35 +481,52 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(uint32_t N) { return dim3((N + 255u) / 256u); }
 
+// One step of one context (bt == nullptr: buffers s -> d, parameters a.m, a.cd) or of
+// the n contexts of a batch (blockIdx.y = context).
+struct StepArgs {
+    const char* s;
+    char* d;
+    const StepBatch* bt;
+    int n;
+};
+
 template <class L, class ST, int WALLS, int TX, int TY, bool MOVING = false>
-static hipError_t launch_tile(const Launch& a, const char* s, char* d) {
+static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
     const int ntx = (a.G.nx + TX - 1) / TX;
     const int nty = (a.G.ny + TY - 1) / TY;
     const int ntz = (a.G.nz + a.bz - 1) / a.bz;
     const int nblk = ntx * nty * ntz;
-    hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING>), dim3(nblk), dim3(TX * TY), 0,
-                       a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk, s, d);
+    if (x.bt) {
+        // batches hold resting-wall contexts only (moving ones are stepped one by one)
+        if constexpr (MOVING) return hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL((k_step_b<L, ST, TX, TY, WALLS, false>), dim3(nblk, x.n),
+                               dim3(TX * TY), 0, a.stream, a.G, a.bz, ntx, nty, nblk, *x.bt);
+    } else {
+        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING>), dim3(nblk), dim3(TX * TY), 0,
+                           a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk, x.s, x.d);
+    }
     return hipGetLastError();
 }
 
 template <class L, class ST, int WALLS>
-static hipError_t launch_step_t(const Launch& a, const char* s, char* d) {
+static hipError_t launch_step_t(const Launch& a, const StepArgs& x) {
     if constexpr (WALLS != WALLS_NONE) {
         // moving walls: one tile shape per lattice
         if (a.m.moving) {
-            if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, s, d);
-            else return launch_tile<L, ST, WALLS, 64, 1, true>(a, s, d);
+            if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, x);
+            else return launch_tile<L, ST, WALLS, 64, 1, true>(a, x);
         }
     }
     if constexpr (L::USES_Y) {
         switch (a.tile) {
-            case 1: return launch_tile<L, ST, WALLS, 64, 8>(a, s, d);
-            case 2: return launch_tile<L, ST, WALLS, 32, 8>(a, s, d);
-            case 3: return launch_tile<L, ST, WALLS, 32, 4>(a, s, d);
-            default: return launch_tile<L, ST, WALLS, 64, 4>(a, s, d);
+            case 1: return launch_tile<L, ST, WALLS, 64, 8>(a, x);
+            case 2: return launch_tile<L, ST, WALLS, 32, 8>(a, x);
+            case 3: return launch_tile<L, ST, WALLS, 32, 4>(a, x);
+            default: return launch_tile<L, ST, WALLS, 64, 4>(a, x);
         }
     } else {
-        return launch_tile<L, ST, WALLS, 64, 1>(a, s, d);
+        return launch_tile<L, ST, WALLS, 64, 1>(a, x);
     }
 }
 
@@ -498,24 +535,32 @@ static inline int wallset(const Geom& G) {
 }
 
 template <class L, class ST>
-static hipError_t dispatch_walls(const Launch& a, const char* s, char* d) {
+static hipError_t dispatch_walls(const Launch& a, const StepArgs& x) {
     switch (wallset(a.G)) {
-        case WALLS_XYZ: return launch_step_t<L, ST, WALLS_XYZ>(a, s, d);
-        case WALLS_XY: return launch_step_t<L, ST, WALLS_XY>(a, s, d);
-        case WALLS_Z: return launch_step_t<L, ST, WALLS_Z>(a, s, d);
-        default: return launch_step_t<L, ST, WALLS_NONE>(a, s, d);
+        case WALLS_XYZ: return launch_step_t<L, ST, WALLS_XYZ>(a, x);
+        case WALLS_XY: return launch_step_t<L, ST, WALLS_XY>(a, x);
+        case WALLS_Z: return launch_step_t<L, ST, WALLS_Z>(a, x);
+        default: return launch_step_t<L, ST, WALLS_NONE>(a, x);
     }
 }
 
-hipError_t launch_step(const Launch& a, const void* src, void* dst) {
-    auto s = static_cast<const char*>(src);
-    auto d = static_cast<char*>(dst);
+static hipError_t dispatch_step(const Launch& a, const StepArgs& x) {
     if (a.q == 19) {
-        if (a.half) return dispatch_walls<LatD3Q19, StoreF16S>(a, s, d);
-        return dispatch_walls<LatD3Q19, StoreF32>(a, s, d);
+        if (a.half) return dispatch_walls<LatD3Q19, StoreF16S>(a, x);
+        return dispatch_walls<LatD3Q19, StoreF32>(a, x);
     }
-    if (a.half) return dispatch_walls<LatD2Q9, StoreF16S>(a, s, d);
-    return dispatch_walls<LatD2Q9, StoreF32>(a, s, d);
+    if (a.half) return dispatch_walls<LatD2Q9, StoreF16S>(a, x);
+    return dispatch_walls<LatD2Q9, StoreF32>(a, x);
+}
+
+hipError_t launch_step(const Launch& a, const void* src, void* dst) {
+    return dispatch_step(a, StepArgs{static_cast<const char*>(src), static_cast<char*>(dst),
+                                     nullptr, 0});
+}
+
+hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n) {
+    if (n < 1 || n > BATCH_MAX) return hipErrorInvalidValue;
+    return dispatch_step(a, StepArgs{nullptr, nullptr, &bt, n});
 }
 
 template <class L>

@@ -708,7 +708,7 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         fJ[k] = J + 2 * k * HW;
         flb[k] = phi_lb + k * HW;
     }
-    std::vector<pflb_ctx*> acc_ctx;
+    std::vector<pflb_ctx*> acc_ctx, rej_ctx;
     std::vector<const float*> acc_phi, acc_P, acc_J;
     auto lb_fail = [&](int r, pflb_ctx* lc, const char* what) {
         return fail(c, r, std::string(what) + pflb_last_error(lc));
@@ -738,9 +738,8 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         if (checked) {
             // the plain steps from the same states are the reference; if a prediction
             // is rejected they are the fallback already taken
-            for (int k = 0; k < n; ++k)
-                if ((r = pflb_step(lbs[k], PFSUR_STEPS, st)))
-                    return lb_fail(r, lbs[k], "lattice steps: ");
+            if ((r = pflb_step_many(lbs, n, PFSUR_STEPS, st)))
+                return lb_fail(r, lbs[0], "lattice steps: ");
             if ((r = pflb_read_many(lbs, n, flb.data(), nullptr, nullptr, st)))
                 return lb_fail(r, lbs[0], "lattice read: ");
             SUR_TRY(maxdiff(phi, phi_lb, n, HW, fpart, GUARD_BLOCKS, st), "phi check");
@@ -762,6 +761,7 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         acc_phi.clear();
         acc_P.clear();
         acc_J.clear();
+        rej_ctx.clear();
         for (int k = 0; k < n; ++k) {
             // fixed-order host sums of the per-block partials (deterministic)
             double s_in = 0.0, s_out = 0.0, err = 0.0, speed = 0.0;
@@ -786,10 +786,12 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
                 acc_J.push_back(fJ[k]);
             } else {
                 *n_fallback += 1;
-                if (!checked && (r = pflb_step(lbs[k], PFSUR_STEPS, st)))
-                    return lb_fail(r, lbs[k], "fallback steps: ");
+                if (!checked) rej_ctx.push_back(lbs[k]);
             }
         }
+        if (!rej_ctx.empty() &&
+            (r = pflb_step_many(rej_ctx.data(), (int)rej_ctx.size(), PFSUR_STEPS, st)))
+            return lb_fail(r, rej_ctx[0], "fallback steps: ");
         if (!acc_ctx.empty() &&
             (r = pflb_reconstruct_many(acc_ctx.data(), (int)acc_ctx.size(), acc_phi.data(),
                                              acc_P.data(), acc_J.data(),

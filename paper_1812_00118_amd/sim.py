@@ -146,6 +146,18 @@ class Sim:
     def step(self, n=1):
         self._check(self.L.pflb_step(self.ctx, int(n), self._stream()))
 
+    @staticmethod
+    def step_many(sims, n=1):
+        """Advance several Sims by n steps each (pflb_step_many): one launch per step for
+        every 16 of them.  They must share lattice, storage, sizes and walls; the result
+        is what each one's own step(n) gives."""
+        sims = list(sims)
+        if not sims:
+            return
+        ctxs = (ctypes.c_void_p * len(sims))(*[s.ctx.value for s in sims])
+        s0 = sims[0]
+        s0._check(s0.L.pflb_step_many(ctxs, len(sims), int(n), s0._stream()))
+
     @property
     def steps(self):
         return int(self.L.pflb_step_count(self.ctx))

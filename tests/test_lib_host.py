@@ -168,6 +168,10 @@ def test_required_bytes_and_unbound_errors(L):
         assert L.pflb_required_bytes(ctypes.byref(p), 9) == 0
         # every state call before pflb_bind reports PFLB_ERR_UNBOUND without GPU work
         assert L.pflb_step(ctx, 1, None) == -3
+        one = (ctypes.c_void_p * 1)(ctx.value)
+        assert L.pflb_step_many(one, 1, 1, None) == -3
+        assert L.pflb_step_many(one, 0, 1, None) == -1      # empty batch
+        assert L.pflb_step_many(None, 1, 1, None) == -1
         assert L.pflb_set_state(ctx, None, None, None) == -3
         assert b"bound" in L.pflb_last_error(ctx)
         # misaligned pointers are refused
