@@ -1,7 +1,7 @@
 // HIP kernels of the phase-field lattice Boltzmann library (gfx950).
 //
-//   k_step         one fused pull-stream + collide pass for both sets (Eqs. 1, 10)
-//   k_step_b       the same over a batch of contexts
+//   k_step         one fused pull-stream + collide pass for both sets (Eqs. 1, 10), for
+//                  one context or a batch of contexts
 //   k_equilibrium  pre-collision equilibria from (phi, u, P); *_j_b: from (phi, J, P)
 //   k_set_state    pre-collision distributions -> pull storage
 //   k_get_state    pull storage -> pre-collision distributions
@@ -41,11 +41,30 @@ __device__ __forceinline__ void lds_barrier() {
 // ---------------------------------------------------------------------------
 // MOVING: the variant for moving walls (momentum-corrected bounce-back, WallWriter),
 // kept apart so that the other variants carry none of its registers.
-template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
-__device__ __forceinline__ void step_tile(const Geom& G, const Model& m, const Codec& cd, int BZ,
-                                          int ntx, int nty, int nblk,
-                                          const char* __restrict__ src,
-                                          char* __restrict__ dst) {
+//
+// BATCHED: a batch of resting-wall contexts that share lattice, storage and geometry;
+// blockIdx.y picks the context, whose buffers and parameters replace src, dst, m and cd.
+// (The single-context kernel takes an empty table; the body stays in the kernel itself,
+// which compiles to measurably faster code than the same body in an inlined function.)
+template <bool BATCHED>
+struct StepTable {};
+template <>
+struct StepTable<true> {
+    StepBatch bt;
+};
+
+template <class L, class ST, int TX, int TY, int WALLS, bool MOVING, bool BATCHED>
+__global__ void __launch_bounds__(TX * TY)
+k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
+       const char* __restrict__ src, char* __restrict__ dst, StepTable<BATCHED> tab) {
+    static_assert(!(BATCHED && MOVING), "moving-wall contexts are stepped one by one");
+    if constexpr (BATCHED) {
+        const StepEnt& e = tab.bt.e[blockIdx.y];
+        m = e.m;
+        cd = e.cd;
+        src = e.src;
+        dst = e.dst;
+    }
     constexpr int Q = L::Q;
     constexpr int HX = TX + 2;
     constexpr int HY = L::USES_Y ? TY + 2 : 1;
@@ -134,23 +153,6 @@ __device__ __forceinline__ void step_tile(const Geom& G, const Model& m, const C
     }
 }
 
-template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
-__global__ void __launch_bounds__(TX * TY)
-k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
-       const char* __restrict__ src, char* __restrict__ dst) {
-    step_tile<L, ST, TX, TY, WALLS, MOVING>(G, m, cd, BZ, ntx, nty, nblk, src, dst);
-}
-
-// The same step over a batch of resting-wall contexts that share lattice, storage and
-// geometry: blockIdx.y picks the context (its buffers and physical parameters),
-// blockIdx.x the tile.
-template <class L, class ST, int TX, int TY, int WALLS, bool MOVING>
-__global__ void __launch_bounds__(TX * TY)
-k_step_b(Geom G, int BZ, int ntx, int nty, int nblk, StepBatch bt) {
-    static_assert(!MOVING, "moving-wall contexts are stepped one by one");
-    const StepEnt& e = bt.e[blockIdx.y];
-    step_tile<L, ST, TX, TY, WALLS, false>(G, e.m, e.cd, BZ, ntx, nty, nblk, e.src, e.dst);
-}
 
 // ---------------------------------------------------------------------------
 // per-site helpers for the non-hot kernels
@@ -498,13 +500,19 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
     const int nblk = ntx * nty * ntz;
     if (x.bt) {
         // batches hold resting-wall contexts only (moving ones are stepped one by one)
-        if constexpr (MOVING) return hipErrorInvalidValue;
-        else
-            hipLaunchKernelGGL((k_step_b<L, ST, TX, TY, WALLS, false>), dim3(nblk, x.n),
-                               dim3(TX * TY), 0, a.stream, a.G, a.bz, ntx, nty, nblk, *x.bt);
+        if constexpr (MOVING) {
+            return hipErrorInvalidValue;
+        } else {
+            StepTable<true> tab;
+            tab.bt = *x.bt;
+            hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, false, true>), dim3(nblk, x.n),
+                               dim3(TX * TY), 0, a.stream, a.G, a.m, a.cd, a.bz, ntx, nty,
+                               nblk, (const char*)nullptr, (char*)nullptr, tab);
+        }
     } else {
-        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING>), dim3(nblk), dim3(TX * TY), 0,
-                           a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk, x.s, x.d);
+        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING, false>), dim3(nblk),
+                           dim3(TX * TY), 0, a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk,
+                           x.s, x.d, StepTable<false>{});
     }
     return hipGetLastError();
 }
