@@ -24,6 +24,11 @@ Workloads (lattice units, rho_L = 1):
                    uniform on the torus at least W apart (edge to edge), each drop moving
                    with a random velocity |u| <= 0.02; nu_H = nu_L = 0.01, M = 0.1, W = 4,
                    sigma = 1e-2.  Seeds: train 0-255, validation 1000-1031, test 2000-2031.
+  dense_bubble     D2Q9 80x40 periodic water (phi = 1) holding a dense bubble (a shallow
+                   Gaussian dip, phi 0.93 at its centre, standard deviation 3 sites) and
+                   a decent bubble (phi = 0 inside, R = 10) 40 sites apart; rho_H = 1000,
+                   nu_H = nu_L = 0.1, W = 3, M = 0.17 (Section 3's dense-bubble values of W
+                   and M), sigma = 1e-3, u = 0, P = 0; dtheta_C as given.
 """
 import math
 
@@ -46,6 +51,14 @@ def static_droplet(n=64, R=16.0, W=4.0, rho_H=1000.0, sigma=1e-3, nu=0.01, M=0.1
                 bc=(PERIODIC, PERIODIC, PERIODIC), rho_L=1.0, rho_H=rho_H, nu_L=nu,
                 nu_H=nu, M=M, W=W, sigma=sigma, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1,
                 dtheta_C=0.0, R=R, steps=1000)
+
+
+def dense_bubble(nx=80, ny=40, C=10.0, depth=0.07, spread=3.0, R=10.0):
+    return dict(name="dense_bubble", lattice=9, shape=(nx, ny, 1),
+                bc=(PERIODIC, PERIODIC, PERIODIC), rho_L=1.0, rho_H=1000.0, nu_L=0.1,
+                nu_H=0.1, M=0.17, W=3.0, sigma=1e-3, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1,
+                dtheta_C=C, depth=depth, spread=spread, R=R,
+                dense_at=(nx / 4.0, (ny - 1) / 2.0), decent_at=(3.0 * nx / 4.0, (ny - 1) / 2.0))
 
 
 def rayleigh_taylor(nx=256, ny=1024):
@@ -218,7 +231,21 @@ def fields_drops(cfg):
     return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
 
 
+def fields_dense_bubble(cfg):
+    """phi = min(1 - depth exp(-r1^2 / (2 spread^2)), tanh bubble of radius R at r2)."""
+    z, y, x = _grid(cfg["shape"])
+    (ax, ay), (bx, by) = cfg["dense_at"], cfg["decent_at"]
+    r1 = np.sqrt((x - ax) ** 2 + (y - ay) ** 2)
+    r2 = np.sqrt((x - bx) ** 2 + (y - by) ** 2)
+    dense = 1.0 - cfg["depth"] * np.exp(-r1 ** 2 / (2.0 * cfg["spread"] ** 2))
+    decent = 0.5 + 0.5 * np.tanh(2.0 * (r2 - cfg["R"]) / cfg["W"])
+    phi = np.minimum(dense, decent)
+    u = np.zeros((3,) + phi.shape)
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
 FIELDS = {"static_droplet": fields_static_droplet,
+          "dense_bubble": fields_dense_bubble,
           "drops": fields_drops,
           "rayleigh_taylor": fields_rayleigh_taylor,
           "rising_bubble": fields_rising_bubble,

@@ -1,4 +1,4 @@
-"""The dimensionless groups the paper prints (Section 3) against the readings of its units.
+"""The dimensionless groups the paper prints (Sections 4.2-4.4) against the readings of its units.
 
 The paper gives only density ratios.  Its printed capillary and Weber numbers contain the
 water density, and they come out as printed only with the light phase at density 1 and

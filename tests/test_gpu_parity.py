@@ -357,6 +357,32 @@ def test_dense_bubble_correction_parity():
     assert abs(m1 - m0) / m0 <= 1e-6
 
 
+def test_dense_bubble_case_parity_and_behaviour():
+    """Section 3's dense-bubble situation with the Eq. 14 correction at C = 10.  F is
+    discontinuous: where (phi - 1/2) lap(phi) crosses zero a rounding-level difference
+    switches the correction on or off at a site, so this case is ill-conditioned (the
+    oracle's own phi moves by ~4e-3 after 300 steps when its start moves by 1e-7, against
+    ~2e-6 without the correction).  phi and J after 300 steps are compared with the
+    conditioning-aware bar (4x the oracle's own divergence from a float32 half-ulp change
+    of its start); after 1,500 steps the dense bubble is diffused away (minimum above
+    0.975) and the decent bubble keeps phi = 0 inside, as in the oracle; sum(phi) is
+    conserved."""
+    cfg = pfinputs.dense_bubble(C=10.0)
+    r, ro, (m0, m1, bad), _ = _run_pair(cfg, 300, conditioning=True)
+    assert not bad and abs(m1 - m0) <= 1e-6 * m0
+    _check_conditioned(cfg, r, ro, 2)
+    phi, u, P = pfinputs.fields(cfg)
+    sim = _sim(cfg)
+    sim.init_fields(phi, u, P)
+    sim.step(1500)
+    p = _np(sim.read(("phi",))["phi"])[0]
+    m2, bad = sim.mass()
+    nx = cfg["shape"][0]
+    assert not bad and abs(m2 - m0) <= 1e-6 * m0
+    assert p[:, : nx // 2].min() > 0.975
+    assert p[:, nx // 2:].min() < 1e-3
+
+
 def test_determinism_and_checkpoint(tmp_path):
     """Two identical runs are bitwise equal; save at step k, load, continue is bitwise
     equal to running straight through."""
