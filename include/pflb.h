@@ -82,7 +82,9 @@ extern "C" {
  *   g[3]         gravitational acceleration; the external force is rho(phi) g
  *   eps          the small constant of the interface normal (text after Eq. 4)
  *   hoc          1: high-order equilibrium correction and modified velocity (Eq. 13)
- *   dtheta_C     C of the dense-bubble correction (Eq. 14); 0 switches it off
+ *   dtheta_C     C of the dense-bubble correction (Eq. 14, with F = -1 where |phi - 1/2|
+ *                > 0.35 and (phi - 1/2) lap(phi) > 0, else 0); 0 switches it off, 10
+ *                diffuses dense bubbles away
  *   storage      PFLB_STORE_FP32 or PFLB_STORE_FP16S
  *   scale_log2   power-of-two scale exponents of the fp16 deviations of h and g
  *                (FP16S only; each in [-14, 24])

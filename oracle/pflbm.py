@@ -22,8 +22,9 @@ Readings of points the paper leaves open (each is also listed in the design note
 * External force F_ex = rho(phi) g (gravity as a body force on the local density).
 * Dense-bubble correction (Eq. 14): the paper leaves C and F open.  Used here:
   F = -1 where |phi - 1/2| > 0.35 and (phi - 1/2) lap(phi) > 0, else 0; C is a
-  parameter (default 0: correction off).  PARITY UNPINNED beyond C = 0 and mass
-  conservation.
+  parameter (default 0: correction off; 10 removes a seeded dense bubble and leaves a
+  decent one, as Section 3 describes).  PARITY UNPINNED beyond C = 0, mass conservation
+  and that behaviour.
 * Boundaries: periodic axes wrap; wall axes use halfway bounce-back for both sets,
   and the ghost value of phi outside a wall equals the adjacent fluid site's value
   (zero normal gradient).
