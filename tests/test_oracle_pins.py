@@ -309,3 +309,93 @@ def test_step_sites_matches_step(lat):
     x, y, z = sites.T
     assert np.allclose(hs, h1[:, z, y, x], atol=1e-15, rtol=1e-13)
     assert np.allclose(gs, g1[:, z, y, x], atol=1e-13, rtol=1e-12)
+
+
+def _collide_brute_force(q, c_list, prm, h, g, phi_nb):
+    """One site's collision in 50-digit arithmetic, from the definitions, with the filter
+    applied as the explicit Q x Q matrix of Section 2's footnote,
+    A_il = w_i/(2T^2) [(c_i.c_l)^2 - T |c_l|^2], acting on g - g^eq (not through Pi).
+    Weights from the speed classes: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    f = mp.mpf
+    Tm = f(1) / 3
+    wc = {9: (f(4) / 9, f(1) / 9, f(1) / 36), 19: (f(1) / 3, f(1) / 18, f(1) / 36)}[q]
+    cs = [tuple(int(v) for v in c) for c in c_list]
+    w = [wc[sum(v * v for v in c)] for c in cs]
+    opp = [cs.index(tuple(-v for v in c)) for c in cs]
+    h = [f(float(v)) for v in h]
+    g = [f(float(v)) for v in g]
+    pn = [f(float(v)) for v in phi_nb]
+    dot = lambda a, b: sum(x * y for x, y in zip(a, b))
+    rho_L, rho_H = f(prm.rho_L), f(prm.rho_H)
+    rdif = rho_H - rho_L
+    tau_L = f(prm.nu_L) / Tm + f(1) / 2
+    tau_H = f(prm.nu_H) / Tm + f(1) / 2
+    M, W, sig, eps, C = f(prm.M), f(prm.W), f(prm.sigma), f(prm.eps), f(prm.dtheta_C)
+    beta = f(1) if prm.hoc else f(0)
+    gvec = [f(float(v)) for v in prm.g]
+    phi = pn[0]
+    grad = [sum(w[i] * cs[i][a] * (pn[i] - pn[opp[i]]) for i in range(q)) / (2 * Tm)
+            for a in range(3)]
+    lap = (2 / Tm) * sum(w[i] * (pn[i] - phi) for i in range(q))
+    rho = rho_L + phi * rdif
+    om = 1 / tau_L + phi * (1 / tau_H - 1 / tau_L)
+    mu = (48 * sig / W) * phi * (phi - 1) * (phi - f(1) / 2) - (3 * sig * W / 2) * lap
+    gn = mp.sqrt(dot(grad, grad))
+    n = [x / (gn + eps) for x in grad]
+    theta = (M / Tm) * (1 - 4 * (phi - f(1) / 2) ** 2) / W
+    if C != 0 and abs(phi - f(1) / 2) > f(35) / 100 and (phi - f(1) / 2) * lap > 0:
+        theta -= C * (M / Tm) * gn
+    F = [rho * x for x in gvec]
+    J = [sum(cs[i][a] * g[i] for i in range(q)) + (mu * grad[a] + F[a]) / 2 for a in range(3)]
+    u = [x / (rho + beta * rdif * lap / 4) for x in J]
+    P = Tm * sum(g) + (Tm * rdif / 2) * dot(u, grad)
+    uu = dot(u, u)
+    Gam = [w[i] * (1 + dot(cs[i], u) / Tm + dot(cs[i], u) ** 2 / (2 * Tm ** 2) - uu / (2 * Tm))
+           for i in range(q)]
+    heq = [phi * Gam[i] + theta * w[i] * dot(cs[i], n) for i in range(q)]
+    om_phi = 1 / (M / Tm + f(1) / 2)
+    hs = [h[i] - om_phi * (h[i] - heq[i]) for i in range(q)]
+    K = []
+    for i in range(q):
+        cmu = [cs[i][a] - u[a] for a in range(3)]
+        K.append(((Gam[i] - w[i]) * rdif + Gam[i] * mu / Tm) * dot(cmu, grad)
+                 + Gam[i] * dot(cmu, F) / Tm)
+    geq = [rho * Gam[i] + w[i] * (P / Tm - rho) - K[i] / 2
+           + beta * w[i] * dot(cs[i], u) * rdif * lap / (4 * Tm) for i in range(q)]
+    A = [[w[i] / (2 * Tm ** 2) * (dot(cs[i], cs[l]) ** 2 - Tm * dot(cs[l], cs[l]))
+          for l in range(q)] for i in range(q)]
+    neq = [g[l] - geq[l] for l in range(q)]
+    gs = [geq[i] + K[i] + (1 - om) * sum(A[i][l] * neq[l] for l in range(q))
+          for i in range(q)]
+    return np.array([float(v) for v in hs]), np.array([float(v) for v in gs])
+
+
+BRUTE_CASES = [  # (lattice, hoc, dtheta_C, phi at the site, neighbour spread)
+    (9, 1, 0.0, 0.62, 0.2), (9, 0, 0.0, 0.37, 0.2), (19, 1, 0.0, 0.55, 0.2),
+    (19, 1, 10.0, 0.93, 0.03),   # a dense dip: the Eq. 14 branch is taken
+]
+
+
+@pytest.mark.parametrize("q,hoc,C,phi0,spread", BRUTE_CASES)
+def test_single_site_collision_brute_force(q, hoc, C, phi0, spread):
+    """The oracle's FP64 collision of one site against the same step evaluated in 50-digit
+    arithmetic with the filter as the explicit Q x Q matrix: agreement to FP64 rounding."""
+    lat = D2Q9 if q == 9 else D3Q19
+    rng = np.random.default_rng(q * 100 + int(10 * C) + hoc)
+    gz = 3e-4 if q == 19 else 0.0
+    prm = _prm(q, (1, 1, 1), rho_H=1000.0, nu_L=0.05, nu_H=0.01, M=0.1, W=4.0, sigma=1e-3,
+               g=(1e-4, -2e-4, gz), eps=1e-10, hoc=hoc, dtheta_C=C)
+    w = np.array([{0: 4 / 9, 1: 1 / 9, 2: 1 / 36}[int(c @ c)] if q == 9 else
+                  {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}[int(c @ c)] for c in lat.c])
+    h = w * (phi0 + 0.05 * rng.standard_normal(q))
+    g = w * (0.3 + 2.0 * rng.standard_normal(q))
+    phi_nb = phi0 + spread * rng.uniform(0.1, 1.0, q) * (1.0 if C else rng.choice([-1, 1], q))
+    phi_nb[0] = phi0
+    hs, gs, m = O.collide(lat, prm, h[:, None], g[:, None], phi_nb[:, None])
+    hb, gb = _collide_brute_force(q, lat.c, prm, h, g, phi_nb)
+    if C:
+        assert m["theta"][0] < (prm.M / T) * (1 - 4 * (phi0 - 0.5) ** 2) / prm.W   # taken
+    assert np.abs(hs[:, 0] - hb).max() <= 1e-13 * np.abs(hb).max()
+    assert np.abs(gs[:, 0] - gb).max() <= 1e-12 * np.abs(gb).max()
