@@ -535,6 +535,43 @@ __device__ __forceinline__ float load_h_acc(const char* __restrict__ b, uint32_t
     }
 }
 
+// Raw moments of the hydrodynamic set up to second order, sum g, sum c g and sum c c g:
+// all that the filtered collision uses of the pre-collision g (Eqs. 10-12: g* depends on
+// g only through P, J and Pi), so a site keeps 10 numbers instead of Q populations.
+// Each sum runs over the directions in index order.
+struct GMom {
+    float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    float xx = 0.f, yy = 0.f, zz = 0.f, xy = 0.f, xz = 0.f, yz = 0.f;
+};
+
+template <class L, int I>
+__device__ __forceinline__ void add_moment(GMom& m, float g) {
+    constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+    m.s += g;
+    if constexpr (ex > 0) m.jx += g;
+    if constexpr (ex < 0) m.jx -= g;
+    if constexpr (ey > 0) m.jy += g;
+    if constexpr (ey < 0) m.jy -= g;
+    if constexpr (ez > 0) m.jz += g;
+    if constexpr (ez < 0) m.jz -= g;
+    if constexpr (ex != 0) m.xx += g;
+    if constexpr (ey != 0) m.yy += g;
+    if constexpr (ez != 0) m.zz += g;
+    if constexpr (ex * ey > 0) m.xy += g;
+    if constexpr (ex * ey < 0) m.xy -= g;
+    if constexpr (ex * ez > 0) m.xz += g;
+    if constexpr (ex * ez < 0) m.xz -= g;
+    if constexpr (ey * ez > 0) m.yz += g;
+    if constexpr (ey * ez < 0) m.yz -= g;
+}
+
+template <class L>
+__device__ __forceinline__ GMom g_moments(const float (&g)[L::Q]) {
+    GMom m;
+    static_for<0, L::Q>([&](auto I) { add_moment<L, decltype(I)::value>(m, g[decltype(I)::value]); });
+    return m;
+}
+
 // Gather the Q pre-collision populations of both sets of one site and its phi.
 template <class L, class ST, int WALLS>
 __device__ __forceinline__ double pull_site(const char* __restrict__ b, const Geom& G,
@@ -569,6 +606,26 @@ __device__ __forceinline__ double pull_site_h(const char* __restrict__ b, const 
     return acc.value();
 }
 
+// Gather the h populations of one site, the raw moments of its g populations and its
+// phi: the form the fused step keeps a site in between the gather and the collision.
+template <class L, class ST, int WALLS>
+__device__ __forceinline__ double pull_site_m(const char* __restrict__ b, const Geom& G,
+                                              const Col& c, const ZRow& r, const Codec& cd,
+                                              float (&h)[L::Q], GMom& gm) {
+    PhiAcc acc;
+    gm = GMom{};
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        uint32_t s;
+        bool flip;
+        upstream<L, i, WALLS>(c, r, s, flip);
+        const float2 v = load_pair_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
+        h[i] = v.x;
+        add_moment<L, i>(gm, v.y);
+    });
+    return acc.value();
+}
+
 // float64 phi as hi + lo floats
 __device__ __forceinline__ float split_hi_lo(double s, float& lo) {
     const float hi = (float)s;
@@ -588,7 +645,7 @@ struct Macro {
 // pn[k] = phi(x + c_k), g = pre-collision hydrodynamic populations at x
 template <class L>
 __device__ __forceinline__ Macro macros(const Model& m, const float (&pn)[L::Q],
-                                        const float (&g)[L::Q]) {
+                                        const GMom& gm) {
     Macro a;
     a.phi = pn[0];
     // grad: pairs i, opp(i) contribute equally -> sum over odd i of w_i c_i (phi+ - phi-)/T
@@ -620,20 +677,10 @@ __device__ __forceinline__ Macro macros(const Model& m, const float (&pn)[L::Q],
         a.theta = fmaf(dense ? -m.dth : 0.0f, gn, a.theta);
     }
     a.Fx = a.rho * m.gx; a.Fy = a.rho * m.gy; a.Fz = a.rho * m.gz;
-    float sg = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        sg += g[i];
-        if constexpr (L::cx(i) > 0) jx += g[i];
-        if constexpr (L::cx(i) < 0) jx -= g[i];
-        if constexpr (L::cy(i) > 0) jy += g[i];
-        if constexpr (L::cy(i) < 0) jy -= g[i];
-        if constexpr (L::cz(i) > 0) jz += g[i];
-        if constexpr (L::cz(i) < 0) jz -= g[i];
-    });
-    a.jx = fmaf(0.5f, fmaf(a.mu, gx, a.Fx), jx);
-    a.jy = fmaf(0.5f, fmaf(a.mu, gy, a.Fy), jy);
-    a.jz = fmaf(0.5f, fmaf(a.mu, gz, a.Fz), jz);
+    const float sg = gm.s;
+    a.jx = fmaf(0.5f, fmaf(a.mu, gx, a.Fx), gm.jx);
+    a.jy = fmaf(0.5f, fmaf(a.mu, gy, a.Fy), gm.jy);
+    a.jz = fmaf(0.5f, fmaf(a.mu, gz, a.Fz), gm.jz);
     const float rho_p = fmaf(m.beta * 0.25f * m.rho_dif, a.lap, a.rho);
     const float irp = 1.0f / rho_p;
     a.ux = a.jx * irp; a.uy = a.jy * irp; a.uz = a.jz * irp;
@@ -699,7 +746,7 @@ __device__ __forceinline__ void eq_dir(const Macro& a, const EqTerms& t, float& 
 // c.u, c.d, c.F and c.n.  a.phi + phi_lo is the site's phi (see PhiAcc).
 template <class L, class Out>
 __device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, float phi_lo,
-                                               const float (&h)[L::Q], const float (&g)[L::Q],
+                                               const float (&h)[L::Q], const GMom& gm,
                                                Out& out) {
     constexpr float third = 1.0f / 3.0f;
     const float ux = a.ux, uy = a.uy, uz = a.uz;
@@ -712,20 +759,7 @@ __device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, f
     const float P3 = 3.0f * a.P;
     const float om1 = 1.0f - a.itau;
     // raw second moments of g over the lattice's axes
-    float Mxx = 0.f, Myy = 0.f, Mzz = 0.f, Mxy = 0.f, Mxz = 0.f, Myz = 0.f;
-    static_for<1, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-        if constexpr (ex != 0) Mxx += g[i];
-        if constexpr (ey != 0) Myy += g[i];
-        if constexpr (ez != 0) Mzz += g[i];
-        if constexpr (ex * ey > 0) Mxy += g[i];
-        if constexpr (ex * ey < 0) Mxy -= g[i];
-        if constexpr (ex * ez > 0) Mxz += g[i];
-        if constexpr (ex * ez < 0) Mxz -= g[i];
-        if constexpr (ey * ez > 0) Myz += g[i];
-        if constexpr (ey * ez < 0) Myz -= g[i];
-    });
+    const float Mxx = gm.xx, Myy = gm.yy, Mzz = gm.zz, Mxy = gm.xy, Mxz = gm.xz, Myz = gm.yz;
     auto pi = [&](float M, float ua, float ub, float da, float db, float Fa, float Fb,
                   bool diag) {
         float sK = A * (fmaf(ua, db, ub * da) * third - ua * ub * ug) + fmaf(ua, Fb, ub * Fa) -

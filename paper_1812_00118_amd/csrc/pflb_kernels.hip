@@ -106,7 +106,8 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         return (float)pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f);
     };
 
-    float hA[Q], gA[Q], loA, hB[Q], gB[Q], loB;
+    float hA[Q], loA, hB[Q], loB;
+    GMom gA, gB;
     {   // plane z0 - 1 (phi only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
         float f[Q];
@@ -114,14 +115,14 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm);
         const ZRow r0 = make_zrow(G, z0);
         sphi[z0 & 3][ty + OY][tx + 1] =
-            split_hi_lo(pull_site<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA);
+            split_hi_lo(pull_site_m<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA);
         if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0);
     }
     // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc).
-    auto plane = [&](int z, const float (&hc)[Q], const float (&gc)[Q], float lo_c,
-                     float (&hn)[Q], float (&gn)[Q], float& lo_n) {
+    auto plane = [&](int z, const float (&hc)[Q], const GMom& gc, float lo_c,
+                     float (&hn)[Q], GMom& gn, float& lo_n) {
         const ZRow rn = make_zrow(G, map_coord(z + 1, G.nz, G.wz));
-        const double pn64 = (z + 1 < zend) ? pull_site<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
+        const double pn64 = (z + 1 < zend) ? pull_site_m<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
                                            : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
         sphi[(z + 1) & 3][ty + OY][tx + 1] = split_hi_lo(pn64, lo_n);
         if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
@@ -223,7 +224,7 @@ __device__ __forceinline__ void equilibrium_site(const Geom& G, const Model& m, 
     // macros with the given u and P: feed a zero g and overwrite J/u/P
     float zero[L::Q];
     static_for<0, L::Q>([&](auto I) { zero[decltype(I)::value] = 0.0f; });
-    Macro a = macros<L>(m, pn, zero);
+    Macro a = macros<L>(m, pn, g_moments<L>(zero));
     float uu[3] = {0.f, 0.f, 0.f};
     if (u) {
         for (int c = 0; c < L::D; ++c) uu[user_axis<L>(c)] = u[(size_t)c * N + s];
@@ -353,7 +354,7 @@ __device__ __forceinline__ void macro_site(const Geom& G, const Model& m, const 
     float pn[L::Q], hv[L::Q], gv[L::Q];
     phi_stencil<L>(G, phi, x, y, z, pn);
     pull_site<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, hv, gv);
-    const Macro a = macros<L>(m, pn, gv);
+    const Macro a = macros<L>(m, pn, g_moments<L>(gv));
     if (P) P[s] = a.P;
     const float jv[3] = {a.jx, a.jy, a.jz};
     const float uv[3] = {a.ux, a.uy, a.uz};
