@@ -34,6 +34,14 @@ Readings of points the paper leaves open (each is also listed in the design note
   times phi(x) (set h) or rho(x) (set g), the site's pre-collision values.  u_w is the
   velocity of the face crossed; a population that crosses two or three wall faces at an
   edge or corner takes the mean of their velocities.  Face velocities are tangential.
+* Open faces (the paper's "pressure condition" of the dam-break case names no
+  mechanism; used here: the sites beyond an open face are copies of the boundary-layer
+  sites they face, zero normal gradient of phi and u, with the pressure extrapolated
+  linearly to the face's P_f): a population i entering x through the face comes from
+  s' = x - c_i with its out-of-range coordinate put back into the layer, as f*_i(s'),
+  plus 2 w_i (P_f - P(s'))/T for g.  A population that crosses a closed wall face as
+  well is bounced back (with the mean velocity of the closed faces it crosses); one that
+  crosses several open faces takes the mean of their P_f.
 * No clipping of phi anywhere; n = grad(phi)/(|grad(phi)| + eps) exactly as printed.
 """
 import numpy as np
@@ -54,7 +62,8 @@ class Params:
     """
 
     def __init__(self, lattice, shape, bc, rho_L, rho_H, nu_L, nu_H, M, W, sigma,
-                 g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0, wall_u=None):
+                 g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0, wall_u=None,
+                 open_P=None):
         self.lat = _lattice(lattice)
         nx, ny, nz = shape
         if self.lat.D == 2 and nz != 1:
@@ -82,6 +91,22 @@ class Params:
                 raise ValueError("a wall moves tangentially: normal velocity must be 0")
             if self.bc[a] != WALL and np.any(self.wall_u[f] != 0.0):
                 raise ValueError("velocity given for a face of a periodic axis")
+        # open faces: pressure P given per face (None or NaN: a closed wall)
+        self.open_P = (np.full(6, np.nan) if open_P is None
+                       else np.asarray(open_P, dtype=np.float64).reshape(6).copy())
+        for f, (a, _) in enumerate(FACES):
+            if np.isnan(self.open_P[f]):
+                continue
+            if self.bc[a] != WALL:
+                raise ValueError("an open face must be on a wall axis")
+            if np.any(self.wall_u[f] != 0.0):
+                raise ValueError("an open face has no wall velocity")
+            if not np.isfinite(self.open_P[f]):
+                raise ValueError("open-face pressure must be finite")
+
+    @property
+    def open_faces(self):
+        return [f for f in range(6) if not np.isnan(self.open_P[f])]
 
     # Eq. 1: relaxation time of h is M/T + 0.5
     @property
@@ -105,7 +130,7 @@ class Params:
     @classmethod
     def from_dict(cls, d):
         keys = ("lattice", "shape", "bc", "rho_L", "rho_H", "nu_L", "nu_H", "M", "W",
-                "sigma", "g", "eps", "hoc", "dtheta_C", "wall_u")
+                "sigma", "g", "eps", "hoc", "dtheta_C", "wall_u", "open_P")
         return cls(**{k: d[k] for k in keys if k in d})
 
 
@@ -319,21 +344,62 @@ def _source_solid(c, shape, bc):
     return solid
 
 
-def wall_cu(prm, k, xyz):
-    """c_k . u_w for populations leaving the sites xyz (N, 3 integer (x, y, z)) in
-    direction k: u_w is the velocity of the wall face the population crosses, the mean of
-    the crossed faces' velocities at an edge or corner, 0 where it crosses none."""
+def _crossed(prm, k, xyz):
+    """(N, 6) mask of the faces (FACES order) a population leaving the sites xyz (N, 3
+    integer (x, y, z)) in direction k crosses."""
     c = prm.lat.c[k]
-    s = np.zeros(len(xyz))
-    n = np.zeros(len(xyz))
+    out = np.zeros((len(xyz), 6), dtype=bool)
     for f, (a, side) in enumerate(FACES):
         if prm.bc[a] != WALL or c[a] != side:
             continue
         dest = xyz[:, a] + c[a]
-        crossed = (dest < 0) | (dest >= prm.shape[a])
-        s += np.where(crossed, float(c @ prm.wall_u[f]), 0.0)
-        n += crossed
-    return np.where(n > 0, s / np.maximum(n, 1.0), 0.0)
+        out[:, f] = (dest < 0) | (dest >= prm.shape[a])
+    return out
+
+
+def wall_cu(prm, k, xyz):
+    """c_k . u_w for populations leaving the sites xyz (N, 3 integer (x, y, z)) in
+    direction k: u_w is the velocity of the closed wall face the population crosses, the
+    mean of the crossed closed faces' velocities at an edge or corner, 0 where it crosses
+    none."""
+    c = prm.lat.c[k]
+    closed = _crossed(prm, k, xyz)
+    closed[:, prm.open_faces] = False
+    s = (closed * (prm.wall_u @ c)[None, :]).sum(1)
+    n = closed.sum(1)
+    return np.where(n > 0, s / np.maximum(n, 1), 0.0)
+
+
+def open_return(prm, i, xyz, m, which, fstar):
+    """Populations i arriving at the sites xyz from beyond open faces: (mask of those
+    whose source x - c_i crosses open faces only, their values).  The site beyond an
+    open face is a copy of the site of the boundary layer it faces (zero normal gradient
+    of phi and u) with the pressure extrapolated linearly to P_f at the face: the source
+    x - c_i, its out-of-range coordinates put back into the layer, is the site s' that
+    population i comes from, with value f*_i(s') and, for g, plus 2 w_i (P_f - P(s'))/T
+    (the filtered collision depends on P only through w_i P/T).  m: the sites'
+    macroscopic quantities (P), flattened; fstar: post-collision populations, flattened
+    per direction."""
+    lat = prm.lat
+    k = lat.opp[i]
+    cr = _crossed(prm, k, xyz)
+    is_open = np.zeros(6, dtype=bool)
+    is_open[prm.open_faces] = True
+    only_open = cr.any(1) & ~(cr & ~is_open[None, :]).any(1)
+    nx, ny, nz = prm.shape
+    src = xyz - lat.c[i][None, :]
+    for a, n in enumerate((nx, ny, nz)):
+        if prm.bc[a] == WALL:
+            src[:, a] = np.clip(src[:, a], 0, n - 1)
+        else:
+            src[:, a] %= n
+    lin = (src[:, 2] * ny + src[:, 1]) * nx + src[:, 0]
+    val = fstar[i][lin]
+    if which == "g":
+        Pf = np.where(is_open, np.nan_to_num(prm.open_P), 0.0)
+        P = (cr * Pf[None, :]).sum(1) / np.maximum(cr.sum(1), 1)
+        val = val + 2.0 * lat.w[i] * (P - m["P"][lin]) / T
+    return only_open, val
 
 
 def _all_sites(shape):
@@ -342,21 +408,31 @@ def _all_sites(shape):
     return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
 
 
-def stream(lat, prm, fstar, scale=None):
+def stream(lat, prm, fstar, m=None, which="h"):
     """f_i(x, n+1) = f*_i(x - c_i, n); where x - c_i is outside a wall the population
     comes back from x itself: f_i(x, n+1) = f*_opp(i)(x, n) (halfway bounce-back), less
-    2 w (c_opp(i) . u_w)/T scale(x) for a moving wall (scale: phi for h, rho for g)."""
+    2 w (c_opp(i) . u_w)/T times phi(x) (which = "h") or rho(x) ("g") for a moving wall,
+    or by anti-bounce-back through an open face (open_return).  m: the pre-collision
+    macroscopic quantities of the step (needed for moving walls and open faces)."""
     out = np.empty_like(fstar)
-    moving = scale is not None and np.any(prm.wall_u != 0.0)
-    xyz = _all_sites(prm.shape) if moving else None
+    moving = m is not None and np.any(prm.wall_u != 0.0)
+    opens = m is not None and len(prm.open_faces) > 0
+    xyz = _all_sites(prm.shape) if (moving or opens) else None
+    if opens:
+        mf = {"P": m["P"].ravel()}
     for i in range(lat.Q):
         c = lat.c[i]
         pulled = np.roll(fstar[i], shift=(int(c[2]), int(c[1]), int(c[0])), axis=(0, 1, 2))
-        back = fstar[lat.opp[i]]
+        j = lat.opp[i]
+        back = fstar[j]
         if moving:
-            j = lat.opp[i]
             cu = wall_cu(prm, j, xyz).reshape(back.shape)
+            scale = m["phi"] if which == "h" else m["rho"]
             back = back - (2.0 / T) * lat.w[j] * cu * scale
+        if opens:
+            only_open, val = open_return(prm, i, xyz, mf, which,
+                                         fstar.reshape(lat.Q, -1))
+            back = np.where(only_open.reshape(back.shape), val.reshape(back.shape), back)
         out[i] = np.where(_source_solid(c, prm.shape, prm.bc), back, pulled)
     return out
 
@@ -371,7 +447,7 @@ def step(prm, h, g):
     phi = h.sum(0)
     phi_nb = phi_stencil(phi, lat, prm.bc)
     hstar, gstar, m = collide(lat, prm, h, g, phi_nb)
-    return stream(lat, prm, hstar, m["phi"]), stream(lat, prm, gstar, m["rho"])
+    return stream(lat, prm, hstar, m, "h"), stream(lat, prm, gstar, m, "g")
 
 
 def run(prm, h, g, nsteps):
@@ -473,6 +549,8 @@ def step_sites(prm, h, g, sites):
     h_out = np.empty((lat.Q, S))
     g_out = np.empty((lat.Q, S))
     moving = np.any(prm.wall_u != 0.0)
+    if prm.open_faces:
+        raise NotImplementedError("sampled-site steps with open faces")
     for i in range(lat.Q):
         h_out[i] = hstar[pop[:, i], rows, i]
         g_out[i] = gstar[pop[:, i], rows, i]

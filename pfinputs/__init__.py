@@ -133,6 +133,8 @@ def model_params(cfg):
     d = {k: cfg[k] for k in keys}
     if cfg.get("wall_u") is not None:       # wall face velocities, rows x-, x+, y-, y+, z-, z+
         d["wall_u"] = np.asarray(cfg["wall_u"], dtype=np.float64).reshape(6, 3)
+    if cfg.get("open_P") is not None:       # open-face pressures, same order (NaN: closed)
+        d["open_P"] = np.asarray(cfg["open_P"], dtype=np.float64).reshape(6)
     return d
 
 

@@ -320,3 +320,53 @@ def test_dense_bubble_correction_removes_dense_not_decent_bubbles():
     assert out["corrected"][:, dense].min() > 0.975
     assert out["corrected"][:, decent].min() < 1e-3
     assert np.abs(out["corrected"][:, decent] - out["plain"][:, decent]).max() < 0.01
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_pressure_driven_channel_is_poiseuille(q):
+    """Open faces (the pressure condition of Section 4.4's dam-break case, mechanism not
+    given in the paper; here a zero-normal-gradient ghost layer with the pressure
+    extrapolated to the face's value): a water channel between no-slip walls with open
+    ends at P_in and P_out.  Steady state: P linear between the faces (at -1/2 and nx - 1/2)
+    and u_x = (dP/L)/(2 mu) s (H - s), s the distance from the wall, uniform along the
+    channel, no cross flow."""
+    nu, rho, dP = 0.1, 1000.0, 0.6
+    if q == 9:
+        shape, bc, ax = (16, 9, 1), (O.WALL, O.WALL, O.PERIODIC), 1
+    else:
+        shape, bc, ax = (16, 2, 9), (O.WALL, O.PERIODIC, O.WALL), 2
+    nx = shape[0]
+    H = shape[ax]
+    prm = O.Params(q, shape, bc, rho_L=1.0, rho_H=rho, nu_L=0.1, nu_H=nu, M=0.1, W=4.0,
+                   sigma=1e-3, open_P=[dP / 2, -dP / 2, np.nan, np.nan, np.nan, np.nan])
+    phi = np.ones(shape[::-1])
+    h, g = O.init(prm, phi, np.zeros((3,) + phi.shape), np.zeros_like(phi))
+    h, g = O.run(prm, h, g, 3000)
+    r = O.read(prm, h, g)
+    u = r["J"][:3] / rho
+    x = np.arange(nx) + 0.5
+    P_exact = dP / 2 - dP * x / nx
+    assert np.abs(r["P"] - P_exact[None, None, :]).max() <= 1e-3 * dP
+    s = np.arange(H) + 0.5
+    prof = (dP / nx) / (2.0 * rho * nu) * s * (H - s)
+    ux = np.moveaxis(u[0], 2 - ax, 0)          # distance-from-wall axis first
+    ux = ux.reshape(H, -1)
+    assert np.abs(ux - prof[:, None]).max() <= 1e-2 * prof.max()
+    assert np.abs(u[1:]).max() <= 1e-4 * prof.max()
+    # phi is not conserved through an open face; the zero-gradient ghost of the h set
+    # lets the single-phase channel drift from phi = 1 by ~2e-5
+    assert np.abs(r["phi"] - 1.0).max() <= 1e-4
+
+
+def test_open_face_parameters_are_checked():
+    base = dict(rho_L=1.0, rho_H=10.0, nu_L=0.1, nu_H=0.1, M=0.1, W=4.0, sigma=1e-3)
+    P = [0.1, np.nan, np.nan, np.nan, np.nan, np.nan]
+    with pytest.raises(ValueError):          # open face on a periodic axis
+        O.Params(9, (8, 8, 1), (O.PERIODIC, O.WALL, O.PERIODIC), open_P=P, **base)
+    w = np.zeros((6, 3))
+    w[0, 1] = 0.01
+    with pytest.raises(ValueError):          # an open face does not move
+        O.Params(9, (8, 8, 1), (O.WALL, O.WALL, O.PERIODIC), open_P=P, wall_u=w, **base)
+    with pytest.raises(ValueError):
+        O.Params(9, (8, 8, 1), (O.WALL, O.WALL, O.PERIODIC),
+                 open_P=[np.inf] + P[1:], **base)
