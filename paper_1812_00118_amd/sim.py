@@ -55,6 +55,9 @@ class Sim:
                 raise ValueError("wall_u: 6 faces x 3 components")
             for k in range(18):
                 p.wall_u[k] = wu[k]
+        op = cfg.get("open_P")
+        if op is not None and not all(math.isnan(float(v)) for v in op):
+            raise ValueError("open (pressure) faces are not supported by the library")
         self.params = p
         self.Q = p.lattice
         self.D = 3 if p.lattice == 19 else 2
