@@ -642,7 +642,7 @@ struct Macro {
     float Fx, Fy, Fz, jx, jy, jz, ux, uy, uz, P;
 };
 
-// pn[k] = phi(x + c_k), g = pre-collision hydrodynamic populations at x
+// pn[k] = phi(x + c_k), gm = raw moments of the pre-collision hydrodynamic populations at x
 template <class L>
 __device__ __forceinline__ Macro macros(const Model& m, const float (&pn)[L::Q],
                                         const GMom& gm) {

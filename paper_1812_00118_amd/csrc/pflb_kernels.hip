@@ -33,8 +33,9 @@ __device__ __forceinline__ void lds_barrier() {
 // ---------------------------------------------------------------------------
 // Fused step.  A workgroup owns a TX x TY column tile (D2Q9: TX x 1) and marches
 // along z over BZ planes.  phi of plane z+1 on the tile plus a one-site ring is
-// gathered into a 4-plane rolling LDS buffer (the h and g values of the tile's own
-// sites are kept in registers for the collision of the next plane), then plane z is
+// gathered into a 4-plane rolling LDS buffer (the tile's own sites keep their h values
+// and the raw moments of their g values in registers for the collision of the next
+// plane), then plane z is
 // collided with grad(phi) and lap(phi) read from the LDS planes z-1, z, z+1.
 // One barrier per plane: plane z+2 is written into the slot plane z-2 used, which
 // no thread can still be reading once it has passed the barrier after plane z+1.
@@ -118,7 +119,8 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             split_hi_lo(pull_site_m<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA);
         if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0);
     }
-    // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc).
+    // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc)
+    // (h values and g moments).
     auto plane = [&](int z, const float (&hc)[Q], const GMom& gc, float lo_c,
                      float (&hn)[Q], GMom& gn, float& lo_n) {
         const ZRow rn = make_zrow(G, map_coord(z + 1, G.nz, G.wz));
