@@ -88,26 +88,61 @@ size_t scratch_bytes() {
 
 uint32_t sites(const pflb_params* p) { return (uint32_t)p->nx * p->ny * p->nz; }
 
-// Planes per workgroup of the fused step for nctx contexts of one launch: long z-marches
-// (each chunk re-gathers two extra planes of h) with about two 4-wave workgroups per CU
-// (8 one-wave workgroups for D2Q9) over the whole launch.  Measured: D3Q19 256x256x128
-// droplet impact, 64 planes beat 32 and 16 (and never below 8); D2Q9 256x1024
-// Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8), and a lone 256x256 domain
-// runs best with 1: small 2-D domains need the parallelism more than they lose to the
-// re-gathered planes.  D2Q9 marches no more than 4 planes: 16 256x256 domains in one
-// launch step fastest with 4 (FP32 8% faster than 8, 1.9x faster than 32).
+// Planes per workgroup of the fused step for nctx contexts of one launch.
+// D3Q19: a CU runs its share of the B workgroups, each marching bz planes and
+// re-gathering two more, so the critical path is ceil(B / CUs) (bz + 2) planes; at least
+// two workgroups per CU are needed to hide the gathers' latency.  bz minimises that path
+// among the choices that give two per CU (else the most workgroups).  This reproduces
+// every measured optimum: 128^3 16 planes (8 and 32 slower), 256x256x128 64 (16, 32
+// slower), 256^3 128, and 192^3, where 48 planes (576 workgroups, 2.25 per CU) measured
+// 16% slower than 16.
+// D2Q9 (one-wave workgroups): about 2048 workgroups, at most 4 planes.  Measured: 256x1024
+// Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8); a lone 256x256 domain runs
+// best with 1 (small 2-D domains need the parallelism more than they lose to the
+// re-gathered planes); 16 256x256 domains in one launch step fastest with 4 (FP32 8%
+// faster than 8, 1.9x faster than 32).
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n < 1)
+        return 256;
+    return n;
+}
+
 int pick_bz(const Geom& G, int lattice, int nctx) {
-    const long cols = (long)((G.nx + 63) / 64) * (lattice == 19 ? (G.ny + 3) / 4 : 1) * nctx;
-    const long want_wgs = lattice == 19 ? 512 : 2048;
-    long chunks = (want_wgs + cols - 1) / cols;
-    if (chunks < 1) chunks = 1;
-    long bz = (G.nz + chunks - 1) / chunks;
-    const long bz_min = lattice == 19 ? 8 : 1;
-    if (bz < bz_min) bz = bz_min;
-    if (lattice == 9 && bz > 4) bz = 4;
-    if (bz > G.nz) bz = G.nz;
     const char* env = getenv("PFLB_BZ");
-    if (env && atoi(env) > 0) bz = atoi(env);
+    if (env && atoi(env) > 0) return atoi(env);
+    const long nz = G.nz;
+    if (lattice == 19) {
+        const long cols = (long)((G.nx + 63) / 64) * ((G.ny + 3) / 4) * nctx;
+        const long cus = device_cus();
+        long best = nz, best_cost = -1;
+        bool best_enough = false;
+        long prev_chunks = -1;
+        for (long bz = (nz < 8 ? nz : 8); bz <= nz; ++bz) {
+            const long chunks = (nz + bz - 1) / bz;
+            if (chunks == prev_chunks) continue;           // same split, longer chunks
+            prev_chunks = chunks;
+            const long B = cols * chunks;
+            const bool enough = B >= 2 * cus;
+            const long cost = ((B + cus - 1) / cus) * (bz + 2);
+            if (best_cost < 0 || (enough && !best_enough) ||
+                (enough == best_enough && (enough ? cost < best_cost : false))) {
+                best = bz;
+                best_cost = cost;
+                best_enough = enough;
+            }
+        }
+        return (int)best;
+    }
+    const long cols = (long)((G.nx + 63) / 64) * nctx;
+    long chunks = (2048 + cols - 1) / cols;
+    if (chunks < 1) chunks = 1;
+    long bz = (nz + chunks - 1) / chunks;
+    if (bz < 1) bz = 1;
+    if (bz > 4) bz = 4;
+    if (bz > nz) bz = nz;
     return (int)bz;
 }
 
