@@ -3,12 +3,12 @@
 Workload: D3Q19 rising bubble, 128^3 sites, periodic in x and y, walls in z,
 rho_H/rho_L = 1000, mu_H/mu_L = 100, R = 16, W = 4, Eotvos number 10, hydrostatic
 start; distributions stored in FP32 (the value), with FP16-shifted storage timed beside
-it (speed-up and the phi difference between the two after the same steps).  The D3Q19
-droplet impact on a film (256x256x128, both storages) is timed as a second block, and
-the D2Q9 Rayleigh-Taylor case (256x1024) as a third, and the learned 16-step surrogate
-(D2Q9 256^2 droplets) as a fourth: trained here on solver
+it (speed-up and the phi difference between the two after the same steps).  Further
+blocks: the D3Q19 droplet impact on a film (256x256x128) and the same rising bubble on
+256^3, both storages; the D2Q9 Rayleigh-Taylor case (256x1024); the top wall moving;
+and the learned 16-step surrogate (D2Q9 256^2 droplets): trained here on solver
 trajectories, then its held-out error, its forward/training rate against the BF16 MFMA
-peak, and its speed-up over 16 plain steps with the guard.
+peak, and its speed against 16 plain steps (batched over the domains) with the guard.
 
 A step is one fused stream-and-collide pass over both distribution sets (every site,
 every population); the sum(phi)/non-finite guard runs once at the end of the timed
@@ -418,6 +418,22 @@ def main():
                 print(f"[bench] droplet_impact {st}: {r2['kernel_ms']:.4f} ms/step",
                       file=sys.stderr, flush=True)
             out["droplet_impact"] = blk
+            # the same rising bubble on 256^3 (16.8 M sites, 5.1 GB of FP32 state)
+            cfg5 = pfinputs.rising_bubble(n=256, R=32.0)
+            n5 = 256 ** 3
+            blk = {"workload": "rising_bubble D3Q19 256^3 (x,y periodic, z walls, R 32, "
+                               "otherwise as the 128^3 case)"}
+            for st in ("fp32", "fp16s"):
+                r5 = time_storage(cfg5, st, max(20, args.steps // 20), args.warmup)
+                blk[st] = {"mlups": round(n5 / (r5["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r5["kernel_ms"], 4),
+                           "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * n5 /
+                                                 (r5["kernel_ms"] * 1e-3) / 1e9, 1)}
+                print(f"[bench] rising_bubble 256^3 {st}: {r5['kernel_ms']:.4f} ms/step",
+                      file=sys.stderr, flush=True)
+            blk["speedup_fp16s_vs_fp32"] = round(blk["fp32"]["kernel_ms"] /
+                                                 blk["fp16s"]["kernel_ms"], 3)
+            out["rising_bubble_256"] = blk
             # D2Q9 Rayleigh-Taylor (256 x 1024, y walls): 38 MB of state per set, so the
             # step runs largely from the 256 MB Infinity Cache; reported as effective rates
             cfg3 = pfinputs.rayleigh_taylor()
