@@ -165,7 +165,12 @@ int pflb_reconstruct(pflb_ctx* ctx, const float* phi, const float* P, const floa
                      float* work, int advance, void* stream);
 
 /* Enqueue nsteps fused stream-and-collide steps of both sets (Eqs. 1 and 10 with
- * the central differences of Section 2).  Returns launch errors only. */
+ * the central differences of Section 2).  Returns launch errors only.
+ * The launch shape is chosen when the context is created (by pflb_step_many for each
+ * call); two environment variables read then override it for tuning (the results do
+ * not depend on them):
+ * PFLB_BZ (planes per workgroup along z) and PFLB_TILE (D3Q19 tile: 0 64x4, the
+ * default; 1 64x8; 2 32x8; 3 32x4). */
 int pflb_step(pflb_ctx* ctx, int nsteps, void* stream);
 
 /* The same steps for n contexts at once (an ensemble of small domains fills the GPU
