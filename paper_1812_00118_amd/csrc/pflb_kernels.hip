@@ -124,11 +124,16 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     auto plane = [&](int z, const float (&hc)[Q], const GMom& gc, float lo_c,
                      float (&hn)[Q], GMom& gn, float& lo_n) {
         const ZRow rn = make_zrow(G, map_coord(z + 1, G.nz, G.wz));
+        // gather phase at raised wave priority, so that the SIMD issues the loads of waves
+        // reaching it ahead of other waves' collision arithmetic (measured: 1-3% faster);
+        // back to normal after the barrier
+        __builtin_amdgcn_s_setprio(2);
         const double pn64 = (z + 1 < zend) ? pull_site_m<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
                                            : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
         sphi[(z + 1) & 3][ty + OY][tx + 1] = split_hi_lo(pn64, lo_n);
         if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
         lds_barrier();
+        __builtin_amdgcn_s_setprio(0);
         if (active) {
             const ZRow r = make_zrow(G, z);
             float pn[Q];
