@@ -310,3 +310,101 @@ def sample_sites(shape, count, seed, include_faces=True):
         xs, ys, zs = (0, nx // 2, nx - 1), (0, ny // 2, ny - 1), (0, nz // 2, nz - 1)
         pts.append(np.array([(x, y, z) for x in xs for y in ys for z in zs]))
     return np.unique(np.concatenate(pts), axis=0)
+
+
+# ---------------------------------------------------------------------------
+# hashed states for domains too large to build on the host
+# ---------------------------------------------------------------------------
+
+_M32 = 0xFFFFFFFF
+
+
+def _mix32(x):
+    """32-bit integer hash (xor-shift-multiply finaliser) of non-negative int64 values
+    below 2^32, on numpy or torch int64 arrays alike (products wrap modulo 2^64, whose
+    low 32 bits are the 32-bit product)."""
+    x = x ^ (x >> 16)
+    x = (x * 0x7FEB352D) & _M32
+    x = x ^ (x >> 15)
+    x = (x * 0x846CA68B) & _M32
+    return x ^ (x >> 16)
+
+
+class HashedState:
+    """Pre-collision populations defined site by site from an integer hash, so that a
+    domain of hundreds of millions of sites can be filled on the GPU while the host
+    evaluates only the sites it needs, with bitwise the same float32 values:
+
+        u_k(s)  = (mix32((s * 0x9E3779B1 + k * 0x85EBCA77 + seed * 0xC2B2AE3D) mod 2^32) >> 8) 2^-24
+        h_i(s)  = a_i (phi(s) + 0.02 (2 u_i(s) - 1)),          phi(s) = u_256(s)
+        g_i(s)  = a_i (0.05 (2 u_257(s) - 1) + 0.02 (2 u_{128+i}(s) - 1))
+
+    with s the linear site index (z ny + y) nx + x and a_i the lattice-weight
+    magnitudes; every float operation is a single float32 operation in this order."""
+
+    def __init__(self, q, shape, seed):
+        self.q = int(q)
+        self.shape = tuple(int(v) for v in shape)
+        self.seed = int(seed)
+        self.a = [np.float32(v) for v in _MAG[self.q]]
+
+    def _u(self, lin, k, xp):
+        key = (lin * 0x9E3779B1 + (k * 0x85EBCA77 + self.seed * 0xC2B2AE3D)) & _M32
+        m = _mix32(key) >> 8
+        if xp is np:
+            return m.astype(np.float32) * np.float32(2.0 ** -24)
+        return m.to(xp.float32) * (2.0 ** -24)
+
+    def _pop(self, lin, i, xp, c):
+        """(h_i, g_i) at the linear indices lin; c holds the float32 constants."""
+        one, two, hn, gs = c["1"], c["2"], c["0.02"], c["0.05"]
+        phi = self._u(lin, 256, xp)
+        s = self._u(lin, 257, xp) * two - one
+        h = (phi + (self._u(lin, i, xp) * two - one) * hn) * c["a"][i]
+        g = (s * gs + (self._u(lin, 128 + i, xp) * two - one) * hn) * c["a"][i]
+        return h, g
+
+    def host(self, lin):
+        """(h, g) float32 numpy arrays (Q, len(lin)) at the given linear indices."""
+        lin = np.asarray(lin, dtype=np.int64).reshape(-1)
+        c = {"1": np.float32(1.0), "2": np.float32(2.0), "0.02": np.float32(0.02),
+             "0.05": np.float32(0.05), "a": self.a}
+        h = np.empty((self.q, lin.size), dtype=np.float32)
+        g = np.empty_like(h)
+        for i in range(self.q):
+            h[i], g[i] = self._pop(lin, i, np, c)
+        return h, g
+
+    def device(self, device):
+        """(h, g) float32 torch tensors (Q, nz, ny, nx) built on `device`."""
+        import torch
+        nx, ny, nz = self.shape
+        n = nx * ny * nz
+        f = lambda v: torch.tensor(np.float32(v), device=device)  # noqa: E731
+        c = {"1": f(1.0), "2": f(2.0), "0.02": f(0.02), "0.05": f(0.05),
+             "a": [f(v) for v in self.a]}
+        h = torch.empty((self.q, n), dtype=torch.float32, device=device)
+        g = torch.empty_like(h)
+        lin = torch.arange(n, dtype=torch.int64, device=device)
+        for i in range(self.q):
+            h[i], g[i] = self._pop(lin, i, torch, c)
+        return h.view(self.q, nz, ny, nx), g.view(self.q, nz, ny, nx)
+
+    def lazy(self):
+        """Host stand-ins for the full (Q, N) arrays: objects whose `[:, idx]` returns
+        the values at those linear indices (what a site-by-site evaluation reads)."""
+        st = self
+
+        class _Set:
+            def __init__(self, which):
+                self.which = which
+
+            def reshape(self, *shape):
+                return self
+
+            def __getitem__(self, key):
+                rows, idx = key
+                assert rows == slice(None)
+                return st.host(idx)[self.which]
+
+        return _Set(0), _Set(1)

@@ -448,6 +448,52 @@ def test_full_size_one_step_sampled(make):
     _close(gg, gr)
 
 
+# the largest domain the library accepts is 2^28 - 64 sites (byte offsets within one
+# direction's array stay below 2^31); this one is 2.68e8 sites, ragged in x (1000 = 15 * 64
+# + 40), so the last sites' slots sit within 4 MB of that limit
+MAX_SHAPE = (1000, 1000, 268)
+
+
+@pytest.mark.parametrize("storage,bc", [("fp32", (P_, P_, W_)), ("fp16s", (W_, W_, W_))],
+                         ids=["fp32-walls-z", "fp16s-walls-all"])
+def test_maximum_domain_one_step_sampled(storage, bc):
+    """At the largest domain the library accepts: one step from a hashed state filled on
+    the GPU, checked at sampled sites (random, box corners and face centres, so also the
+    last slots of every direction's array) against the oracle's site-by-site evaluation
+    of the same hashed values; sum(phi) is conserved and finite."""
+    need = (130 if storage == "fp32" else 90) * 2 ** 30
+    if torch.cuda.mem_get_info()[0] < need:
+        pytest.skip("needs about %d GiB of free device memory" % (need >> 30))
+    assert MAX_SHAPE[0] * MAX_SHAPE[1] * MAX_SHAPE[2] <= 2 ** 28 - 64
+    cfg = _cfg(19, MAX_SHAPE, bc, g=(2e-5, -1e-5, 3e-5))
+    st = pfinputs.HashedState(19, MAX_SHAPE, seed=29)
+    sim = _sim(cfg, storage=storage)
+    h0, g0 = st.device(sim.device)
+    sim.set_state(h0, g0)
+    del h0, g0
+    torch.cuda.empty_cache()
+    m0, bad0 = sim.mass()
+    sim.step(1)
+    m1, bad1 = sim.mass()
+    assert not bad0 and not bad1
+    assert abs(m1 - m0) <= (1e-7 if storage == "fp32" else 1e-10) * abs(m0), (m0, m1)
+    h1, g1 = sim.get_state()
+    sites = pfinputs.sample_sites(MAX_SHAPE, 300, seed=3)
+    x, y, z = (torch.as_tensor(v, device=h1.device) for v in sites.T)
+    hg = _np(h1[:, z, y, x])
+    gg = _np(g1[:, z, y, x])
+    del h1, g1, sim
+    torch.cuda.empty_cache()
+    hl, gl = st.lazy()
+    hr, gr = O.step_sites(_oracle_params(cfg), hl, gl, sites)
+    if storage == "fp32":
+        _close(hg, hr)
+        _close(gg, gr)
+    else:   # the fp16 rounding of the deviations, as in the small one-step cases below
+        assert np.abs(hg - hr).max() <= 2e-3 * np.abs(hr).max()
+        assert np.abs(gg - gr).max() <= 2e-3 * np.abs(gr).max()
+
+
 # ----------------------------------------------------------------------------- FP16S
 FP16S_CASES = [("d2q9-walls", 9, (70, 33, 1), (W_, W_, P_)),
                ("d3q19-walls-z", 19, (37, 21, 19), (P_, P_, W_))]
