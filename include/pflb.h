@@ -97,6 +97,14 @@ extern "C" {
  *                a wall face returns reduced by 2 w_i (c_i . u_w)/T times the sending
  *                site's phi (h) or rho (g); one crossing two or three faces at an edge or
  *                corner takes the mean of their velocities.
+ *   wet_cos      cos of the contact angle of each wall face (measured through the
+ *                heavy phase), rows as wall_u; each in [-1, 1], 0 on faces of periodic
+ *                axes (D2Q9: entries 4, 5 must be 0).  All zeros (90 degrees) is the
+ *                mirror ghost above.  Not in the paper, which has no contact angles: the
+ *                geometric wetting condition n_w . grad(phi) = -(4/W) cos(theta) phi (1 -
+ *                phi) across the half-way wall, i.e. the ghost beyond the face takes
+ *                phi_m + (4/W) cos(theta) phi_m (1 - phi_m), phi_m the adjacent site's
+ *                phi; a ghost beyond two or three faces adds their terms.
  */
 typedef struct pflb_params {
     int lattice;
@@ -112,6 +120,7 @@ typedef struct pflb_params {
     int storage;
     int scale_log2[2];
     double wall_u[6][3];
+    double wet_cos[6];
 } pflb_params;
 
 typedef struct pflb_ctx pflb_ctx;

@@ -42,6 +42,15 @@ Readings of points the paper leaves open (each is also listed in the design note
   plus 2 w_i (P_f - P(s'))/T for g.  A population that crosses a closed wall face as
   well is bounced back (with the mean velocity of the closed faces it crosses); one that
   crosses several open faces takes the mean of their P_f.
+* Wetting (not in the paper, which has no contact angles; the usual geometric condition
+  of diffuse-interface models): a wall face f may prescribe a contact angle theta_f,
+  measured through the heavy phase, by n_w . grad(phi) = -(4/W) cos(theta_f) phi (1 - phi)
+  with n_w the unit normal into the fluid; 4 phi (1 - phi)/W is |grad(phi)| of the
+  equilibrium profile.  Taken across the half-way wall between the boundary site and
+  its ghost one site out, the ghost value becomes phi_m + k phi_m (1 - phi_m) with phi_m
+  the adjacent fluid site's value (the mirror above) and k the sum of
+  (4/W) cos(theta_f) over the wall faces the ghost lies beyond (edges and corners add
+  the faces they cross).  cos(theta_f) = 0 (90 degrees) is the zero-gradient rule.
 * No clipping of phi anywhere; n = grad(phi)/(|grad(phi)| + eps) exactly as printed.
 """
 import numpy as np
@@ -63,7 +72,7 @@ class Params:
 
     def __init__(self, lattice, shape, bc, rho_L, rho_H, nu_L, nu_H, M, W, sigma,
                  g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0, wall_u=None,
-                 open_P=None):
+                 open_P=None, wet_cos=None):
         self.lat = _lattice(lattice)
         nx, ny, nz = shape
         if self.lat.D == 2 and nz != 1:
@@ -104,6 +113,22 @@ class Params:
             if not np.isfinite(self.open_P[f]):
                 raise ValueError("open-face pressure must be finite")
 
+        # wetting: cos(contact angle) per wall face (0: 90 degrees, the mirror ghost)
+        self.wet_cos = (np.zeros(6) if wet_cos is None
+                        else np.asarray(wet_cos, dtype=np.float64).reshape(6).copy())
+        for f, (a, _) in enumerate(FACES):
+            if not np.isfinite(self.wet_cos[f]) or abs(self.wet_cos[f]) > 1.0:
+                raise ValueError("wet_cos must be finite and in [-1, 1]")
+            if self.wet_cos[f] != 0.0 and self.bc[a] != WALL:
+                raise ValueError("a contact angle given for a face of a periodic axis")
+            if self.wet_cos[f] != 0.0 and not np.isnan(self.open_P[f]):
+                raise ValueError("a contact angle given for an open face")
+
+    @property
+    def wet_k(self):
+        """(4/W) cos(theta_f) per face: the ghost's phi_m (1 - phi_m) coefficient."""
+        return 4.0 * self.wet_cos / self.W
+
     @property
     def open_faces(self):
         return [f for f in range(6) if not np.isnan(self.open_P[f])]
@@ -130,7 +155,7 @@ class Params:
     @classmethod
     def from_dict(cls, d):
         keys = ("lattice", "shape", "bc", "rho_L", "rho_H", "nu_L", "nu_H", "M", "W",
-                "sigma", "g", "eps", "hoc", "dtheta_C", "wall_u", "open_P")
+                "sigma", "g", "eps", "hoc", "dtheta_C", "wall_u", "open_P", "wet_cos")
         return cls(**{k: d[k] for k in keys if k in d})
 
 
@@ -150,17 +175,33 @@ def _ghost_pad(field, bc):
     return out
 
 
-def neighbour(field, c, bc):
-    """field(x + c) for every site x, with the ghost rule at walls."""
-    p = _ghost_pad(field, bc)
+def _wet_pad(p, wet_k):
+    """Apply the wetting ghost rule to a ghost-padded phi field: each ghost beyond wall
+    faces f gets phi_m + (sum_f k_f) phi_m (1 - phi_m), phi_m its mirrored value."""
+    if wet_k is None or not np.any(wet_k != 0.0):
+        return p
+    k = np.zeros_like(p)
+    # face f = (axis, side); numpy axis of bc axis a is 2 - a
+    for f, (a, side) in enumerate(FACES):
+        if wet_k[f] != 0.0:
+            sl = [slice(None)] * 3
+            sl[2 - a] = 0 if side < 0 else -1
+            k[tuple(sl)] += wet_k[f]
+    return p + k * p * (1.0 - p)
+
+
+def neighbour(field, c, bc, wet_k=None):
+    """field(x + c) for every site x, with the ghost rules at walls."""
+    p = _wet_pad(_ghost_pad(field, bc), wet_k)
     nz, ny, nx = field.shape
     cx, cy, cz = (int(v) for v in c)
     return p[1 + cz:1 + cz + nz, 1 + cy:1 + cy + ny, 1 + cx:1 + cx + nx]
 
 
-def phi_stencil(phi, lat, bc):
-    """phi at x + c_k for k = 0..Q-1 (index 0 is phi itself)."""
-    return np.stack([neighbour(phi, lat.c[k], bc) for k in range(lat.Q)])
+def phi_stencil(phi, lat, bc, wet_k=None):
+    """phi at x + c_k for k = 0..Q-1 (index 0 is phi itself); wet_k: the wetting
+    coefficients per wall face (None: the mirror ghost)."""
+    return np.stack([neighbour(phi, lat.c[k], bc, wet_k) for k in range(lat.Q)])
 
 
 # ---------------------------------------------------------------------------
@@ -445,7 +486,7 @@ def step(prm, h, g):
     """One time step of both sets: (h, g) at step n -> (h, g) at step n + 1."""
     lat = prm.lat
     phi = h.sum(0)
-    phi_nb = phi_stencil(phi, lat, prm.bc)
+    phi_nb = phi_stencil(phi, lat, prm.bc, prm.wet_k)
     hstar, gstar, m = collide(lat, prm, h, g, phi_nb)
     return stream(lat, prm, hstar, m, "h"), stream(lat, prm, gstar, m, "g")
 
@@ -460,7 +501,7 @@ def read(prm, h, g):
     """phi, P, J (= rho u as printed) and u of the state at step n."""
     lat = prm.lat
     phi = h.sum(0)
-    m = macros(lat, prm, h, g, phi_stencil(phi, lat, prm.bc))
+    m = macros(lat, prm, h, g, phi_stencil(phi, lat, prm.bc, prm.wet_k))
     return dict(phi=m["phi"], P=m["P"], J=m["J"], u=m["u"])
 
 
@@ -477,7 +518,7 @@ def init(prm, phi0, u0, P0=None):
     phi0 = np.asarray(phi0, dtype=np.float64)
     u0 = np.asarray(u0, dtype=np.float64)
     P0 = np.zeros_like(phi0) if P0 is None else np.asarray(P0, dtype=np.float64)
-    phi_nb = phi_stencil(phi0, lat, prm.bc)
+    phi_nb = phi_stencil(phi0, lat, prm.bc, prm.wet_k)
     grad = grad_cd(lat, phi_nb)
     lap = lap_cd(lat, phi_nb)
     rho = prm.rho_L + phi0 * prm.rho_dif
@@ -537,11 +578,20 @@ def step_sites(prm, h, g, sites):
     hu = hf[:, idx].astype(np.float64)
     gu = gf[:, idx].astype(np.float64)
     phi_nb = np.empty((lat.Q, len(ups)))
+    wk = prm.wet_k
     for k in range(lat.Q):
-        x = _map_axis(ups[:, 0] + lat.c[k, 0], nx, prm.bc[0])
-        y = _map_axis(ups[:, 1] + lat.c[k, 1], ny, prm.bc[1])
-        z = _map_axis(ups[:, 2] + lat.c[k, 2], nz, prm.bc[2])
-        phi_nb[k] = hf[:, lin(x, y, z)].astype(np.float64).sum(0)
+        raw = ups + lat.c[k][None, :]
+        x = _map_axis(raw[:, 0], nx, prm.bc[0])
+        y = _map_axis(raw[:, 1], ny, prm.bc[1])
+        z = _map_axis(raw[:, 2], nz, prm.bc[2])
+        pm = hf[:, lin(x, y, z)].astype(np.float64).sum(0)
+        # wetting ghost rule for the neighbours beyond wall faces
+        kk = np.zeros(len(ups))
+        for f, (a, side) in enumerate(FACES):
+            if wk[f] != 0.0:
+                n_a = prm.shape[a]
+                kk += np.where(raw[:, a] < 0 if side < 0 else raw[:, a] >= n_a, wk[f], 0.0)
+        phi_nb[k] = pm + kk * pm * (1.0 - pm) if np.any(wk != 0.0) else pm
     hstar, gstar, m = collide(lat, prm, hu, gu, phi_nb)
     hstar = hstar.reshape(lat.Q, S, lat.Q)
     gstar = gstar.reshape(lat.Q, S, lat.Q)

@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("dtheta_C", ctypes.c_double),
                 ("storage", ctypes.c_int),
                 ("scale_log2", ctypes.c_int * 2),
-                ("wall_u", ctypes.c_double * 18)]
+                ("wall_u", ctypes.c_double * 18),
+                ("wet_cos", ctypes.c_double * 6)]
 
 
 class SurCfg(ctypes.Structure):

@@ -72,6 +72,14 @@ std::string check_params(const pflb_params* p) {
             if (p->bc[axis] != PFLB_BC_WALL) return "wall velocity given for a face of a periodic axis";
             if (a == axis) return "a wall moves tangentially: its normal velocity must be 0";
         }
+    for (int f = 0; f < 6; ++f) {
+        const double v = p->wet_cos[f];
+        if (!finite(v) || v < -1.0 || v > 1.0) return "wet_cos must be finite and in [-1, 1]";
+        if (v == 0.0) continue;
+        const int axis = f / 2;
+        if (axis >= naxes) return "contact angle on an axis the lattice does not have";
+        if (p->bc[axis] != PFLB_BC_WALL) return "contact angle given for a face of a periodic axis";
+    }
     return "";
 }
 
@@ -182,11 +190,16 @@ void derive(pflb_ctx* c) {
     m.beta = p.hoc ? 1.0f : 0.0f;
     // wall faces and velocity components in internal axes (D2Q9: user y is internal z)
     m.moving = 0;
-    for (int f = 0; f < 6; ++f)
+    m.wetting = 0;
+    for (int f = 0; f < 6; ++f) {
         for (int a = 0; a < 3; ++a) m.uw[f][a] = 0.0f;
+        m.wk[f] = 0.0f;
+    }
     for (int f = 0; f < 6; ++f) {
         const int fi = p.lattice == 19 ? f : (f < 2 ? f : (f < 4 ? f + 2 : -1));
         if (fi < 0) continue;
+        m.wk[fi] = (float)(4.0 * p.wet_cos[f] / p.W);
+        if (p.wet_cos[f] != 0.0) m.wetting = 1;
         for (int a = 0; a < 3; ++a) {
             const int ai = p.lattice == 19 ? a : (a == 0 ? 0 : (a == 1 ? 2 : -1));
             if (ai < 0) continue;
@@ -587,12 +600,13 @@ extern "C" int pflb_step_many(pflb_ctx* const* c, int n, int nsteps, void* strea
     std::sort(sorted.begin(), sorted.end());
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
         return fail(c[0], PFLB_ERR_PARAM, "a context appears twice in a batch");
-    // Contexts with moving walls take their own launches: the batched kernel has no
-    // moving-wall variant, and each context must run the arithmetic its own pflb_step
-    // runs (separately compiled kernel variants may contract and round differently).
+    // Contexts with moving walls or contact angles take their own launches: the batched
+    // kernel has no variant for them, and each context must run the arithmetic its own
+    // pflb_step runs (separately compiled kernel variants may contract and round
+    // differently).
     std::vector<pflb_ctx*> gr;
     for (int k = 0; k < n; ++k) {
-        if (!c[k]->L.m.moving) {
+        if (!c[k]->L.m.moving && !c[k]->L.m.wetting) {
             gr.push_back(c[k]);
         } else if ((r = pflb_step(c[k], nsteps, stream))) {
             if (c[k] != c[0]) fail(c[0], r, pflb_last_error(c[k]));

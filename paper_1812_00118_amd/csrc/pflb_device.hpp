@@ -119,6 +119,8 @@ struct Model {
     float beta;               // 1: Eq. 13 correction and modified velocity
     float uw[6][3];           // wall face velocities, faces x-, x+, y-, y+, z-, z+ (internal)
     int moving;               // 1 if any wall moves
+    float wk[6];              // wetting: (4/W) cos(contact angle) per face (internal)
+    int wetting;              // 1 if any face has a contact angle other than 90 degrees
 };
 
 struct Codec {                // FP16S: power-of-two scales of the fp16 deviations
@@ -347,6 +349,23 @@ __host__ __device__ __forceinline__ int map_coord(int v, int n, int wall) {
     if (wall) return v < 0 ? 0 : (v >= n ? n - 1 : v);
     v %= n;
     return v < 0 ? v + n : v;
+}
+
+// Wetting ghost rule: the phi of position (vx, vy, vz) beyond wall faces is
+// pm + k pm (1 - pm), pm the value of the site map_coord gives and k the sum, over the
+// faces the position lies beyond, of (4/W) cos(contact angle).  Inside the domain, and
+// beyond faces of periodic axes (whose coefficients are 0), k = 0 and pm is returned
+// unchanged.
+__device__ __forceinline__ float wet_ghost(const Geom& G, const Model& m, int vx, int vy,
+                                           int vz, float pm) {
+    float k = 0.0f;
+    if (vx < 0) k += m.wk[0];
+    else if (vx >= G.nx) k += m.wk[1];
+    if (vy < 0) k += m.wk[2];
+    else if (vy >= G.ny) k += m.wk[3];
+    if (vz < 0) k += m.wk[4];
+    else if (vz >= G.nz) k += m.wk[5];
+    return fmaf(k, pm * (1.0f - pm), pm);
 }
 
 // Upstream offsets of an (x, y) column: source x - 1 (for c_x = +1) and x + 1 (c_x = -1)

@@ -21,7 +21,8 @@ struct Launch {
 };
 
 hipError_t launch_step(const Launch& a, const void* src, void* dst);
-// one step of n <= BATCH_MAX contexts without moving walls (blockIdx.y = context)
+// one step of n <= BATCH_MAX contexts without moving walls or contact angles
+// (blockIdx.y = context)
 hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n);
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
                               const float* P, float* h, float* g);

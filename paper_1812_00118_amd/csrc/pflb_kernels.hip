@@ -40,8 +40,9 @@ __device__ __forceinline__ void lds_barrier() {
 // One barrier per plane: plane z+2 is written into the slot plane z-2 used, which
 // no thread can still be reading once it has passed the barrier after plane z+1.
 // ---------------------------------------------------------------------------
-// MOVING: the variant for moving walls (momentum-corrected bounce-back, WallWriter),
-// kept apart so that the other variants carry none of its registers.
+// XBC: the variant for the extra wall conditions, moving walls (momentum-corrected
+// bounce-back, WallWriter) and contact angles (the wetting ghost rule), kept apart so
+// that the other variants carry none of their registers.
 //
 // BATCHED: a batch of resting-wall contexts that share lattice, storage and geometry;
 // blockIdx.y picks the context, whose buffers and parameters replace src, dst, m and cd.
@@ -54,11 +55,11 @@ struct StepTable<true> {
     StepBatch bt;
 };
 
-template <class L, class ST, int TX, int TY, int WALLS, bool MOVING, bool BATCHED>
+template <class L, class ST, int TX, int TY, int WALLS, bool XBC, bool BATCHED>
 __global__ void __launch_bounds__(TX * TY)
 k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
        const char* __restrict__ src, char* __restrict__ dst, StepTable<BATCHED> tab) {
-    static_assert(!(BATCHED && MOVING), "moving-wall contexts are stepped one by one");
+    static_assert(!(BATCHED && XBC), "contexts with moving walls or contact angles are stepped one by one");
     if constexpr (BATCHED) {
         const StepEnt& e = tab.bt.e[blockIdx.y];
         m = e.m;
@@ -102,9 +103,19 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     const Col ring = make_col(G, map_coord(x0 - 1 + rhx, G.nx, G.wx),
                               L::USES_Y ? map_coord(y0 - 1 + rhy, G.ny, G.wy) : 0);
 
-    auto ring_phi = [&](const ZRow& r) {
+    // contact angles (XBC variant): ghost positions beyond wall faces (the own lanes
+    // past a ragged edge, the ring past the domain, the planes below and above it) take
+    // the wetting rule
+    const int rrx = x0 - 1 + rhx, rry = L::USES_Y ? y0 - 1 + rhy : 0;
+    auto wet = [&](float v, int vx, int vy, int vz) {
+        if constexpr (WALLS != WALLS_NONE && XBC) {
+            if (m.wetting) return wet_ghost(G, m, vx, vy, vz, v);
+        }
+        return v;
+    };
+    auto ring_phi = [&](const ZRow& r, int zr) {
         float f[Q];
-        return (float)pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f);
+        return wet((float)pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f), rrx, rry, zr);
     };
 
     float hA[Q], loA, hB[Q], loB;
@@ -112,12 +123,13 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     {   // plane z0 - 1 (phi only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
         float f[Q];
-        sphi[(z0 - 1) & 3][ty + OY][tx + 1] = (float)pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f);
-        if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm);
+        sphi[(z0 - 1) & 3][ty + OY][tx + 1] =
+            wet((float)pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f), x, y, z0 - 1);
+        if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm, z0 - 1);
         const ZRow r0 = make_zrow(G, z0);
         sphi[z0 & 3][ty + OY][tx + 1] =
-            split_hi_lo(pull_site_m<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA);
-        if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0);
+            wet(split_hi_lo(pull_site_m<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA), x, y, z0);
+        if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0, z0);
     }
     // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc)
     // (h values and g moments).
@@ -130,8 +142,8 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         __builtin_amdgcn_s_setprio(2);
         const double pn64 = (z + 1 < zend) ? pull_site_m<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
                                            : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
-        sphi[(z + 1) & 3][ty + OY][tx + 1] = split_hi_lo(pn64, lo_n);
-        if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn);
+        sphi[(z + 1) & 3][ty + OY][tx + 1] = wet(split_hi_lo(pn64, lo_n), x, y, z + 1);
+        if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn, z + 1);
         lds_barrier();
         __builtin_amdgcn_s_setprio(0);
         if (active) {
@@ -143,7 +155,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             });
             const Macro a = macros<L>(m, pn, gc);
             SiteWriter<L, ST> out(dst, own.base + r.base, G.S, cd, a.phi, lo_c);
-            if constexpr (WALLS == WALLS_NONE || !MOVING) {
+            if constexpr (WALLS == WALLS_NONE || !XBC) {
                 collide_stream<L>(m, a, lo_c, hc, gc, out);
             } else {
                 const uint32_t solid = own.solid | r.solid;
@@ -176,16 +188,19 @@ __device__ __forceinline__ uint32_t site_of(const Geom& G, int x, int y, int z) 
     return (uint32_t)z * G.sxy + (uint32_t)y * (uint32_t)G.nx + (uint32_t)x;
 }
 
-// phi(x + c_k) for all k from a phi field, with the ghost rule
+// phi(x + c_k) for all k from a phi field, with the ghost rules (mirror, wetting)
 template <class L>
-__device__ __forceinline__ void phi_stencil(const Geom& G, const float* __restrict__ phi,
+__device__ __forceinline__ void phi_stencil(const Geom& G, const Model& m,
+                                            const float* __restrict__ phi,
                                             int x, int y, int z, float (&pn)[L::Q]) {
     static_for<0, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        const int xx = map_coord(x + L::cx(i), G.nx, G.wx);
-        const int yy = map_coord(y + L::cy(i), G.ny, G.wy);
-        const int zz = map_coord(z + L::cz(i), G.nz, G.wz);
+        const int vx = x + L::cx(i), vy = y + L::cy(i), vz = z + L::cz(i);
+        const int xx = map_coord(vx, G.nx, G.wx);
+        const int yy = map_coord(vy, G.ny, G.wy);
+        const int zz = map_coord(vz, G.nz, G.wz);
         pn[i] = phi[site_of(G, xx, yy, zz)];
+        if (m.wetting) pn[i] = wet_ghost(G, m, vx, vy, vz, pn[i]);
     });
 }
 
@@ -227,7 +242,7 @@ __device__ __forceinline__ void equilibrium_site(const Geom& G, const Model& m, 
     int x, y, z;
     site_coords(G, s, x, y, z);
     float pn[L::Q];
-    phi_stencil<L>(G, phi, x, y, z, pn);
+    phi_stencil<L>(G, m, phi, x, y, z, pn);
     // macros with the given u and P: feed a zero g and overwrite J/u/P
     float zero[L::Q];
     static_for<0, L::Q>([&](auto I) { zero[decltype(I)::value] = 0.0f; });
@@ -359,7 +374,7 @@ __device__ __forceinline__ void macro_site(const Geom& G, const Model& m, const 
     int x, y, z;
     site_coords(G, s, x, y, z);
     float pn[L::Q], hv[L::Q], gv[L::Q];
-    phi_stencil<L>(G, phi, x, y, z, pn);
+    phi_stencil<L>(G, m, phi, x, y, z, pn);
     pull_site<L, ST, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, hv, gv);
     const Macro a = macros<L>(m, pn, g_moments<L>(gv));
     if (P) P[s] = a.P;
@@ -500,15 +515,16 @@ struct StepArgs {
     int n;
 };
 
-template <class L, class ST, int WALLS, int TX, int TY, bool MOVING = false>
+template <class L, class ST, int WALLS, int TX, int TY, bool XBC = false>
 static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
     const int ntx = (a.G.nx + TX - 1) / TX;
     const int nty = (a.G.ny + TY - 1) / TY;
     const int ntz = (a.G.nz + a.bz - 1) / a.bz;
     const int nblk = ntx * nty * ntz;
     if (x.bt) {
-        // batches hold resting-wall contexts only (moving ones are stepped one by one)
-        if constexpr (MOVING) {
+        // batches hold contexts without moving walls or contact angles only (the
+        // others are stepped one by one)
+        if constexpr (XBC) {
             return hipErrorInvalidValue;
         } else {
             StepTable<true> tab;
@@ -518,7 +534,7 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
                                nblk, (const char*)nullptr, (char*)nullptr, tab);
         }
     } else {
-        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, MOVING, false>), dim3(nblk),
+        hipLaunchKernelGGL((k_step<L, ST, TX, TY, WALLS, XBC, false>), dim3(nblk),
                            dim3(TX * TY), 0, a.stream, a.G, a.m, a.cd, a.bz, ntx, nty, nblk,
                            x.s, x.d, StepTable<false>{});
     }
@@ -528,8 +544,8 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
 template <class L, class ST, int WALLS>
 static hipError_t launch_step_t(const Launch& a, const StepArgs& x) {
     if constexpr (WALLS != WALLS_NONE) {
-        // moving walls: one tile shape per lattice
-        if (a.m.moving) {
+        // moving walls or contact angles: one tile shape per lattice
+        if (a.m.moving || a.m.wetting) {
             if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, x);
             else return launch_tile<L, ST, WALLS, 64, 1, true>(a, x);
         }

@@ -24,7 +24,9 @@ def _ptr(t):
 
 class Sim:
     """cfg: dict with lattice (9/19), shape (nx, ny, nz), bc (per axis 'periodic'/'wall'),
-    rho_L, rho_H, nu_L, nu_H, M, W, sigma, g (3), eps, hoc, dtheta_C.
+    rho_L, rho_H, nu_L, nu_H, M, W, sigma, g (3), eps, hoc, dtheta_C; optionally wall_u
+    (6 faces x 3) and wet_cos (cos of the contact angle per face), faces x-, x+, y-, y+,
+    z-, z+.
     Fields use shape (nz, ny, nx) (nz = 1 for D2Q9), vectors (D, nz, ny, nx),
     distributions (Q, nz, ny, nx)."""
 
@@ -55,6 +57,13 @@ class Sim:
                 raise ValueError("wall_u: 6 faces x 3 components")
             for k in range(18):
                 p.wall_u[k] = wu[k]
+        wc = cfg.get("wet_cos")
+        if wc is not None:
+            wc = [float(v) for v in np.asarray(wc).reshape(-1)]
+            if len(wc) != 6:
+                raise ValueError("wet_cos: one value per face")
+            for k in range(6):
+                p.wet_cos[k] = wc[k]
         op = cfg.get("open_P")
         if op is not None and not all(math.isnan(float(v)) for v in op):
             raise ValueError("open (pressure) faces are not supported by the library")

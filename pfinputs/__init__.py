@@ -24,6 +24,9 @@ Workloads (lattice units, rho_L = 1):
                    uniform on the torus at least W apart (edge to edge), each drop moving
                    with a random velocity |u| <= 0.02; nu_H = nu_L = 0.01, M = 0.1, W = 4,
                    sigma = 1e-2.  Seeds: train 0-255, validation 1000-1031, test 2000-2031.
+  sessile_drop     D2Q9 96x40, x periodic, y walls, a half disc R = 12 on the bottom
+                   wall, which prescribes a contact angle (rho_H = 10, nu = 0.1, M = 0.1,
+                   W = 4, sigma = 0.05): the wetting check (not a case of the paper).
   dense_bubble     D2Q9 80x40 periodic water (phi = 1) holding a dense bubble (a shallow
                    Gaussian dip, phi 0.93 at its centre, standard deviation 3 sites) and
                    a decent bubble (phi = 0 inside, R = 10) 40 sites apart; rho_H = 1000,
@@ -59,6 +62,16 @@ def dense_bubble(nx=80, ny=40, C=10.0, depth=0.07, spread=3.0, R=10.0):
                 nu_H=0.1, M=0.17, W=3.0, sigma=1e-3, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1,
                 dtheta_C=C, depth=depth, spread=spread, R=R,
                 dense_at=(nx / 4.0, (ny - 1) / 2.0), decent_at=(3.0 * nx / 4.0, (ny - 1) / 2.0))
+
+
+def sessile_drop(theta_deg, nx=96, ny=40, R=12.0):
+    """D2Q9 cap on the bottom wall (x periodic, y walls) whose bottom wall prescribes the
+    contact angle theta_deg; it starts as a half disc (90 degrees)."""
+    c = math.cos(math.radians(theta_deg))
+    return dict(name="sessile_drop", lattice=9, shape=(nx, ny, 1),
+                bc=(PERIODIC, WALL, PERIODIC), rho_L=1.0, rho_H=10.0, nu_L=0.1, nu_H=0.1,
+                M=0.1, W=4.0, sigma=0.05, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0,
+                wet_cos=(0.0, 0.0, c, 0.0, 0.0, 0.0), theta_deg=theta_deg, R=R)
 
 
 def rayleigh_taylor(nx=256, ny=1024):
@@ -135,6 +148,8 @@ def model_params(cfg):
         d["wall_u"] = np.asarray(cfg["wall_u"], dtype=np.float64).reshape(6, 3)
     if cfg.get("open_P") is not None:       # open-face pressures, same order (NaN: closed)
         d["open_P"] = np.asarray(cfg["open_P"], dtype=np.float64).reshape(6)
+    if cfg.get("wet_cos") is not None:      # cos(contact angle) per wall face, same order
+        d["wet_cos"] = np.asarray(cfg["wet_cos"], dtype=np.float64).reshape(6)
     return d
 
 
@@ -246,7 +261,18 @@ def fields_dense_bubble(cfg):
     return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
 
 
+def fields_sessile_drop(cfg):
+    """Half disc of radius R centred on the wall line y = -1/2 (phi = 1 inside)."""
+    z, y, x = _grid(cfg["shape"])
+    nx = cfg["shape"][0]
+    r = np.sqrt((x - (nx - 1) / 2.0) ** 2 + (y + 0.5) ** 2)
+    phi = 0.5 - 0.5 * np.tanh(2.0 * (r - cfg["R"]) / cfg["W"])
+    u = np.zeros((3,) + phi.shape)
+    return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
+
+
 FIELDS = {"static_droplet": fields_static_droplet,
+          "sessile_drop": fields_sessile_drop,
           "dense_bubble": fields_dense_bubble,
           "drops": fields_drops,
           "rayleigh_taylor": fields_rayleigh_taylor,

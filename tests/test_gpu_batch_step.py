@@ -101,6 +101,24 @@ def test_step_many_d3q19_walls_one_moving(storage):
     _assert_same(batch, alone)
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_step_many_with_a_wetting_context(storage):
+    """A context whose walls prescribe contact angles is stepped on its own (by the
+    kernel variant that applies the wetting rule), the others batched: all end as their
+    own steps leave them."""
+    from paper_1812_00118_amd import Sim
+
+    def wet(k):
+        return dict(wet_cos=(0, 0, 0.5, -0.3, 0, 0)) if k == 2 else {}
+
+    batch, alone = _pairs(9, (67, 45, 1), (P_, W_, P_), storage, VARIANTS, [0, 1, 0, 3, 2],
+                          extra=wet)
+    Sim.step_many(batch, 6)
+    for s in alone:
+        s.step(6)
+    _assert_same(batch, alone)
+
+
 def test_step_many_d3q19_periodic_full_tile():
     from paper_1812_00118_amd import Sim
     batch, alone = _pairs(19, (64, 8, 24), (P_, P_, P_), "fp32", VARIANTS[:2], [0, 1])

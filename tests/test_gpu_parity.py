@@ -296,6 +296,58 @@ def test_static_droplet_1000_steps():
     assert abs(m1 - mo) / mo <= 1e-6
 
 
+WET_CASES = [("d2q9-walls", 9, (70, 33, 1), (W_, W_, P_), (0.3, -0.5, 0.8, -0.2, 0, 0)),
+             ("d3q19-walls-z", 19, (70, 9, 13), (P_, P_, W_), (0, 0, 0, 0, 0.6, -0.7)),
+             ("d3q19-walls-all", 19, (17, 11, 6), (W_, W_, W_),
+              (0.3, -0.5, 0.8, -0.2, 0.6, -0.7))]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("name,q,shape,bc,wet", WET_CASES, ids=[c[0] for c in WET_CASES])
+def test_one_step_contact_angles(name, q, shape, bc, wet, storage):
+    """One step from a random state with a different contact angle on every wall face
+    (edges and corners add their faces' terms): FP32 at the one-step bar, FP16S within
+    its fp16 rounding bound."""
+    cfg = _cfg(q, shape, bc, wet_cos=wet, g=(1e-5, -2e-5, 0.0))
+    h0, g0 = pfinputs.random_state(q, shape, seed=sum(name.encode()) + 5)
+    s = _sim(cfg, storage=storage)
+    s.set_state(h0, g0)
+    s.step(1)
+    h1, g1 = (_np(t) for t in s.get_state())
+    hr, gr = O.step(_oracle_params(cfg), h0.astype(np.float64), g0.astype(np.float64))
+    if storage == "fp32":
+        _close(h1, hr)
+        _close(g1, gr)
+    else:
+        assert np.abs(h1 - hr).max() <= 2e-3 * np.abs(hr).max()
+        assert np.abs(g1 - gr).max() <= 2e-3 * np.abs(gr).max()
+    # the rule is active: the same step with 90-degree walls differs at the walls
+    hm, _ = O.step(_oracle_params(_cfg(q, shape, bc, g=(1e-5, -2e-5, 0.0))),
+                   h0.astype(np.float64), g0.astype(np.float64))
+    assert np.abs(hm - hr).max() > 1e-4 * np.abs(hr).max()
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_sessile_drop_parity_and_angle(theta):
+    """The wetting case on the GPU: equilibrium start, read-out and 1000 steps against
+    the oracle (max|d phi| <= 1e-5, relative momentum <= 1e-4), then 3000 more steps to
+    the prescribed contact angle (within 3.5 degrees, as the oracle reaches it)."""
+    from capgeom import cap_angle
+    cfg = pfinputs.sessile_drop(theta)
+    r, ro, (m0, m1, bad), mo = _run_pair(cfg, 1000)
+    assert not bad
+    assert np.abs(r["phi"] - ro["phi"]).max() <= 1e-5
+    assert _jerr(r["J"], ro["J"][:2], cfg["rho_H"]) <= 1e-4
+    assert abs(m1 - m0) / m0 <= 1e-7
+    phi, u, P = pfinputs.fields(cfg)
+    sim = _sim(cfg)
+    sim.init_fields(phi, u, P)
+    sim.step(4000)
+    got = cap_angle(_np(sim.read()["phi"]))
+    print(f"\nsessile drop {theta}: GPU angle after 4000 steps {got:.2f}")
+    assert abs(got - theta) < 3.5
+
+
 def _check_conditioned(cfg, r, ro, D):
     """max|d phi| <= max(1e-5, 4 x the oracle's half-ulp divergence), and the momentum
     error likewise against max(1e-4, 4 x the oracle's own)."""

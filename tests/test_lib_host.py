@@ -118,6 +118,8 @@ def _params(**kw):
             p.scale_log2[0], p.scale_log2[1] = v
         elif k == "wall":                      # (face, component, velocity)
             p.wall_u[3 * v[0] + v[1]] = v[2]
+        elif k == "wet":                       # (face, cos of the contact angle)
+            p.wet_cos[v[0]] = v[1]
         else:
             setattr(p, k, v)
     return p
@@ -131,12 +133,16 @@ def _params(**kw):
                                  dict(nx=1024, ny=1024, nz=256),
                                  dict(wall=(0, 1, 0.01)), dict(wall=(4, 2, 0.01)),
                                  dict(wall=(5, 0, float("nan"))),
-                                 dict(lattice=9, nz=1, wall=(4, 0, 0.01))])
+                                 dict(lattice=9, nz=1, wall=(4, 0, 0.01)),
+                                 dict(wet=(4, 1.5)), dict(wet=(5, float("nan"))),
+                                 dict(wet=(0, 0.5)),
+                                 dict(lattice=9, nz=1, bc=(1, 1, 0), wet=(4, 0.5))])
 def test_create_rejects_bad_params(L, bad):
     """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1,
-    domains beyond 2^28 - 64 sites, and wall velocities on periodic faces, normal to
-    their face, non-finite or on faces D2Q9 does not have return PFLB_ERR_PARAM and
-    leave *out NULL."""
+    domains beyond 2^28 - 64 sites, wall velocities on periodic faces, normal to
+    their face, non-finite or on faces D2Q9 does not have, and contact-angle cosines
+    outside [-1, 1], non-finite, on periodic faces or on faces D2Q9 does not have return
+    PFLB_ERR_PARAM and leave *out NULL."""
     p = _params(**bad)
     ctx = ctypes.c_void_p(1)
     rc = L.pflb_create(ctypes.byref(p), ctypes.byref(ctx))
@@ -147,6 +153,14 @@ def test_create_rejects_bad_params(L, bad):
 
 def test_create_accepts_tangential_wall_velocity(L):
     p = _params(wall=(5, 0, 0.01))            # z+ face moving along x
+    ctx = ctypes.c_void_p()
+    assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    L.pflb_destroy(ctx)
+
+
+@pytest.mark.parametrize("wet", [(4, 0.5), (5, -1.0), (5, 1.0)])
+def test_create_accepts_contact_angles_on_wall_faces(L, wet):
+    p = _params(wet=wet)                      # z faces are walls
     ctx = ctypes.c_void_p()
     assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
     L.pflb_destroy(ctx)
