@@ -6,6 +6,7 @@ start; distributions stored in FP32 (the value), with FP16-shifted storage timed
 it (speed-up and the phi difference between the two after the same steps).  Further
 blocks: the D3Q19 droplet impact on a film (256x256x128) and the same rising bubble on
 256^3, both storages; the D2Q9 Rayleigh-Taylor case (256x1024); the top wall moving;
+contact angles of 60 and 120 degrees on the bottom and top walls;
 and the learned 16-step surrogate (D2Q9 256^2 droplets): trained here on solver
 trajectories, then its held-out error, its forward/training rate against the BF16 MFMA
 peak, and its speed against 16 plain steps (batched over the domains) with the guard.
@@ -465,6 +466,23 @@ def main():
                       f"({r4['kernel_ms'] / rest:.3f}x the resting-wall step)",
                       file=sys.stderr, flush=True)
             out["moving_walls"] = blk
+            # contact angles: the rising-bubble domain with 60 degrees on the bottom and
+            # 120 on the top wall (the step variant with the wetting ghost rule)
+            cfg5 = dict(cfg, wet_cos=[0.0] * 4 + [0.5, -0.5])
+            blk = {"workload": "rising_bubble D3Q19 128^3, contact angles 60 (z-) and 120 (z+) "
+                               "degrees"}
+            for st in ("fp32", "fp16s"):
+                r5 = time_storage(cfg5, st, max(50, args.steps // 4), args.warmup)
+                rest = ms if st == args.storage else oms
+                blk[st] = {"mlups": round(N / (r5["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r5["kernel_ms"], 4),
+                           "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * N /
+                                                 (r5["kernel_ms"] * 1e-3) / 1e9, 1),
+                           "time_vs_90_degree_walls": round(r5["kernel_ms"] / rest, 3)}
+                print(f"[bench] contact_angles {st}: {r5['kernel_ms']:.4f} ms/step "
+                      f"({r5['kernel_ms'] / rest:.3f}x the 90-degree-wall step)",
+                      file=sys.stderr, flush=True)
+            out["contact_angles"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
