@@ -26,7 +26,8 @@ Workloads (lattice units, rho_L = 1):
                    sigma = 1e-2.  Seeds: train 0-255, validation 1000-1031, test 2000-2031.
   sessile_drop     D2Q9 96x40, x periodic, y walls, a half disc R = 12 on the bottom
                    wall, which prescribes a contact angle (rho_H = 10, nu = 0.1, M = 0.1,
-                   W = 4, sigma = 0.05): the wetting check (not a case of the paper).
+                   W = 4, sigma = 0.05): the wetting check (not a case of the paper);
+                   D3Q19 variant nx x nx x nz with a half ball on the z- wall.
   dense_bubble     D2Q9 80x40 periodic water (phi = 1) holding a dense bubble (a shallow
                    Gaussian dip, phi 0.93 at its centre, standard deviation 3 sites) and
                    a decent bubble (phi = 0 inside, R = 10) 40 sites apart; rho_H = 1000,
@@ -64,14 +65,18 @@ def dense_bubble(nx=80, ny=40, C=10.0, depth=0.07, spread=3.0, R=10.0):
                 dense_at=(nx / 4.0, (ny - 1) / 2.0), decent_at=(3.0 * nx / 4.0, (ny - 1) / 2.0))
 
 
-def sessile_drop(theta_deg, nx=96, ny=40, R=12.0):
-    """D2Q9 cap on the bottom wall (x periodic, y walls) whose bottom wall prescribes the
-    contact angle theta_deg; it starts as a half disc (90 degrees)."""
+def sessile_drop(theta_deg, nx=96, ny=40, R=12.0, lattice=9, nz=32):
+    """Cap on the bottom wall whose bottom wall prescribes the contact angle theta_deg;
+    it starts as a half disc (90 degrees).  D2Q9: nx x ny, x periodic, y walls; D3Q19:
+    nx x nx x nz, x and y periodic, z walls (a hemisphere)."""
     c = math.cos(math.radians(theta_deg))
-    return dict(name="sessile_drop", lattice=9, shape=(nx, ny, 1),
-                bc=(PERIODIC, WALL, PERIODIC), rho_L=1.0, rho_H=10.0, nu_L=0.1, nu_H=0.1,
-                M=0.1, W=4.0, sigma=0.05, g=(0.0, 0.0, 0.0), eps=1e-10, hoc=1, dtheta_C=0.0,
-                wet_cos=(0.0, 0.0, c, 0.0, 0.0, 0.0), theta_deg=theta_deg, R=R)
+    if lattice == 9:
+        shape, bc, wet = (nx, ny, 1), (PERIODIC, WALL, PERIODIC), (0.0, 0.0, c, 0.0, 0.0, 0.0)
+    else:
+        shape, bc, wet = (nx, nx, nz), (PERIODIC, PERIODIC, WALL), (0.0, 0.0, 0.0, 0.0, c, 0.0)
+    return dict(name="sessile_drop", lattice=lattice, shape=shape, bc=bc, rho_L=1.0,
+                rho_H=10.0, nu_L=0.1, nu_H=0.1, M=0.1, W=4.0, sigma=0.05, g=(0.0, 0.0, 0.0),
+                eps=1e-10, hoc=1, dtheta_C=0.0, wet_cos=wet, theta_deg=theta_deg, R=R)
 
 
 def rayleigh_taylor(nx=256, ny=1024):
@@ -262,10 +267,14 @@ def fields_dense_bubble(cfg):
 
 
 def fields_sessile_drop(cfg):
-    """Half disc of radius R centred on the wall line y = -1/2 (phi = 1 inside)."""
+    """Half disc (D2Q9) or half ball (D3Q19) of radius R centred on the wall line
+    y = -1/2 (resp. plane z = -1/2), phi = 1 inside."""
     z, y, x = _grid(cfg["shape"])
-    nx = cfg["shape"][0]
-    r = np.sqrt((x - (nx - 1) / 2.0) ** 2 + (y + 0.5) ** 2)
+    nx, ny = cfg["shape"][0], cfg["shape"][1]
+    if cfg["lattice"] == 9:
+        r = np.sqrt((x - (nx - 1) / 2.0) ** 2 + (y + 0.5) ** 2)
+    else:
+        r = np.sqrt((x - (nx - 1) / 2.0) ** 2 + (y - (ny - 1) / 2.0) ** 2 + (z + 0.5) ** 2)
     phi = 0.5 - 0.5 * np.tanh(2.0 * (r - cfg["R"]) / cfg["W"])
     u = np.zeros((3,) + phi.shape)
     return _f32(phi), _f32(u), _f32(np.zeros_like(phi))

@@ -29,3 +29,28 @@ def cap_angle(phi):
         mid = 0.5 * (lo + hi)
         lo, hi = (mid, hi) if f(mid) > r else (lo, mid)
     return math.degrees(0.5 * (lo + hi))
+
+
+def cap_angle_3d(phi):
+    """Angle in degrees of a three-dimensional cap on the z- wall (phi of shape
+    (nz, ny, nx), the cap centred in x and y): a spherical cap of radius R and angle t
+    has volume V = pi R^3 (2 - 3 cos t + cos^3 t) / 3 and height H = R (1 - cos t), so
+    V / H^3 = pi (2 - 3 cos t + cos^3 t) / (3 (1 - cos t)^3), which falls monotonically
+    from infinity to pi/6."""
+    phi = np.asarray(phi, dtype=np.float64)
+    nz, ny, nx = phi.shape
+    V = phi.sum()
+    col = phi[:, ny // 2 - 1:ny // 2 + 1, nx // 2 - 1:nx // 2 + 1].mean((1, 2))
+    j = int(np.where(col < 0.5)[0][0])
+    H = (j - 1) + (col[j - 1] - 0.5) / (col[j - 1] - col[j]) + 0.5
+    r = V / H ** 3
+
+    def f(t):
+        c = math.cos(t)
+        return math.pi * (2.0 - 3.0 * c + c ** 3) / (3.0 * (1.0 - c) ** 3)
+
+    lo, hi = 1e-6, math.pi - 1e-6
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) > r else (lo, mid)
+    return math.degrees(0.5 * (lo + hi))

@@ -426,3 +426,21 @@ def test_wetting_parameters_are_checked():
     a = O.step(p0, h.astype(np.float64), g.astype(np.float64))
     b = O.step(p1, h.astype(np.float64), g.astype(np.float64))
     assert all(np.array_equal(u, v) for u, v in zip(a, b))
+
+
+def test_cap_geometry_of_exact_caps_3d():
+    """The three-dimensional angle measurement recovers voxelised spherical caps."""
+    from capgeom import cap_angle_3d
+    nx = ny = 80
+    nz, R = 48, 24.0
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    s = (np.arange(4) + 0.5) / 4 - 0.5
+    for t in (60.0, 90.0, 120.0):
+        zc = -0.5 - R * np.cos(np.radians(t))
+        acc = np.zeros((nz, ny, nx))
+        for dx in s:
+            for dy in s:
+                for dz in s:
+                    acc += (((x + dx - (nx - 1) / 2) ** 2 + (y + dy - (ny - 1) / 2) ** 2
+                             + (z + dz - zc) ** 2 < R ** 2) & (z + dz > -0.5))
+        assert abs(cap_angle_3d(acc / 64.0) - t) < 1.0
