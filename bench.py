@@ -6,7 +6,8 @@ start; distributions stored in FP32 (the value), with FP16-shifted storage timed
 it (speed-up and the phi difference between the two after the same steps).  Further
 blocks: the D3Q19 droplet impact on a film (256x256x128) and the same rising bubble on
 256^3, both storages; the D2Q9 Rayleigh-Taylor case (256x1024); the top wall moving;
-contact angles of 60 and 120 degrees on the bottom and top walls;
+contact angles of 60 and 120 degrees on the bottom and top walls; the largest domain the
+library accepts (1000x1000x268 sites);
 and the learned 16-step surrogate (D2Q9 256^2 droplets): trained here on solver
 trajectories, then its held-out error, its forward/training rate against the BF16 MFMA
 peak, and its speed against 16 plain steps (batched over the domains) with the guard.
@@ -108,6 +109,50 @@ def time_storage(cfg, storage, steps, warmup):
     phi_out = sim.read(fields=("phi",))["phi"]
     return dict(kernel_ms=kernel_ms, wall_s=wall, mass=mass, nonfinite=bad, phi=phi_out,
                 steps_done=sim.steps)
+
+
+def largest_domain_block(steps=20, warmup=5):
+    """The step on the largest domain the library accepts (2.68e8 D3Q19 sites; 82 GB of
+    FP32 state): the rising-bubble fluid with a bubble of radius 64, its phi built on
+    the device (u = 0, P = 0)."""
+    import torch
+    from paper_1812_00118_amd import Sim
+    import pfinputs
+    nx, ny, nz, R = 1000, 1000, 268, 64.0
+    n = nx * ny * nz
+    cfg = dict(pfinputs.rising_bubble(R=R), shape=(nx, ny, nz))
+    blk = {"workload": f"rising_bubble D3Q19 {nx}x{ny}x{nz} ({n:.3g} sites, the largest "
+                       f"domain accepted), x,y periodic, z walls, R {R:g}"}
+    dev = torch.device("cuda")
+    for st in ("fp32", "fp16s"):
+        z = torch.arange(nz, device=dev, dtype=torch.float32).view(nz, 1, 1)
+        y = torch.arange(ny, device=dev, dtype=torch.float32).view(1, ny, 1)
+        x = torch.arange(nx, device=dev, dtype=torch.float32).view(1, 1, nx)
+        r = torch.sqrt((x - (nx - 1) / 2) ** 2 + (y - (ny - 1) / 2) ** 2 + (z - 2 * R) ** 2)
+        phi = 0.5 + 0.5 * torch.tanh(2.0 * (r - R) / cfg["W"])
+        del x, y, z, r
+        u = torch.zeros((3, nz, ny, nx), device=dev)
+        sim = Sim(cfg, storage=st)
+        sim.init_fields(phi, u)
+        del phi, u
+        sim.release_work()
+        torch.cuda.empty_cache()
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        _, bad = sim.mass()
+        ms = e0.elapsed_time(e1) / steps
+        blk[st] = {"mlups": round(n / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 3),
+                   "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * n / (ms * 1e-3) / 1e9, 1),
+                   "nonfinite": bad}
+        print(f"[bench] largest domain {st}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        del sim
+        torch.cuda.empty_cache()
+    return blk
 
 
 def read_traffic(storage):
@@ -466,6 +511,7 @@ def main():
                       f"({r4['kernel_ms'] / rest:.3f}x the resting-wall step)",
                       file=sys.stderr, flush=True)
             out["moving_walls"] = blk
+            out["largest_domain"] = largest_domain_block()
             # contact angles: the rising-bubble domain with 60 degrees on the bottom and
             # 120 on the top wall (the step variant with the wetting ghost rule)
             cfg5 = dict(cfg, wet_cos=[0.0] * 4 + [0.5, -0.5])
