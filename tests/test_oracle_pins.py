@@ -295,13 +295,16 @@ def test_init_recovers_fields(lat):
     assert np.allclose(r["P"], P0, atol=1e-13)
 
 
+@pytest.mark.parametrize("wet", [False, True], ids=["mirror", "contact-angles"])
 @pytest.mark.parametrize("lat", LATS, ids=lambda l: l.name)
-def test_step_sites_matches_step(lat):
-    """The sampled-site evaluation agrees with the whole-array step."""
+def test_step_sites_matches_step(lat, wet):
+    """The sampled-site evaluation agrees with the whole-array step (also with contact
+    angles on the wall faces, whose ghost rule the two apply separately)."""
     import pfinputs
     shape = (7, 6, 5 if lat.D == 3 else 1)
     bc = (O.PERIODIC, O.WALL, O.WALL if lat.D == 3 else O.PERIODIC)
-    prm = _prm(lat.Q, shape, bc, g=(1e-4, -1e-4, 2e-4))
+    kw = dict(wet_cos=(0, 0, 0.7, -0.4) + ((0.3, -0.9) if lat.D == 3 else (0, 0))) if wet else {}
+    prm = _prm(lat.Q, shape, bc, g=(1e-4, -1e-4, 2e-4), **kw)
     h, g = _random(lat, shape, 41)
     h1, g1 = O.step(prm, h, g)
     sites = pfinputs.sample_sites(shape, 20, 3)
