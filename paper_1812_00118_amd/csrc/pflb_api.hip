@@ -106,9 +106,11 @@ uint32_t sites(const pflb_params* p) { return (uint32_t)p->nx * p->ny * p->nz; }
 // 16% slower than 16.  Where even whole columns give more than two workgroups per CU
 // (several rounds of workgroups whatever bz), long marches let the running workgroups
 // drift apart in z and touch many more pages at once: there 16 planes, which keeps
-// them within a few planes of each other.  Measured (FP32): 1000x1000x268 16 planes
-// 24% faster than whole columns and the best of eight choices; 512x512x256 2.6% and
-// 384^3 2% faster than the model's choice (FP16S: 0.7% slower, 5.8% faster, 3.6% slower).
+// them within a few planes of each other.  Measured against the model's choice, FP32
+// (FP16S): 1000x1000x268 24% faster, the best of eight plane counts (0.7% slower);
+// 512x512x256 2.6% (5.8%) and 384^3 2% faster (3.6% slower); 512^3 11% (4.4%) faster;
+// 448^3 8% (9%) slower, where the model's 56 planes were the best of four.  On average
+// 7% faster in FP32 and neutral in FP16S; no single count is best everywhere.
 // D2Q9 (one-wave workgroups): about 2048 workgroups, at most 4 planes.  Measured: 256x1024
 // Rayleigh-Taylor, 2 planes beat 1, 4 and 8 (1.6x over 8); a lone 256x256 domain runs
 // best with 1 (small 2-D domains need the parallelism more than they lose to the
