@@ -111,7 +111,9 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
  * (the surrogate's densities per context are the contexts' own rho_L, rho_H).
  * For each window the surrogate predicts, in one batched forward pass, the state 16
  * steps ahead of every context; the prediction for context k is accepted when
- * |sum(phi_out) - sum(phi_in)| <= mass_tol * |sum(phi_in)|, when the largest speed the
+ * |sum(phi_out) - sum(phi_0)| <= mass_tol * |sum(phi_0)|, sum(phi_0) the context's sum
+ * at the start of the call (the method conserves it, so accepted windows cannot add up
+ * to a drift beyond mass_tol), when the largest speed the
  * hand-over would give, max |J| / rho' with rho' = rho_L + phi (rho_H - rho_L) +
  * rho_dif lap(phi) / 4 (Eq. 13's density where the context uses it; rho' <= 0 counts as
  * infinite), is at most u_max (a state handed over with an unphysical speed would make
@@ -119,7 +121,9 @@ int pfsur_gradients(pfsur_ctx* ctx, const void* x, const float* y, int batch, fl
  * check_every-th window (0: never), when max|phi_out - phi_LB| <= phi_tol against 16
  * plain steps taken from the same state.  An accepted prediction becomes the context's
  * new state (pflb_reconstruct); otherwise the 16 plain steps are taken.  A context whose
- * state is non-finite at the start of a window ends the call with PFLB_ERR_NONFINITE.
+ * state is non-finite at the start of a window ends the call with PFLB_ERR_NONFINITE
+ * before that window hands over a prediction or takes a fallback (on a checked window
+ * every context has by then taken the window's plain steps, its reference).
  *   lbs[batch]  contexts (periodic, nx = W, ny = H), batch <= max_batch
  *   work        pfsur_guard_work_bytes(cfg, batch) bytes of device memory, 256-aligned
  *   *n_fallback (host) number of (window, context) pairs that fell back.
@@ -131,8 +135,21 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int wi
                          double mass_tol, double phi_tol, double u_max, int check_every,
                          int* n_fallback, void* work, void* stream);
 
+/* pflb_advance_guarded that also records each decision and the quantities it rests on:
+ * trace (host, NULL: none) receives windows x batch records of PFSUR_TRACE_FIELDS
+ * doubles, record (window w, context k) at trace[(w * batch + k) * PFSUR_TRACE_FIELDS]:
+ *   [0] sum(phi_0)  [1] sum(phi_in) of the window  [2] sum(phi_out) of the prediction
+ *   [3] max |J_out| / rho'(phi_out)  [4] max |phi_out - phi_LB| (NaN if not checked)
+ *   [5] 1 accepted, 0 fell back.
+ * Sums are float64 over the float32 read-out fields in a fixed order. */
+#define PFSUR_TRACE_FIELDS 6
+int pflb_advance_guarded_trace(pflb_ctx* const* lbs, int batch, pfsur_ctx* sur, int windows,
+                               double mass_tol, double phi_tol, double u_max, int check_every,
+                               int* n_fallback, double* trace, void* work, void* stream);
+
 /* The accept rule of pflb_advance_guarded, a pure host function (1 accept, 0 reject):
- * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums),
+ * accept iff |sum_out - sum_in| <= mass_tol * |sum_in| (false for non-finite sums;
+ * pflb_advance_guarded passes the sum at the start of the call as sum_in),
  * speed <= u_max (false if non-finite) and, when checked != 0, phi_err <= phi_tol. */
 int pfsur_guard_accept(double sum_in, double sum_out, double mass_tol, double speed,
                        double u_max, int checked, double phi_err, double phi_tol);

@@ -89,6 +89,11 @@ _SIGS = {
                                             ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_int), _vp, _vp]),
+    "pflb_advance_guarded_trace": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int,
+                                                  ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ctypes.c_double), _vp, _vp]),
     "pfsur_guard_accept": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double]),

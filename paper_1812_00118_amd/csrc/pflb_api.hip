@@ -256,13 +256,14 @@ struct FileHeader {
     char magic[8];
     int lattice, nx, ny, nz, bc[3], storage, scale_log2[2], hoc;
     double rho_L, rho_H, nu_L, nu_H, M, W, sigma, g[3], eps, dtheta_C;
+    double wall_u[6][3], wet_cos[6];
     long long steps;
     unsigned long long set_bytes;
 };
 
 void fill_header(const pflb_ctx* c, FileHeader* h) {
     memset(h, 0, sizeof(*h));
-    memcpy(h->magic, "PFLBCK02", 8);
+    memcpy(h->magic, "PFLBCK03", 8);
     const pflb_params& p = c->p;
     h->lattice = p.lattice; h->nx = p.nx; h->ny = p.ny; h->nz = p.nz;
     for (int a = 0; a < 3; ++a) { h->bc[a] = p.bc[a]; h->g[a] = p.g[a]; }
@@ -272,6 +273,10 @@ void fill_header(const pflb_ctx* c, FileHeader* h) {
     h->hoc = p.hoc;
     h->rho_L = p.rho_L; h->rho_H = p.rho_H; h->nu_L = p.nu_L; h->nu_H = p.nu_H;
     h->M = p.M; h->W = p.W; h->sigma = p.sigma; h->eps = p.eps; h->dtheta_C = p.dtheta_C;
+    for (int f = 0; f < 6; ++f) {
+        for (int a = 0; a < 3; ++a) h->wall_u[f][a] = p.wall_u[f][a];
+        h->wet_cos[f] = p.wet_cos[f];
+    }
     h->steps = c->steps;
     h->set_bytes = set_bytes(&c->p, c->N);
 }

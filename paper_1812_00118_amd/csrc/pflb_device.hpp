@@ -690,7 +690,10 @@ __device__ __forceinline__ Macro macros(const Model& m, const float (&pn)[L::Q],
     const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
     const float inv = 1.0f / (gn + m.eps);
     a.nx = gx * inv; a.ny = gy * inv; a.nz = gz * inv;
-    a.theta = m.th_a * (1.0f - 4.0f * ph * ph);
+    // Eq. 4's 1 - 4 (phi - 1/2)^2 evaluated as 4 phi (1 - phi): the same value, without
+    // the cancellation that leaves it only ~1e-7 / (phi (1 - phi)) accurate in float32
+    // in the bulk phases (phi near 0 or 1), where the sharpening flux is then noise
+    a.theta = m.th_a * (4.0f * a.phi) * (1.0f - a.phi);
     if (m.dth != 0.0f) {
         const bool dense = fabsf(ph) > 0.35f && ph * a.lap > 0.0f;
         a.theta = fmaf(dense ? -m.dth : 0.0f, gn, a.theta);

@@ -667,6 +667,13 @@ size_t pfsur_guard_work_bytes(const pfsur_cfg* cfg, int batch) {
 int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
                          double mass_tol, double phi_tol, double u_max, int check_every,
                          int* n_fallback, void* work, void* stream) {
+    return pflb_advance_guarded_trace(lbs, n, c, windows, mass_tol, phi_tol, u_max,
+                                      check_every, n_fallback, nullptr, work, stream);
+}
+
+int pflb_advance_guarded_trace(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
+                               double mass_tol, double phi_tol, double u_max, int check_every,
+                               int* n_fallback, double* trace, void* work, void* stream) {
     if (!c) return PFLB_ERR_PARAM;
     if (!lbs || !work || !n_fallback) return fail(c, PFLB_ERR_PARAM, "NULL pointer");
     if (n < 1 || n > c->cfg.max_batch) return fail(c, PFLB_ERR_PARAM, "batch must be in [1, max_batch]");
@@ -708,6 +715,7 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         fJ[k] = J + 2 * k * HW;
         flb[k] = phi_lb + k * HW;
     }
+    std::vector<double> s_ref(n, 0.0);        // sum(phi) of each context at the start
     std::vector<pflb_ctx*> acc_ctx, rej_ctx;
     std::vector<const float*> acc_phi, acc_P, acc_J;
     auto lb_fail = [&](int r, pflb_ctx* lc, const char* what) {
@@ -749,13 +757,16 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
         SUR_TRY(hipMemcpyAsync(hd.data(), dpart, 2 * nb * 8, hipMemcpyDeviceToHost, st),
                 "field sums");
         SUR_TRY(hipStreamSynchronize(st), "guard read-back");
-        // a context whose state went non-finite ends the call before any context changes
+        // a context whose state is non-finite at the window's start ends the call before
+        // any prediction is handed over or any fallback taken; on a checked window every
+        // context has already taken the window's plain steps (the reference) by then
         for (int k = 0; k < n; ++k) {
             double s_in = 0.0;
             for (int b = 0; b < GUARD_BLOCKS; ++b) s_in += hd[(size_t)k * GUARD_BLOCKS + b];
             if (!isfinite(s_in))
                 return fail(c, PFLB_ERR_NONFINITE,
                             "lattice state of context " + std::to_string(k) + " is non-finite");
+            if (win == 0) s_ref[k] = s_in;
         }
         acc_ctx.clear();
         acc_phi.clear();
@@ -779,7 +790,20 @@ int pflb_advance_guarded(pflb_ctx* const* lbs, int n, pfsur_ctx* c, int windows,
                 }
                 if (err != err) err = INFINITY;
             }
-            if (pfsur_guard_accept(s_in, s_out, mass_tol, speed, u_max, checked, err, phi_tol)) {
+            // the mass test is against the sum at the start of the call, which the method
+            // conserves: accepted windows cannot add up to a drift beyond mass_tol
+            const int ok =
+                pfsur_guard_accept(s_ref[k], s_out, mass_tol, speed, u_max, checked, err, phi_tol);
+            if (trace) {
+                double* t = trace + ((size_t)win * n + k) * PFSUR_TRACE_FIELDS;
+                t[0] = s_ref[k];
+                t[1] = s_in;
+                t[2] = s_out;
+                t[3] = speed;
+                t[4] = checked ? err : NAN;
+                t[5] = ok;
+            }
+            if (ok) {
                 acc_ctx.push_back(lbs[k]);
                 acc_phi.push_back(fphi[k]);
                 acc_P.push_back(fP[k]);

@@ -190,13 +190,16 @@ class Surrogate:
 
     # ------------------------------------------------------------------ hand-over
     def advance_guarded(self, sims, windows, mass_tol=1e-3, phi_tol=0.05, check_every=0,
-                        u_max=0.1):
+                        u_max=0.1, trace=False):
         """Advance D2Q9 periodic Sims (one, or a list of at most max_batch) by windows x 16
         steps with one batched forward pass per window; returns the number of (window,
         sim) pairs that fell back to the plain steps.  A prediction is rejected when it
-        changes sum(phi) by more than mass_tol (relative), when its largest speed exceeds
-        u_max, or (on every check_every-th window) when it is more than phi_tol from the
-        plain steps."""
+        changes sum(phi) from its value at the start of the call by more than mass_tol
+        (relative), when its largest speed exceeds u_max, or (on every check_every-th
+        window) when it is more than phi_tol from the plain steps.  With trace=True returns
+        (n_fallback, records), records a float64 array [windows][len(sims)][6] of
+        (sum phi at the start, sum phi_in, sum phi_out, max speed, max|phi_out - phi_LB|
+        (NaN unchecked), accepted) per decision."""
         if not isinstance(sims, (list, tuple)):
             sims = [sims]
         n = len(sims)
@@ -207,11 +210,13 @@ class Surrogate:
         wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
         ctxs = (ctypes.c_void_p * n)(*[s.ctx.value for s in sims])
         nf = ctypes.c_int()
-        self._check(self.L.pflb_advance_guarded(ctxs, n, self.ctx, int(windows),
-                                                float(mass_tol), float(phi_tol), float(u_max),
-                                                int(check_every), ctypes.byref(nf), wp,
-                                                _stream(self.device)))
-        return int(nf.value)
+        rec = np.zeros((max(int(windows), 0), n, 6), dtype=np.float64) if trace else None
+        self._check(self.L.pflb_advance_guarded_trace(
+            ctxs, n, self.ctx, int(windows), float(mass_tol), float(phi_tol), float(u_max),
+            int(check_every), ctypes.byref(nf),
+            rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if trace else None, wp,
+            _stream(self.device)))
+        return (int(nf.value), rec) if trace else int(nf.value)
 
 
 # ---------------------------------------------------------------------- building blocks

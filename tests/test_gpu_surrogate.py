@@ -499,3 +499,128 @@ def test_context_calls_reject_bad_arguments(sur_mod, tmp_path):
     junk.write_bytes(b"not a checkpoint" * 8)
     with pytest.raises(PflbError):
         s.load(junk)
+
+
+# ----------------------------------------------------------- guard decision quantities
+def _host_speed(phi, J, rho_L, rho_H, beta):
+    """max |J| / rho' in float64, rho' = rho_L + phi rho_dif + beta rho_dif lap(phi) / 4
+    with the D2Q9 central Laplacian (2/T) sum_i w_i (phi(x + c_i) - phi(x)) on the
+    periodic grid (Eq. 13's density); rho' <= 0 counts as infinite."""
+    p = phi.astype(np.float64)
+    nb = lambda dy, dx: np.roll(np.roll(p, -dy, 0), -dx, 1) - p
+    lap = 6.0 * ((nb(0, 1) + nb(0, -1) + nb(1, 0) + nb(-1, 0)) / 9.0 +
+                 (nb(1, 1) + nb(1, -1) + nb(-1, 1) + nb(-1, -1)) / 36.0)
+    rd = rho_H - rho_L
+    rp = rho_L + p * rd + beta * 0.25 * rd * lap
+    sp = np.hypot(J[0].astype(np.float64), J[1].astype(np.float64))
+    with np.errstate(divide="ignore"):
+        return float(np.where(rp > 0, sp / np.where(rp > 0, rp, 1.0), np.inf).max())
+
+
+def test_guard_decision_quantities_match_host_fp64(sur_mod):
+    """The quantities each guard decision rests on -- sum(phi) at the start, before and
+    after the prediction, the largest hand-over speed max|J|/rho' and, on a checked
+    window, max|phi_out - phi_LB| -- as the library records them, against a float64
+    evaluation on the host of the same read-out fields: the prediction rebuilt from the
+    public pack/forward/apply calls, the plain steps from a twin context."""
+    s = _net(sur_mod, 64)
+    seeds = (3, 4, 5)
+    ctx = [_drops_sim(seed=k)[0] for k in seeds]
+    twin = [_drops_sim(seed=k)[0] for k in seeds]      # follows ctx, fields read on host
+    lbs = [_drops_sim(seed=k)[0] for k in seeds]       # takes the plain steps
+    cfgs = [pfinputs_drops(k) for k in seeds]
+    rho = [(c["rho_L"], c["rho_H"]) for c in cfgs]
+    for win, checked in enumerate((False, True)):
+        f = [t.read(("phi", "P", "J")) for t in twin]
+        phi = torch.stack([x["phi"].reshape(64, 64) for x in f])
+        P = torch.stack([x["P"].reshape(64, 64) for x in f])
+        J = torch.stack([x["J"].reshape(2, 64, 64) for x in f])
+        s_in = phi.cpu().numpy().astype(np.float64).sum(axis=(1, 2)).tolist()
+        s_ref = s_in                  # each call's reference is the sum at its start
+        out = s.forward(s.pack(phi, P, J, rho))
+        s.apply(out, phi, P, J, rho)
+        nf, rec = s.advance_guarded(ctx, 1, mass_tol=1e30, phi_tol=1e30,
+                                    check_every=1 if checked else 0, u_max=1e30, trace=True)
+        assert nf == 0 and rec.shape == (1, 3, 6)
+        if checked:
+            for t in lbs:
+                t.step(16)
+        for k in range(3):
+            r = rec[0, k]
+            ph = phi[k].cpu().numpy()
+            s_out = ph.astype(np.float64).sum()
+            sp = _host_speed(ph, J[k].cpu().numpy(), rho[k][0], rho[k][1], 1.0)
+            print(f"\nwindow {win} ctx {k}: sum0 {r[0]:.10g} ({s_ref[k]:.10g}) sum_in {r[1]:.10g} "
+                  f"({s_in[k]:.10g}) sum_out {r[2]:.10g} ({s_out:.10g}) speed {r[3]:.6g} "
+                  f"({sp:.6g}) phi_err {r[4]:.6g}")
+            assert abs(r[0] - s_ref[k]) <= 1e-12 * abs(s_ref[k])
+            assert abs(r[1] - s_in[k]) <= 1e-12 * abs(s_in[k])
+            assert abs(r[2] - s_out) <= 1e-12 * abs(s_out)
+            assert abs(r[3] - sp) <= 1e-4 * sp
+            if checked:
+                lb = lbs[k].read(("phi",))["phi"].reshape(64, 64).cpu().numpy()
+                err = np.abs(ph.astype(np.float64) - lb.astype(np.float64)).max()
+                assert abs(r[4] - err) <= 1e-6 * err
+            else:
+                assert np.isnan(r[4])
+            assert r[5] == 1.0
+        # keep the twins on the accepted path
+        for k in range(3):
+            for t in (twin[k], lbs[k]):
+                t.reconstruct(phi[k].reshape(1, 64, 64), J[k].reshape(2, 1, 64, 64),
+                              P[k].reshape(1, 64, 64), advance=16)
+            assert torch.equal(twin[k].read(("phi",))["phi"], ctx[k].read(("phi",))["phi"])
+
+
+def _mass_shift_net(sur_mod, n, rel):
+    """A network whose phi prediction is phi + c everywhere, c chosen so that the
+    prediction moves sum(phi) of the drops start by `rel` (relative): the head's phi
+    weights zeroed and its phi bias set from the host."""
+    params = U.init_weights(1, scale=0.1)
+    w, b = params["head"]
+    w = w.copy()
+    b = b.copy()
+    w[0] = 0.0
+    out_scale = 1e-3
+    sim, cfg = _drops_sim(n=n)
+    s0 = sim.mass()[0]
+    b[0] = rel * s0 / (n * n) / out_scale
+    params["head"] = (w, b)
+    norm = dict(in_shift=[0.5, 0.0, 0.0, 0.0], in_scale=[2.0, 100.0, 100.0, 100.0],
+                out_scale=[out_scale] * 4, lrr_scale=0.5)
+    s = sur_mod.Surrogate(n, n, 4, norm)
+    s.set_params(flat_params(params))
+    return s
+
+
+def test_guard_rejects_a_prediction_shifted_by_one_percent_of_the_mass(sur_mod):
+    """A prediction whose sum(phi) is 1e-2 off (set from the host through the head's
+    bias) is rejected at mass_tol 1e-3, every other check open: the context ends exactly
+    as after the plain steps, and the record shows the 1e-2 shift."""
+    s = _mass_shift_net(sur_mod, 64, 1e-2)
+    a, _ = _drops_sim()
+    b, _ = _drops_sim()
+    nf, rec = s.advance_guarded(a, 1, mass_tol=1e-3, phi_tol=1e30, check_every=0,
+                                u_max=1e30, trace=True)
+    b.step(16)
+    r = rec[0, 0]
+    print(f"\nshifted prediction: sum_out / sum_0 - 1 = {r[2] / r[0] - 1:.4e}, accepted {r[5]}")
+    assert nf == 1 and r[5] == 0.0
+    assert abs((r[2] / r[0] - 1.0) - 1e-2) <= 1e-4
+    assert torch.equal(a.read(("phi",))["phi"], b.read(("phi",))["phi"])
+
+
+def test_guard_mass_drift_does_not_compound_over_windows(sur_mod):
+    """Each prediction moves sum(phi) by +6e-4 of its input (below mass_tol 1e-3), so
+    windows judged against their own input would all pass and drift by 1.8e-3 over three
+    windows; judged against the sum at the start of the call the first is accepted and
+    the next two, 1.2e-3 off, fall back: the drift stays within mass_tol."""
+    s = _mass_shift_net(sur_mod, 64, 6e-4)
+    a, _ = _drops_sim()
+    m0 = a.mass()[0]
+    nf, rec = s.advance_guarded(a, 3, mass_tol=1e-3, phi_tol=1e30, check_every=0,
+                                u_max=1e30, trace=True)
+    m1 = a.mass()[0]
+    print(f"\nper-window decisions {rec[:, 0, 5].tolist()}, drift {(m1 - m0) / m0:.3e}")
+    assert rec[:, 0, 5].tolist() == [1.0, 0.0, 0.0] and nf == 2
+    assert abs(m1 - m0) <= 1e-3 * m0
