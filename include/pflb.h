@@ -162,6 +162,24 @@ int pflb_get_state(pflb_ctx* ctx, float* h, float* g, void* stream);
 int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
                      float* work, void* stream);
 
+/* Allocation-free start, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as pflb_init_fields, bit for bit, with the 2*Q*N floats it stages between its
+ * two kernels held in a fixed device array of the library instead of a work buffer.
+ *   Limit: 2*Q*N*4 <= PFLB_NOALLOC_SCRATCH_BYTES (64 MiB: N <= 441,505 D3Q19 sites,
+ *   932,067 D2Q9 sites); larger domains return PFLB_ERR_PARAM and change nothing.
+ *   The call allocates nothing (no hipMalloc, no library allocation).  The array is
+ *   one per GPU, held from its first use on that GPU until the process ends, and
+ *   shared by every call on that GPU: calls on one GPU that overlap in time (other
+ *   threads, other streams not ordered with this one) race on it and must not be
+ *   issued.  Asynchronous on stream, like pflb_init_fields. */
+#define PFLB_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int pflb_init_fields_noalloc(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
+                             void* stream);
+
+/* PFLB_NOALLOC_SCRATCH_BYTES, as compiled into the library. */
+size_t pflb_noalloc_scratch_bytes(void);
+
 /* Replace the state by the equilibria of given macroscopic fields (a hand-over from
  * another model of the same flow, e.g. a learned surrogate): u = J / rho' with rho' the
  * density read-out divides by, then the equilibria of pflb_equilibrium and the state

@@ -56,6 +56,8 @@ _SIGS = {
     "pflb_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pflb_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pflb_init_fields": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pflb_init_fields_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pflb_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "pflb_reconstruct": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "pflb_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "pflb_step_many": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -374,6 +375,71 @@ int pflb_init_fields(pflb_ctx* c, const float* phi, const float* u, const float*
     if (!work) return fail(c, PFLB_ERR_PARAM, "NULL work buffer");
     float* h = work;
     float* g = work + (size_t)c->Q * c->N;
+    r = pflb_equilibrium(c, phi, u, P, h, g, stream);
+    if (r) return r;
+    return pflb_set_state(c, h, g, stream);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free start: the equilibria staged between the two kernels of
+// pflb_init_fields (2 Q N floats) live in a fixed device array of this library instead
+// of caller memory.  Each GPU the library runs on holds its own copy of the array from
+// the first use of this code on that GPU until the process ends; its address on each
+// device is looked up once, with that device current, and kept.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+static __device__ __align__(256) float scratch[PFLB_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (hipGetSymbolAddress once per device)
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pflb_noalloc_scratch_bytes(void) { return PFLB_NOALLOC_SCRATCH_BYTES; }
+
+int pflb_init_fields_noalloc(pflb_ctx* c, const float* phi, const float* u, const float* P,
+                             void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!phi || !u) return fail(c, PFLB_ERR_PARAM, "NULL field pointer");
+    const size_t need = (size_t)2 * c->Q * c->N * sizeof(float);
+    if (need > (size_t)PFLB_NOALLOC_SCRATCH_BYTES)
+        return fail(c, PFLB_ERR_PARAM,
+                    "domain too large for the allocation-free start: it stages 2*Q*N floats (" +
+                        std::to_string(need) + " bytes) in a fixed array of " +
+                        std::to_string((size_t)PFLB_NOALLOC_SCRATCH_BYTES) +
+                        " bytes; use pflb_init_fields with a work buffer");
+    void* ptr = nullptr;
+    hipError_t e = scratch_address(&ptr);
+    if (e != hipSuccess) return hip_fail(c, e, "address of the static scratch array");
+    // every staged value is written by the equilibrium kernel before the state load
+    // reads it, so the array needs no clearing between calls
+    float* h = static_cast<float*>(ptr);
+    float* g = h + (size_t)c->Q * c->N;
     r = pflb_equilibrium(c, phi, u, P, h, g, stream);
     if (r) return r;
     return pflb_set_state(c, h, g, stream);

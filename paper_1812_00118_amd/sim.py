@@ -130,6 +130,17 @@ class Sim:
         self._check(self.L.pflb_init_fields(self.ctx, _ptr(phi_t), _ptr(u_t), _ptr(P_t),
                                             _ptr(self._work), self._stream()))
 
+    def init_fields_noalloc(self, phi, u, P=None):
+        """init_fields through pflb_init_fields_noalloc: the library stages the
+        equilibria in its fixed device array (no work buffer; domains up to
+        pflb_noalloc_scratch_bytes() / (8 Q) sites)."""
+        phi_t = self._dev(phi, self.shape)
+        u_t = self._dev(np.asarray(u)[:self.D] if not torch.is_tensor(u) else u[:self.D],
+                        (self.D,) + self.shape)
+        P_t = self._dev(P, self.shape) if P is not None else None
+        self._check(self.L.pflb_init_fields_noalloc(self.ctx, _ptr(phi_t), _ptr(u_t),
+                                                    _ptr(P_t), self._stream()))
+
     def reconstruct(self, phi, J, P=None, advance=0):
         """Replace the state by the equilibria of (phi, P, J); the step counter grows by
         `advance`."""
