@@ -49,6 +49,12 @@ struct LatD3Q19 {
     __host__ __device__ static constexpr float w(int i) {
         return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
     }
+    // w_i - float(w_i): the float32 weights are 1/18 and 1/36 only to 7.5e-9 relative
+    __host__ __device__ static constexpr float w_lo(int i) {
+        return i == 0 ? (float)(1.0 / 3.0 - (double)(1.0f / 3.0f))
+                      : (i <= 6 ? (float)(1.0 / 18.0 - (double)(1.0f / 18.0f))
+                                : (float)(1.0 / 36.0 - (double)(1.0f / 36.0f)));
+    }
     // FP16S reference coefficients: dyadic r_i ~ 4 w_i with sum_i r_i = 4 exactly
     __host__ __device__ static constexpr float r(int i) {
         return i == 0 ? 1398112.0f / 1048576.0f
@@ -71,6 +77,11 @@ struct LatD2Q9 {  // user (x, y) -> internal (x, z)
     }
     __host__ __device__ static constexpr float w(int i) {
         return i == 0 ? 4.0f / 9.0f : (i <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f);
+    }
+    __host__ __device__ static constexpr float w_lo(int i) {
+        return i == 0 ? (float)(4.0 / 9.0 - (double)(4.0f / 9.0f))
+                      : (i <= 4 ? (float)(1.0 / 9.0 - (double)(1.0f / 9.0f))
+                                : (float)(1.0 / 36.0 - (double)(1.0f / 36.0f)));
     }
     __host__ __device__ static constexpr float r(int i) {
         return i == 0 ? 1864144.0f / 1048576.0f
@@ -707,7 +718,10 @@ __device__ __forceinline__ Macro macros(const Model& m, const float (&pn)[L::Q],
     const float irp = 1.0f / rho_p;
     a.ux = a.jx * irp; a.uy = a.jy * irp; a.uz = a.jz * irp;
     const float ug = a.ux * gx + a.uy * gy + a.uz * gz;
-    a.P = (1.0f / 3.0f) * sg + (m.rho_dif * (1.0f / 6.0f)) * ug;
+    // T sum g with T = 1/3 carried as two floats: float(1/3) alone is 3e-8 too large,
+    // a bias the pressure would pick up at every step
+    constexpr float third_lo = (float)(1.0 / 3.0 - (double)(1.0f / 3.0f));
+    a.P = fmaf(1.0f / 3.0f, sg, third_lo * sg) + (m.rho_dif * (1.0f / 6.0f)) * ug;
     return a;
 }
 
@@ -751,7 +765,8 @@ __device__ __forceinline__ void eq_dir(const Macro& a, const EqTerms& t, float& 
     const float kc = w * fmaf(e, t.A, 3.0f * a.mu);
     K = fmaf(kc, cg - t.ug, 3.0f * Gam * (cF - t.uF));
     // rho Gamma + w (P/T - rho) = w (rho e + 3P); Eq. 13: + w cu (3/4) rho_dif lap
-    geq = fmaf(w, fmaf(a.rho, e, t.P3) + cu * t.dcoef, -0.5f * K);
+    const float X = fmaf(a.rho, e, t.P3) + cu * t.dcoef;
+    geq = fmaf(w, X, fmaf(L::w_lo(I), X, -0.5f * K));
 }
 
 
@@ -800,17 +815,18 @@ __device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, f
     const float tr3 = (Pxx + Pyy + Pzz) * third;
     const float hw0 = fmaf(a.phi, L::w(0), -h[0]);
     {   // rest population: c = 0
-        constexpr float w = L::w(0);
+        constexpr float w = L::w(0), wl = L::w_lo(0);
         const float hdev = fmaf(a.phi, w * E0, a.phi * kappa<L>());
         const float ho = fmaf(m.om_phi, hw0 + fmaf(phi_lo, w, hdev), h[0]);
         const float K = w * (fmaf(E0, A, mu3) * (-ug) + 3.0f * (1.0f + E0) * (-uF));
-        const float go = fmaf(w, fmaf(a.rho, E0, P3), fmaf(0.5f, K, om1 * 4.5f * w * (-tr3)));
+        const float X = fmaf(a.rho, E0, P3);
+        const float go = fmaf(w, X, fmaf(wl, X, fmaf(0.5f, K, om1 * 4.5f * w * (-tr3))));
         out.template put<0>(ho, go);
     }
     static_for<0, (L::Q - 1) / 2>([&](auto K_) {
         constexpr int i = 2 * decltype(K_)::value + 1;          // pair (i, i + 1), c_{i+1} = -c_i
         constexpr int ex = L::cx(i), ey = L::cy(i), ez = L::cz(i);
-        constexpr float w = L::w(i);
+        constexpr float w = L::w(i), wl = L::w_lo(i);
         float cu = 0.f, cd = 0.f, cF = 0.f, cn = 0.f, ccP = 0.f;
         if constexpr (ex != 0) { cu += ex * ux; cd += ex * a.gx; cF += ex * a.Fx; cn += ex * a.nx; ccP += Pxx; }
         if constexpr (ey != 0) { cu += ey * uy; cd += ey * a.gy; cF += ey * a.Fy; cn += ey * a.ny; ccP += Pyy; }
@@ -828,10 +844,15 @@ __device__ __forceinline__ void collide_stream(const Model& m, const Macro& a, f
         // K_i = w [(e A + 3 mu)(c.d - u.d) + 3 (1 + e)(c.F - u.F)]             (Eq. 7)
         const float Kp = w * fmaf(fmaf(ep, A, mu3), cd - ug, 3.0f * (1.0f + ep) * (cF - uF));
         const float Km = w * fmaf(fmaf(em, A, mu3), -cd - ug, 3.0f * (1.0f + em) * (-cF - uF));
-        // g* = w (rho e + 3P + (c.u) dcoef) + K/2 + (1 - 1/tau) 4.5 w (c c : Pi - tr/3)
+        // g* = w (rho e + 3P + (c.u) dcoef) + K/2 + (1 - 1/tau) 4.5 w (c c : Pi - tr/3).
+        // The equilibrium part takes w as float(w_i) + w_lo: with float(w_i) alone the
+        // equilibrium's momentum is rho u (1 + 7.5e-9), a gain that compounds over the
+        // steps (after 1000 steps of the droplet impact, 1.9e-5 in phi)
         const float filt = om1 * 4.5f * w * (ccP - tr3);
-        const float gp = fmaf(w, fmaf(a.rho, ep, P3) + cu * dcoef, fmaf(0.5f, Kp, filt));
-        const float gm = fmaf(w, fmaf(a.rho, em, P3) - cu * dcoef, fmaf(0.5f, Km, filt));
+        const float Xp = fmaf(a.rho, ep, P3) + cu * dcoef;
+        const float Xm = fmaf(a.rho, em, P3) - cu * dcoef;
+        const float gp = fmaf(w, Xp, fmaf(wl, Xp, fmaf(0.5f, Kp, filt)));
+        const float gm = fmaf(w, Xm, fmaf(wl, Xm, fmaf(0.5f, Km, filt)));
         out.template put<i>(hp, gp);
         out.template put<i + 1>(hm, gm);
     });

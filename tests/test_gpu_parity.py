@@ -490,25 +490,24 @@ def test_d3q19_reduced_1000_steps(name):
 
 
 def test_dense_bubble_correction_parity():
-    """The Eq. 14 correction with the reading F = -1 on dense bubbles (C = 0.1) matches
-    the oracle's reading of it over 300 steps and conserves sum(phi)."""
-    cfg = pfinputs.static_droplet(n=48, R=10.0)
-    cfg["dtheta_C"] = 0.1
-    phi, u, P = pfinputs.fields(cfg)
-    phi = np.clip(phi + 0.05 * pfinputs.smooth_random_field(cfg["shape"], 9).astype(np.float32),
-                  0, 1).astype(np.float32)
-    sim = _sim(cfg)
-    sim.init_fields(phi, u, P)
-    m0, _ = sim.mass()
-    sim.step(300)
-    r = sim.read()
-    m1, _ = sim.mass()
-    prm = _oracle_params(cfg)
-    h, g = O.init(prm, phi.astype(np.float64), u.astype(np.float64), P.astype(np.float64))
-    h, g = O.run(prm, h, g, 300)
-    ro = O.read(prm, h, g)
-    assert np.abs(_np(r["phi"]) - ro["phi"]).max() <= 1e-5
-    assert abs(m1 - m0) / m0 <= 1e-6
+    """The Eq. 14 correction with the reading F = -1 on dense bubbles, at C = 0.1, on the
+    seeded dense-bubble case (F switched on at ~300 sites) over 50 steps against the
+    oracle's reading of it, at the plain bar (max|d phi| <= 1e-5, relative J error <=
+    1e-4), with sum(phi) conserved.  50 steps keeps the case well conditioned: the
+    oracle's own divergence from a float32 half-ulp change of its start is 1e-6 there
+    and grows to 4e-5 by 300 steps, as the dip sharpens into a bubble (a physically
+    unstable nucleation); the 300-step comparison at C = 10 below carries the
+    conditioning-aware bar."""
+    cfg = pfinputs.dense_bubble(C=0.1)
+    r, ro, (m0, m1, bad), mo = _run_pair(cfg, 50, conditioning=True)
+    assert not bad
+    dphi = np.abs(r["phi"] - ro["phi"]).max()
+    eJ = _jerr(r["J"], ro["J"][:2], cfg["rho_H"])
+    print(f"\ndense bubble C = 0.1, 50 steps: max|dphi| {dphi:.2e} (oracle half-ulp floor "
+          f"{ro['dphi_floor']:.2e}), J err {eJ:.2e}")
+    assert dphi <= 1e-5
+    assert eJ <= 1e-4
+    assert abs(m1 - m0) / m0 <= 1e-6 and abs(m1 - mo) / mo <= 1e-6
 
 
 def test_dense_bubble_case_parity_and_behaviour():
