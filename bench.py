@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 two-set MLUPS & % HBM roofline; FP16-store/surrogate vs FP32 at stated φ err"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per site update: read + write of both sets once
-# (FP16S: per site a float32 reference level and one fp16 word per population, per set)
-BYTES_PER_SITE = {("19", "fp32"): 2 * 2 * 19 * 4, ("19", "fp16s"): 2 * 2 * (4 + 19 * 2),
-                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * 2 * (4 + 9 * 2)}
+# algorithmic bytes per site update: read + write of both sets once (FP16S: per site
+# the float32 rest populations of both sets and an fp16 moments word of 8 values, and
+# per moving population one fp16 deviation per set)
+BYTES_PER_SITE = {("19", "fp32"): 2 * 2 * 19 * 4, ("19", "fp16s"): 2 * (8 + 16 + 18 * 4),
+                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * (8 + 16 + 8 * 4)}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rising_bubble_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1812_00118_amd", "csrc")
 

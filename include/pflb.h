@@ -52,16 +52,19 @@ extern "C" {
 #define PFLB_BC_WALL     1     /* no-slip wall half a site outside the last layer   */
 
 #define PFLB_STORE_FP32  0     /* populations stored as float32                     */
-#define PFLB_STORE_FP16S 1     /* per site a float32 reference level R ~ phi/4 per  */
-                               /* set; every population stored as an fp16 deviation */
-                               /* from r_i R (dyadic r_i ~ 4 w_i, sum r_i = 4);     */
-                               /* FP32 arithmetic throughout                        */
+#define PFLB_STORE_FP16S 1     /* rest populations float32; every moving population */
+                               /* an fp16 deviation from the first-order equilibrium */
+                               /* of its reading site's previous moments (FP32      */
+                               /* arithmetic throughout)                             */
 
 /* buffer ids for pflb_required_bytes / pflb_bind.  A state buffer holds both
- * distribution sets interleaved per population (FP32: float2 (h_i, g_i) per slot;
- * FP16S: a float2 pair of reference levels per site, then a half2 deviation pair
- * per population);
- * the step reads one state buffer and writes the other. */
+ * distribution sets (FP32: float2 (h_i, g_i) per slot, [Q][S]; FP16S: per site the
+ * float2 rest pair (h_0, g_0) and a 16-byte word of its pre-collision moments in fp16
+ * (sum h, sum g, sum c h, sum c g), then a half2 deviation pair (h_i, g_i) per moving
+ * population, [Q-1][S], decoded as w_i (sum h + 3 c_i . sum c h) + dev_h / 2^scale_h
+ * and likewise for g, with the moments of the site that reads the slot); the step
+ * reads one state buffer and writes the other.  The FP16S moments and deviations must
+ * stay within the fp16 range (|sum g|, |sum c g| < 65504; |dev| 2^scale < 65504). */
 #define PFLB_BUF_STATE0  0
 #define PFLB_BUF_STATE1  1
 #define PFLB_BUF_SCRATCH 2     /* reduction partial sums and flags                  */
@@ -199,6 +202,15 @@ int pflb_reconstruct(pflb_ctx* ctx, const float* phi, const float* P, const floa
  * PFLB_BZ (planes per workgroup along z) and PFLB_TILE (D3Q19 tile: 0 64x4, the
  * default; 1 64x8; 2 32x8; 3 32x4). */
 int pflb_step(pflb_ctx* ctx, int nsteps, void* stream);
+
+/* The same nsteps steps as pflb_step, enqueued as one HIP graph: the first call for a
+ * given nsteps and current state buffer captures the launches pflb_step would issue
+ * and instantiates them; later calls with the same nsteps replay that graph (one launch
+ * instead of nsteps).  Results are bitwise those of pflb_step.  `stream` must not be
+ * the null stream (stream capture needs a created stream).  The graphs are kept until
+ * a call with another nsteps, pflb_bind or pflb_destroy.  A device-side way to cut the
+ * launch overhead of small, launch-bound domains (Section 4's two-dimensional cases). */
+int pflb_step_graph(pflb_ctx* ctx, int nsteps, void* stream);
 
 /* The same steps for n contexts at once (an ensemble of small domains fills the GPU
  * where one alone is launch-bound): each step is one launch per 16 contexts; a context

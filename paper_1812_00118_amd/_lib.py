@@ -60,6 +60,7 @@ _SIGS = {
     "pflb_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "pflb_reconstruct": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "pflb_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "pflb_step_graph": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "pflb_step_many": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp]),
     "pflb_read": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pflb_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),

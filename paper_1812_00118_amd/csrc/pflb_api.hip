@@ -26,6 +26,19 @@ struct pflb_ctx {
     int cur = 0;              // state buffer holding the current state
     long long steps = 0;
     std::string err;
+    // pflb_step_graph: instantiated graphs of `graph_n` steps starting from state buffer
+    // 0 or 1 (the launches alternate buffers, so the start decides every launch)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_n = 0;
+    void drop_graphs() {
+        for (auto& g : graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        graph_n = 0;
+    }
+    ~pflb_ctx() { drop_graphs(); }
 };
 
 namespace {
@@ -327,6 +340,7 @@ int pflb_bind(pflb_ctx* c, void* const* dev_ptrs, int n) {
         if (!dev_ptrs[k]) return fail(c, PFLB_ERR_PARAM, "NULL buffer pointer");
         if (!aligned(dev_ptrs[k])) return fail(c, PFLB_ERR_ALIGN, "buffer not 256-byte aligned");
     }
+    c->drop_graphs();         // captured launches name the previous buffers
     for (int k = 0; k < n; ++k) c->buf[k] = dev_ptrs[k];
     c->bound = true;
     c->cur = 0;
@@ -463,6 +477,50 @@ int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
         c->cur ^= 1;
         c->steps += 1;
     }
+    return PFLB_OK;
+}
+
+int pflb_step_graph(pflb_ctx* c, int nsteps, void* stream) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (nsteps < 1) return fail(c, PFLB_ERR_PARAM, "nsteps < 1");
+    if (!stream) return fail(c, PFLB_ERR_PARAM, "pflb_step_graph needs a stream other than the null stream");
+    hipStream_t st = (hipStream_t)stream;
+    if (nsteps != c->graph_n) c->drop_graphs();
+    hipGraphExec_t& ex = c->graph[c->cur];
+    if (!ex) {
+        // capture the launches pflb_step would enqueue, from the current buffer
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+        Launch a = c->L;
+        a.stream = st;
+        int cur = c->cur;
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < nsteps && le == hipSuccess; ++k) {
+            void* src = c->buf[cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1];
+            void* dst = c->buf[cur == 0 ? PFLB_BUF_STATE1 : PFLB_BUF_STATE0];
+            le = launch_step(a, src, dst);
+            cur ^= 1;
+        }
+        e = hipStreamEndCapture(st, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(c, le, "step launch under capture");
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            ex = nullptr;
+            return hip_fail(c, e, "graph instantiation");
+        }
+        c->graph_n = nsteps;
+    }
+    hipError_t e = hipGraphLaunch(ex, st);
+    if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    c->cur ^= (nsteps & 1);
+    c->steps += nsteps;
     return PFLB_OK;
 }
 

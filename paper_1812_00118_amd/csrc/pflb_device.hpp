@@ -55,11 +55,6 @@ struct LatD3Q19 {
                       : (i <= 6 ? (float)(1.0 / 18.0 - (double)(1.0f / 18.0f))
                                 : (float)(1.0 / 36.0 - (double)(1.0f / 36.0f)));
     }
-    // FP16S reference coefficients: dyadic r_i ~ 4 w_i with sum_i r_i = 4 exactly
-    __host__ __device__ static constexpr float r(int i) {
-        return i == 0 ? 1398112.0f / 1048576.0f
-                      : (i <= 6 ? 233016.0f / 1048576.0f : 116508.0f / 1048576.0f);
-    }
 };
 
 struct LatD2Q9 {  // user (x, y) -> internal (x, z)
@@ -83,10 +78,6 @@ struct LatD2Q9 {  // user (x, y) -> internal (x, z)
                       : (i <= 4 ? (float)(1.0 / 9.0 - (double)(1.0f / 9.0f))
                                 : (float)(1.0 / 36.0 - (double)(1.0f / 36.0f)));
     }
-    __host__ __device__ static constexpr float r(int i) {
-        return i == 0 ? 1864144.0f / 1048576.0f
-                      : (i <= 4 ? 466032.0f / 1048576.0f : 116508.0f / 1048576.0f);
-    }
 };
 
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
@@ -101,12 +92,6 @@ __host__ __device__ constexpr float kappa() {
     return (float)(1.0 - s);
 }
 
-template <class L>
-__host__ __device__ constexpr bool dyadic_refs_sum_to_four() {
-    double s = 0.0;
-    for (int i = 0; i < L::Q; ++i) s += (double)L::r(i);
-    return s == 4.0;
-}
 
 // ---------------------------------------------------------------------------
 // geometry and model constants passed by value to every kernel
@@ -167,15 +152,22 @@ struct StepBatch {
 };
 
 // ---------------------------------------------------------------------------
-// storage codecs.  One state buffer holds both sets, interleaved per population so
-// that one load brings h_i and g_i of a slot:
-//   FP32 : [Q][S] float2 (h_i, g_i)
-//   FP16S: [S] float2 (R_h, R_g), then [Q][S] half2 (dev_h_i, dev_g_i).  Slot (s, i)
-//          decodes to r_i R(s) + dev_i(s)/scale, with the dyadic r_i ~ 4 w_i of the
-//          lattice (sum r_i = 4): R ~ phi/4 is the site's zeroth-order equilibrium
-//          level and the fp16 words hold the deviations from it.  The rest word dev_0
-//          carries what the float32 R cannot: the site's stored values sum to the
-//          intended total to a few 1e-11, so sum(phi) is conserved.
+// storage codecs.  One state buffer holds both sets.
+//   FP32 : [Q][S] float2 (h_i, g_i): one load brings h_i and g_i of a slot.
+//   FP16S: [S] float2 (h_0, g_0), the rest populations in float32;
+//          [S] uint4, the site's moments word: its pre-collision moments of the step
+//          that wrote the buffer, rounded to fp16, as half2 pairs (Phi, Psi),
+//          (jh_x, Jg_x), (jh_y, Jg_y), (jh_z, Jg_z) with Phi = sum h, jh = sum c h,
+//          Psi = sum g, Jg = sum c g;
+//          [Q-1][S] half2 (dev_h, dev_g) for the moving directions i = 1..Q-1.
+//   A moving population is stored as an fp16 deviation from a reference that its
+//   reader can form on its own: the first-order equilibrium w_i (Phi + 3 c_i . jh) (and
+//   w_i (Psi + 3 c_i . Jg) for g) of the reading site's moments.  The writer, which
+//   collides the neighbours of the reading site in the same workgroup, takes the same
+//   moments from the workgroup's LDS planes, so the reader gathers deviations only (no
+//   per-direction reference words), and the deviation is second order in the lattice
+//   spacing.  The rest population h_0 is the float32 complement that makes the site's
+//   decoded outgoing values sum to its h total.
 // ---------------------------------------------------------------------------
 struct StoreF32 {
     static constexpr bool HALF = false;
@@ -185,45 +177,28 @@ struct StoreF32 {
 struct StoreF16S {
     static constexpr bool HALF = true;
     __host__ __device__ static constexpr size_t bytes_per_site(int q) {
-        return 8 + (size_t)q * 4;
+        return 8 + 16 + (size_t)(q - 1) * 4;
     }
+    // byte offsets of the regions in a buffer of stride S
+    __host__ __device__ static constexpr size_t mom_off(uint32_t S) { return (size_t)S * 8; }
+    __host__ __device__ static constexpr size_t dev_off(uint32_t S) { return (size_t)S * 24; }
 };
 
-// Encode pre-collision values of a slot-site without the complement (state upload).
-template <class L, class ST>
-__device__ __forceinline__ void encode_site(char* __restrict__ b, uint32_t site, uint32_t S,
-                                            const float (&h)[L::Q], const float (&g)[L::Q],
-                                            const Codec& cd) {
-    if constexpr (!ST::HALF) {
-        float2* o = reinterpret_cast<float2*>(b);
-        static_for<0, L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            o[(size_t)i * S + site] = make_float2(h[i], g[i]);
-        });
-    } else {
-        __half2* dev = reinterpret_cast<__half2*>(b + (size_t)S * 8);
-        const float Rh = h[0] / L::r(0), Rg = g[0] / L::r(0);
-        reinterpret_cast<float2*>(b)[site] = make_float2(Rh, Rg);
-        static_for<0, L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            dev[(size_t)i * S + site] =
-                __halves2half2(__float2half_rn((h[i] - L::r(i) * Rh) * cd.sh),
-                               __float2half_rn((g[i] - L::r(i) * Rg) * cd.sg));
-        });
-    }
+// Encode pre-collision values of a slot-site (FP32 state upload).
+template <class L>
+__device__ __forceinline__ void encode_site_f32(char* __restrict__ b, uint32_t site, uint32_t S,
+                                                const float (&h)[L::Q], const float (&g)[L::Q]) {
+    float2* o = reinterpret_cast<float2*>(b);
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        o[(size_t)i * S + site] = make_float2(h[i], g[i]);
+    });
 }
-
-// Streaming writer of one site's post-collision pairs.  Pairs arrive rest population
-// first.  FP16S: the moving populations are rounded as deviations from r_i f_0 / r_0,
-// and R is written last as the complement (total - sum of decoded deviations) / 4 (an
-// exact scaling), so that the decoded values of the site sum to the total up to one
-// float32 rounding; for h this keeps sum(phi) conserved as with float32 storage.
-template <class L, class ST>
-struct SiteWriter;
 
 // Streaming stores: the written state is read back only by the next launch, after far
 // more data than the caches hold has passed, so the stores bypass cache allocation.
 typedef float nt_float2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_uint4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void store_nt(char* p, float a, float b) {
     nt_float2 v = {a, b};
@@ -234,68 +209,83 @@ __device__ __forceinline__ void store_nt(char* p, __half2 v) {
     __builtin_nontemporal_store(*reinterpret_cast<uint32_t*>(&v), reinterpret_cast<uint32_t*>(p));
 }
 
-template <class L>
-struct SiteWriter<L, StoreF32> {
-    char* __restrict__ b;
-    uint32_t off8;                 // site * 8
-    uint32_t S;
-    __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site, uint32_t S_,
-                                          const Codec&, float, float)
-        : b(b_), off8(site * 8u), S(S_) {}
-    template <int I>
-    __device__ __forceinline__ void put(float h, float g) {
-        char* base = b + (size_t)I * ((size_t)S * 8);
-        store_nt(base + off8, h, g);
-    }
-    __device__ __forceinline__ void finish() {}
-    __device__ __forceinline__ void shift_h_total(double) {}
+__device__ __forceinline__ void store_nt(char* p, uint4 v) {
+    nt_uint4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_uint4*>(p));
+}
+
+// ----- FP16S moments word and references -----
+struct MomF {
+    float Phi, Psi, jx, jy, jz, Jx, Jy, Jz;
 };
 
-template <class L>
-struct SiteWriter<L, StoreF16S> {
-    char* __restrict__ b;
-    uint32_t site, S;
-    const Codec& cd;
-    double th;                     // h total (the site's phi)
-    double dh;                     // sum of the decoded h deviations (exact dyadic terms)
-    float tg, dg;                  // g total and decoded g deviations: no total of the g
-                                   // set is conserved exactly, so float32 sums suffice
-    float Rh0, Rg0;
-    __device__ __forceinline__ SiteWriter(char* __restrict__ b_, uint32_t site_, uint32_t S_,
-                                          const Codec& cd_, float th_, float th_lo_)
-        : b(b_), site(site_), S(S_), cd(cd_), th((double)th_ + (double)th_lo_), dh(0.0),
-          tg(0.f), dg(0.f), Rh0(0.f), Rg0(0.f) {}
-    __device__ __forceinline__ char* dev_addr(int i) const {
-        return b + (size_t)S * 8 + (size_t)i * ((size_t)S * 4) + site * 4u;
-    }
-    template <int I>
-    __device__ __forceinline__ void put(float h, float g) {
-        static_assert(dyadic_refs_sum_to_four<L>(), "reference coefficients must sum to 4");
-        tg += g;
-        if constexpr (I == 0) {
-            Rh0 = h * (1.0f / L::r(0));
-            Rg0 = g * (1.0f / L::r(0));
-        } else {
-            const __half qh = __float2half_rn((h - L::r(I) * Rh0) * cd.sh);
-            const __half qg = __float2half_rn((g - L::r(I) * Rg0) * cd.sg);
-            dh += (double)(__half2float(qh) * cd.ish);
-            dg = fmaf(__half2float(qg), cd.isg, dg);
-            store_nt(dev_addr(I), __halves2half2(qh, qg));
-        }
-    }
-    // a moving wall changed an h value by d after the total was taken: the stored values
-    // must sum to the changed total
-    __device__ __forceinline__ void shift_h_total(double d) { th += d; }
-    // R from the float64 complement, and the rest word from what R's rounding left over
-    __device__ __forceinline__ void finish() {
-        const float Rh = (float)(0.25 * (th - dh));
-        const double resh = (th - dh) - 4.0 * (double)Rh;
-        const float cg = tg - dg;
-        const float Rg = 0.25f * cg;
-        const float resg = fmaf(-4.0f, Rg, cg);
-        store_nt(b + site * 8u, Rh, Rg);
-        store_nt(dev_addr(0), __halves2half2(__float2half_rn((float)resh * cd.sh),
-                                             __float2half_rn(resg * cd.sg)));
+__device__ __forceinline__ uint32_t pack_h2(float a, float b) {
+    __half2 v = __halves2half2(__float2half_rn(a), __float2half_rn(b));
+    return *reinterpret_cast<uint32_t*>(&v);
+}
+
+__device__ __forceinline__ float2 unpack_h2(uint32_t w) {
+    return __half22float2(*reinterpret_cast<const __half2*>(&w));
+}
+
+__device__ __forceinline__ uint4 pack_mom(float Phi, float Psi, float jx, float jy, float jz,
+                                          float Jx, float Jy, float Jz) {
+    return make_uint4(pack_h2(Phi, Psi), pack_h2(jx, Jx), pack_h2(jy, Jy), pack_h2(jz, Jz));
+}
+
+__device__ __forceinline__ MomF unpack_mom(const uint4& w) {
+    MomF m;
+    const float2 a = unpack_h2(w.x), bx = unpack_h2(w.y), by = unpack_h2(w.z),
+                 bz = unpack_h2(w.w);
+    m.Phi = a.x; m.Psi = a.y;
+    m.jx = bx.x; m.Jx = bx.y;
+    m.jy = by.x; m.Jy = by.y;
+    m.jz = bz.x; m.Jz = bz.y;
+    return m;
+}
+
+// c_I . v as a fixed sum of the components (the same float operations wherever a
+// reference is formed, so that writer and reader agree bit for bit)
+template <class L, int I>
+__device__ __forceinline__ float cdot(float vx, float vy, float vz) {
+    constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+    float s = 0.f;
+    bool first = true;
+    auto add = [&](int e, float v) {
+        if (e == 0) return;
+        const float t = e > 0 ? v : -v;
+        s = first ? t : s + t;
+        first = false;
+    };
+    add(ex, vx);
+    add(ey, vy);
+    add(ez, vz);
+    return s;
+}
+
+// FP16S references of the population I (>= 1) a site with moments m reads:
+// w_I (Phi + 3 c_I . jh) and w_I (Psi + 3 c_I . Jg)
+template <class L, int I>
+__device__ __forceinline__ void ref_of(const MomF& m, float& rh, float& rg) {
+    constexpr float w = L::w(I);
+    rh = w * fmaf(3.0f, cdot<L, I>(m.jx, m.jy, m.jz), m.Phi);
+    rg = w * fmaf(3.0f, cdot<L, I>(m.Jx, m.Jy, m.Jz), m.Psi);
+}
+
+// moments of a gathered site, accumulated as its populations are decoded
+struct MomAcc {
+    float S = 0.f;                     // sum of the moving h, in index order
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+    template <class L, int I>
+    __device__ __forceinline__ void add_h(float h) {
+        constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+        S = I == 1 ? h : S + h;
+        if constexpr (ex > 0) jx += h;
+        if constexpr (ex < 0) jx -= h;
+        if constexpr (ey > 0) jy += h;
+        if constexpr (ey < 0) jy -= h;
+        if constexpr (ez > 0) jz += h;
+        if constexpr (ez < 0) jz -= h;
     }
 };
 
@@ -477,93 +467,31 @@ __device__ __forceinline__ const char* slot_addr(const char* __restrict__ base0,
     }
 }
 
-// Load slot pair (h, g) of direction I.
-template <class L, class ST, int I, int WALLS>
-__device__ __forceinline__ float2 load_pair(const char* __restrict__ b, uint32_t S,
-                                            uint32_t slot_site, bool flip, const Codec& cd) {
-    if constexpr (!ST::HALF) {
-        uint32_t off;
-        const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
-        return *reinterpret_cast<const float2*>(base + off);
-    } else {
-        const float2 R = *reinterpret_cast<const float2*>(b + slot_site * 8u);
-        uint32_t off;
-        // deviation arrays start after the R pairs, one per population
-        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
-        const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
-        return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
-    }
+// FP32 storage: slot pair (h, g), or h alone, of direction I.
+template <class L, int I, int WALLS>
+__device__ __forceinline__ float2 load_pair32(const char* __restrict__ b, uint32_t S,
+                                              uint32_t slot_site, bool flip) {
+    uint32_t off;
+    const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
+    return *reinterpret_cast<const float2*>(base + off);
 }
 
-// Load h of slot of direction I.
-template <class L, class ST, int I, int WALLS>
-__device__ __forceinline__ float load_h(const char* __restrict__ b, uint32_t S,
-                                        uint32_t slot_site, bool flip, const Codec& cd) {
-    if constexpr (!ST::HALF) {
-        uint32_t off;
-        const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
-        return *reinterpret_cast<const float*>(base + off);
-    } else {
-        const float R = *reinterpret_cast<const float*>(b + slot_site * 8u);
-        uint32_t off;
-        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
-        return fmaf(__half2float(*reinterpret_cast<const __half*>(base + off)), cd.ish,
-                    L::r(I) * R);
-    }
+template <class L, int I, int WALLS>
+__device__ __forceinline__ float load_h32(const char* __restrict__ b, uint32_t S,
+                                          uint32_t slot_site, bool flip) {
+    uint32_t off;
+    const char* base = slot_addr<L, I, WALLS, 8>(b, S, slot_site, flip, off);
+    return *reinterpret_cast<const float*>(base + off);
 }
 
-// phi of a gathered site, summed in float64 from the stored values and used as hi + lo
-// floats.  The BGK update relaxes h towards phi w_i and the site keeps the mass phi: a
-// float32-rounded phi would add that rounding error to the site at every step (a random
-// walk of the phase field).  With FP32 storage
-// the terms are the (exact) float32 populations.  With FP16S storage they are
-// r_i R + dev_i / scale taken from the stored words, where r_i R is exact in float64:
-// the float32-rounded decoded populations would make phi, which becomes the total the
-// next writer stores, inherit rounding errors that are identical over uniform regions
-// and so drift sum(phi) systematically.
+// phi of a gathered site with FP32 storage, summed in float64 from the stored values
+// and used as hi + lo floats.  The BGK update relaxes h towards phi w_i and the site
+// keeps the mass phi: a float32-rounded phi would add that rounding error to the site
+// at every step (a random walk of the phase field).
 struct PhiAcc {
-    double r = 0.0;   // FP32: sum of populations; FP16S: sum of r_i R
-    double d = 0.0;   // FP16S: sum of dev_i / scale (exact dyadic terms)
-    __device__ __forceinline__ double value() const { return r + d; }
+    double r = 0.0;
+    __device__ __forceinline__ double value() const { return r; }
 };
-
-template <class L, class ST, int I, int WALLS>
-__device__ __forceinline__ float2 load_pair_acc(const char* __restrict__ b, uint32_t S,
-                                                uint32_t slot_site, bool flip, const Codec& cd,
-                                                PhiAcc& acc) {
-    if constexpr (!ST::HALF) {
-        const float2 v = load_pair<L, ST, I, WALLS>(b, S, slot_site, flip, cd);
-        acc.r += (double)v.x;
-        return v;
-    } else {
-        const float2 R = *reinterpret_cast<const float2*>(b + slot_site * 8u);
-        acc.r = fma((double)R.x, (double)L::r(I), acc.r);
-        uint32_t off;
-        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
-        const float2 df = __half22float2(*reinterpret_cast<const __half2*>(base + off));
-        acc.d += (double)(df.x * cd.ish);
-        return make_float2(fmaf(df.x, cd.ish, L::r(I) * R.x), fmaf(df.y, cd.isg, L::r(I) * R.y));
-    }
-}
-
-template <class L, class ST, int I, int WALLS>
-__device__ __forceinline__ float load_h_acc(const char* __restrict__ b, uint32_t S,
-                                            uint32_t slot_site, bool flip, const Codec& cd,
-                                            PhiAcc& acc) {
-    if constexpr (!ST::HALF) {
-        const float v = load_h<L, ST, I, WALLS>(b, S, slot_site, flip, cd);
-        acc.r += (double)v;
-        return v;
-    } else {
-        const float R = *reinterpret_cast<const float*>(b + slot_site * 8u);
-        acc.r = fma((double)R, (double)L::r(I), acc.r);
-        uint32_t off;
-        const char* base = slot_addr<L, I, WALLS, 4>(b + (size_t)S * 8, S, slot_site, flip, off);
-        const float d = __half2float(*reinterpret_cast<const __half*>(base + off)) * cd.ish;
-        acc.d += (double)d;
-        return d + L::r(I) * R;
-    }
-}
 
 // Raw moments of the hydrodynamic set up to second order, sum g, sum c g and sum c c g:
 // all that the filtered collision uses of the pre-collision g (Eqs. 10-12: g* depends on
@@ -602,22 +530,66 @@ __device__ __forceinline__ GMom g_moments(const float (&g)[L::Q]) {
     return m;
 }
 
+// FP16S: decode the populations site (c, r) reads, with its own rest word and moments
+// word, calling f(I, h_I, g_I) in index order.  Returns phi = h_0 + (sum of the moving h
+// in index order); acc holds that sum and the first moment of h.  The float sums are the
+// ones a writer's complement mirrors: over a uniform region the reader's sum and the
+// writer's take the same values in the same order, and h_0 = T - S with S within a
+// factor two of T is exact (Sterbenz), so phi returns to T exactly there.
+template <class L, int WALLS, class F>
+__device__ __forceinline__ float gather16(const char* __restrict__ b, const Geom& G,
+                                          const Col& c, const ZRow& r, const Codec& cd,
+                                          MomAcc& acc, F&& f) {
+    const uint32_t site = c.base + r.base;
+    const float2 rest = reinterpret_cast<const float2*>(b)[site];
+    const MomF m =
+        unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[site]);
+    f(std::integral_constant<int, 0>{}, rest.x, rest.y);
+    // deviation of population pop >= 1 at dev_off + (pop - 1) S 4
+    const char* base0 = b + StoreF16S::dev_off(G.S) - (size_t)G.S * 4;
+    static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        uint32_t s;
+        bool flip;
+        upstream<L, i, WALLS>(c, r, s, flip);
+        uint32_t off;
+        const char* base = slot_addr<L, i, WALLS, 4>(base0, G.S, s, flip, off);
+        const float2 q = __half22float2(*reinterpret_cast<const __half2*>(base + off));
+        float rh, rg;
+        ref_of<L, i>(m, rh, rg);
+        const float hv = fmaf(q.x, cd.ish, rh);
+        const float gv = fmaf(q.y, cd.isg, rg);
+        acc.template add_h<L, i>(hv);
+        f(I, hv, gv);
+    });
+    return rest.x + acc.S;
+}
+
 // Gather the Q pre-collision populations of both sets of one site and its phi.
 template <class L, class ST, int WALLS>
 __device__ __forceinline__ double pull_site(const char* __restrict__ b, const Geom& G,
                                             const Col& c, const ZRow& r, const Codec& cd,
                                             float (&h)[L::Q], float (&g)[L::Q]) {
-    PhiAcc acc;
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        uint32_t s;
-        bool flip;
-        upstream<L, i, WALLS>(c, r, s, flip);
-        const float2 v = load_pair_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
-        h[i] = v.x;
-        g[i] = v.y;
-    });
-    return acc.value();
+    if constexpr (ST::HALF) {
+        MomAcc acc;
+        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float gv) {
+            h[decltype(I)::value] = hv;
+            g[decltype(I)::value] = gv;
+        });
+    } else {
+        PhiAcc acc;
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            uint32_t s;
+            bool flip;
+            upstream<L, i, WALLS>(c, r, s, flip);
+            const float2 v = load_pair32<L, i, WALLS>(b, G.S, s, flip);
+            acc.r += (double)v.x;
+            h[i] = v.x;
+            g[i] = v.y;
+        });
+        return acc.value();
+    }
 }
 
 // Gather only the h populations of one site and its phi.
@@ -625,23 +597,32 @@ template <class L, class ST, int WALLS>
 __device__ __forceinline__ double pull_site_h(const char* __restrict__ b, const Geom& G,
                                               const Col& c, const ZRow& r, const Codec& cd,
                                               float (&h)[L::Q]) {
-    PhiAcc acc;
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        uint32_t s;
-        bool flip;
-        upstream<L, i, WALLS>(c, r, s, flip);
-        h[i] = load_h_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
-    });
-    return acc.value();
+    if constexpr (ST::HALF) {
+        MomAcc acc;
+        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float) {
+            h[decltype(I)::value] = hv;
+        });
+    } else {
+        PhiAcc acc;
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            uint32_t s;
+            bool flip;
+            upstream<L, i, WALLS>(c, r, s, flip);
+            h[i] = load_h32<L, i, WALLS>(b, G.S, s, flip);
+            acc.r += (double)h[i];
+        });
+        return acc.value();
+    }
 }
 
 // Gather the h populations of one site, the raw moments of its g populations and its
-// phi: the form the fused step keeps a site in between the gather and the collision.
-template <class L, class ST, int WALLS>
+// phi: the form the fused step keeps a site in between the gather and the collision
+// (FP32 storage).
+template <class L, int WALLS>
 __device__ __forceinline__ double pull_site_m(const char* __restrict__ b, const Geom& G,
-                                              const Col& c, const ZRow& r, const Codec& cd,
-                                              float (&h)[L::Q], GMom& gm) {
+                                              const Col& c, const ZRow& r, float (&h)[L::Q],
+                                              GMom& gm) {
     PhiAcc acc;
     gm = GMom{};
     static_for<0, L::Q>([&](auto I) {
@@ -649,12 +630,129 @@ __device__ __forceinline__ double pull_site_m(const char* __restrict__ b, const 
         uint32_t s;
         bool flip;
         upstream<L, i, WALLS>(c, r, s, flip);
-        const float2 v = load_pair_acc<L, ST, i, WALLS>(b, G.S, s, flip, cd, acc);
+        const float2 v = load_pair32<L, i, WALLS>(b, G.S, s, flip);
+        acc.r += (double)v.x;
         h[i] = v.x;
         add_moment<L, i>(gm, v.y);
     });
     return acc.value();
 }
+
+// The same for FP16S storage, which also returns the site's moments (phi, sum c h,
+// sum g, sum c g) as the fp16 moments word the writers of its populations use.
+template <class L, int WALLS>
+__device__ __forceinline__ float pull_site_m16(const char* __restrict__ b, const Geom& G,
+                                               const Col& c, const ZRow& r, const Codec& cd,
+                                               float (&h)[L::Q], GMom& gm, uint4& mom) {
+    MomAcc acc;
+    gm = GMom{};
+    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float gv) {
+        h[decltype(I)::value] = hv;
+        add_moment<L, decltype(I)::value>(gm, gv);
+    });
+    mom = pack_mom(phi, gm.s, acc.jx, acc.jy, acc.jz, gm.jx, gm.jy, gm.jz);
+    return phi;
+}
+
+// FP16S: phi and the moments word of a site whose populations are not kept (the halo
+// ring and the planes a workgroup only gathers for its neighbours' references).
+template <class L, int WALLS>
+__device__ __forceinline__ float pull_site_mom16(const char* __restrict__ b, const Geom& G,
+                                                 const Col& c, const ZRow& r, const Codec& cd,
+                                                 uint4& mom) {
+    MomAcc acc;
+    float Sg = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
+    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float, float gv) {
+        constexpr int i = decltype(I)::value;
+        Sg += gv;
+        if constexpr (L::cx(i) > 0) Jx += gv;
+        if constexpr (L::cx(i) < 0) Jx -= gv;
+        if constexpr (L::cy(i) > 0) Jy += gv;
+        if constexpr (L::cy(i) < 0) Jy -= gv;
+        if constexpr (L::cz(i) > 0) Jz += gv;
+        if constexpr (L::cz(i) < 0) Jz -= gv;
+    });
+    mom = pack_mom(phi, Sg, acc.jx, acc.jy, acc.jz, Jx, Jy, Jz);
+    return phi;
+}
+
+// True if site + c_I lies beyond a wall face, for a site with wall bits `solid`: the
+// population it sends in direction I then comes back to itself as opp(I).
+template <class L, int I, int WALLS>
+__device__ __forceinline__ bool dest_beyond(uint32_t solid) {
+    // the upstream site of opp(I) is site + c_I
+    using U = Up<L, opp(I), WALLS>;
+    bool bb = false;
+    if constexpr (U::test_xy) bb = bb || (solid & U::need_xy) != 0u;
+    if constexpr (U::test_z) bb = bb || (solid & U::need_z) != 0u;
+    return bb;
+}
+
+// Streaming writer of one site's post-collision pairs (pairs arrive rest population
+// first), FP32 storage.
+template <class L>
+struct SiteWriter32 {
+    char* __restrict__ b;
+    uint32_t off8;                 // site * 8
+    uint32_t S;
+    template <int I>
+    __device__ __forceinline__ void put(float h, float g) {
+        char* base = b + (size_t)I * ((size_t)S * 8);
+        store_nt(base + off8, h, g);
+    }
+    __device__ __forceinline__ void finish() {}
+    __device__ __forceinline__ void shift_h_total(double) {}
+};
+
+// FP16S writer.  A moving population is stored as the fp16 deviation from the reference
+// of its reader, formed from the reader's moments in the workgroup's LDS planes
+// (mom(DX, DY, DZ) gives the moments word of site + (DX, DY, DZ)); a population sent
+// into a wall face is read back by the site itself as opp(I), with the site's own
+// moments and the reference of opp(I).  h_0 is written last as the complement T - (sum
+// of the decoded moving values, in index order), so that the decoded values the site
+// sends out sum to its h total; the site's moments word (the same fp16 values the
+// writers of its incoming populations used) is written beside it.
+template <class L, int WALLS, class MomAt>
+struct SiteWriter16 {
+    char* __restrict__ b;
+    uint32_t site, S;
+    const Codec& cd;
+    MomAt mom;
+    uint32_t solid;
+    float T;                       // h total of the site
+    float Sout = 0.f, g0 = 0.f;
+    float D = 0.f;                 // moving-wall changes of the total (0 where they cancel)
+    template <int I>
+    __device__ __forceinline__ void put(float h, float g) {
+        if constexpr (I == 0) {
+            g0 = g;
+        } else {
+            constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
+            const bool back = dest_beyond<L, I, WALLS>(solid);
+            const MomF m = unpack_mom(back ? mom(0, 0, 0) : mom(ex, ey, ez));
+            // reference of population I at the reader, or of opp(I) (c = -c_I) at the site
+            constexpr float w = L::w(I);
+            const float sgn = back ? -3.0f : 3.0f;
+            const float rh = w * fmaf(sgn, cdot<L, I>(m.jx, m.jy, m.jz), m.Phi);
+            const float rg = w * fmaf(sgn, cdot<L, I>(m.Jx, m.Jy, m.Jz), m.Psi);
+            const __half qh = __float2half_rn((h - rh) * cd.sh);
+            const __half qg = __float2half_rn((g - rg) * cd.sg);
+            const float dec = fmaf(__half2float(qh), cd.ish, rh);
+            Sout = I == 1 ? dec : Sout + dec;
+            store_nt(b + StoreF16S::dev_off(S) + (size_t)(I - 1) * ((size_t)S * 4) + site * 4u,
+                     __halves2half2(qh, qg));
+        }
+    }
+    // a moving wall changed an h value by d after the total was taken: the stored values
+    // must sum to the changed total.  The changes are summed apart and added last: the
+    // opposite changes of a tangential pair cancel exactly in D, which leaves T - Sout
+    // (exact when Sout is within a factor two of T) untouched
+    __device__ __forceinline__ void shift_h_total(double d) { D += (float)d; }
+    __device__ __forceinline__ void finish() {
+        store_nt(b + (size_t)site * 8u, (T - Sout) + D, g0);
+        store_nt(b + StoreF16S::mom_off(S) + (size_t)site * 16u, mom(0, 0, 0));
+    }
+};
 
 // float64 phi as hi + lo floats
 __device__ __forceinline__ float split_hi_lo(double s, float& lo) {

@@ -74,7 +74,10 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     constexpr int NR = L::USES_Y ? 2 * HX + 2 * TY : 2;
     static_assert(L::USES_Y || TY == 1, "D2Q9 tiles are one row high");
     static_assert(NR <= TX * TY, "ring larger than the workgroup");
+    constexpr bool HALF = ST::HALF;
     __shared__ float sphi[4][HY][HX];
+    // FP16S: the moments words of the same positions (the references of the writers)
+    __shared__ uint4 smom[HALF ? 4 : 1][HALF ? HY : 1][HALF ? HX : 1];
 
     const int t = xcd_tile(blockIdx.x, nblk);
     const int bx = t % ntx;
@@ -113,23 +116,42 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         }
         return v;
     };
-    auto ring_phi = [&](const ZRow& r, int zr) {
-        float f[Q];
-        return wet((float)pull_site_h<L, ST, WALLS>(src, G, ring, r, cd, f), rrx, rry, zr);
+    // phi (and, FP16S, the moments word) of a site kept only for the neighbours: a ring
+    // site, or an own site of a plane this workgroup does not collide
+    auto side_site = [&](const Col& cc, const ZRow& r, int zr, int py, int px, int vx, int vy) {
+        if constexpr (HALF) {
+            uint4 mw;
+            const float ph = pull_site_mom16<L, WALLS>(src, G, cc, r, cd, mw);
+            sphi[zr & 3][py][px] = wet(ph, vx, vy, zr);
+            smom[zr & 3][py][px] = mw;
+        } else {
+            float f[Q];
+            sphi[zr & 3][py][px] = wet((float)pull_site_h<L, ST, WALLS>(src, G, cc, r, cd, f), vx, vy, zr);
+        }
+    };
+    // an own site that will be collided: its h values and g moments stay in registers
+    auto own_site = [&](const ZRow& r, int zr, float (&hv)[Q], GMom& gv, float& lo) {
+        if constexpr (HALF) {
+            uint4 mw;
+            const float ph = pull_site_m16<L, WALLS>(src, G, own, r, cd, hv, gv, mw);
+            lo = 0.0f;
+            sphi[zr & 3][ty + OY][tx + 1] = wet(ph, x, y, zr);
+            smom[zr & 3][ty + OY][tx + 1] = mw;
+        } else {
+            sphi[zr & 3][ty + OY][tx + 1] =
+                wet(split_hi_lo(pull_site_m<L, WALLS>(src, G, own, r, hv, gv), lo), x, y, zr);
+        }
     };
 
     float hA[Q], loA, hB[Q], loB;
     GMom gA, gB;
-    {   // plane z0 - 1 (phi only) and plane z0
+    {   // plane z0 - 1 (for the neighbours only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
-        float f[Q];
-        sphi[(z0 - 1) & 3][ty + OY][tx + 1] =
-            wet((float)pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f), x, y, z0 - 1);
-        if (has_ring) sphi[(z0 - 1) & 3][rhy][rhx] = ring_phi(rm, z0 - 1);
+        side_site(own, rm, z0 - 1, ty + OY, tx + 1, x, y);
+        if (has_ring) side_site(ring, rm, z0 - 1, rhy, rhx, rrx, rry);
         const ZRow r0 = make_zrow(G, z0);
-        sphi[z0 & 3][ty + OY][tx + 1] =
-            wet(split_hi_lo(pull_site_m<L, ST, WALLS>(src, G, own, r0, cd, hA, gA), loA), x, y, z0);
-        if (has_ring) sphi[z0 & 3][rhy][rhx] = ring_phi(r0, z0);
+        own_site(r0, z0, hA, gA, loA);
+        if (has_ring) side_site(ring, r0, z0, rhy, rhx, rrx, rry);
     }
     // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc)
     // (h values and g moments).
@@ -140,10 +162,13 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         // reaching it ahead of other waves' collision arithmetic (measured: 1-3% faster);
         // back to normal after the barrier
         __builtin_amdgcn_s_setprio(2);
-        const double pn64 = (z + 1 < zend) ? pull_site_m<L, ST, WALLS>(src, G, own, rn, cd, hn, gn)
-                                           : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
-        sphi[(z + 1) & 3][ty + OY][tx + 1] = wet(split_hi_lo(pn64, lo_n), x, y, z + 1);
-        if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = ring_phi(rn, z + 1);
+        if (z + 1 < zend) {
+            own_site(rn, z + 1, hn, gn, lo_n);
+        } else {
+            // the plane above the chunk, for the neighbours only
+            side_site(own, rn, z + 1, ty + OY, tx + 1, x, y);
+        }
+        if (has_ring) side_site(ring, rn, z + 1, rhy, rhx, rrx, rry);
         lds_barrier();
         __builtin_amdgcn_s_setprio(0);
         if (active) {
@@ -154,16 +179,28 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                 pn[i] = sphi[(z + L::cz(i)) & 3][ty + OY + L::cy(i)][tx + 1 + L::cx(i)];
             });
             const Macro a = macros<L>(m, pn, gc);
-            SiteWriter<L, ST> out(dst, own.base + r.base, G.S, cd, a.phi, lo_c);
-            if constexpr (WALLS == WALLS_NONE || !XBC) {
-                collide_stream<L>(m, a, lo_c, hc, gc, out);
+            const uint32_t solid = own.solid | r.solid;
+            auto collide_to = [&](auto& out) {
+                if constexpr (WALLS == WALLS_NONE || !XBC) {
+                    collide_stream<L>(m, a, lo_c, hc, gc, out);
+                } else {
+                    const bool on =
+                        m.moving && __builtin_amdgcn_ballot_w64(solid != 0u) != 0ull;
+                    WallWriter<L, std::remove_reference_t<decltype(out)>> wout{
+                        out, m, solid, 6.0f * a.phi, 6.0f * a.rho, on};
+                    collide_stream<L>(m, a, lo_c, hc, gc, wout);
+                }
+            };
+            if constexpr (HALF) {
+                auto mom_at = [&](int dx, int dy, int dz) {
+                    return smom[(z + dz) & 3][ty + OY + dy][tx + 1 + dx];
+                };
+                SiteWriter16<L, WALLS, decltype(mom_at)> out{dst, own.base + r.base, G.S, cd,
+                                                             mom_at, solid, a.phi};
+                collide_to(out);
             } else {
-                const uint32_t solid = own.solid | r.solid;
-                const bool on =
-                    m.moving && __builtin_amdgcn_ballot_w64(solid != 0u) != 0ull;
-                WallWriter<L, SiteWriter<L, ST>> wout{out, m, solid, 6.0f * a.phi,
-                                                      6.0f * a.rho, on};
-                collide_stream<L>(m, a, lo_c, hc, gc, wout);
+                SiteWriter32<L> out{dst, (own.base + r.base) * 8u, G.S};
+                collide_to(out);
             }
         }
     };
@@ -299,23 +336,97 @@ __device__ __forceinline__ void set_state_site(const Geom& G, const Codec& cd, u
                                                char* __restrict__ b) {
     int x, y, z;
     site_coords(G, s, x, y, z);
-    float fh[L::Q], fg[L::Q];
+    if constexpr (!ST::HALF) {
+        float fh[L::Q], fg[L::Q];
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int j = decltype(I)::value;
+            const int xx = x + L::cx(j), yy = y + L::cy(j), zz = z + L::cz(j);
+            const bool solid = (G.wx && (xx < 0 || xx >= G.nx)) ||
+                               (G.wy && (yy < 0 || yy >= G.ny)) ||
+                               (G.wz && (zz < 0 || zz >= G.nz));
+            if (solid) {
+                fh[j] = h[(size_t)opp(j) * N + s];
+                fg[j] = g[(size_t)opp(j) * N + s];
+            } else {
+                const uint32_t t = site_of(G, map_coord(xx, G.nx, 0), map_coord(yy, G.ny, 0),
+                                           map_coord(zz, G.nz, 0));
+                fh[j] = h[(size_t)j * N + t];
+                fg[j] = g[(size_t)j * N + t];
+            }
+        });
+        encode_site_f32<L>(b, s, G.S, fh, fg);
+    } else {
+        // FP16S, second pass: each moving slot (s, j) as the deviation from the reference
+        // of its reader, whose moments word the first pass wrote
+        const uint4* mw = reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S));
+        static_for<1, L::Q>([&](auto I) {
+            constexpr int j = decltype(I)::value;
+            const int xx = x + L::cx(j), yy = y + L::cy(j), zz = z + L::cz(j);
+            const bool solid = (G.wx && (xx < 0 || xx >= G.nx)) ||
+                               (G.wy && (yy < 0 || yy >= G.ny)) ||
+                               (G.wz && (zz < 0 || zz >= G.nz));
+            uint32_t t;
+            float vh, vg, rh, rg;
+            if (solid) {            // read back by s itself as population opp(j)
+                t = s;
+                vh = h[(size_t)opp(j) * N + s];
+                vg = g[(size_t)opp(j) * N + s];
+                ref_of<L, opp(j)>(unpack_mom(mw[t]), rh, rg);
+            } else {
+                t = site_of(G, map_coord(xx, G.nx, 0), map_coord(yy, G.ny, 0),
+                            map_coord(zz, G.nz, 0));
+                vh = h[(size_t)j * N + t];
+                vg = g[(size_t)j * N + t];
+                ref_of<L, j>(unpack_mom(mw[t]), rh, rg);
+            }
+            reinterpret_cast<__half2*>(b + StoreF16S::dev_off(G.S))[(size_t)(j - 1) * G.S + s] =
+                __halves2half2(__float2half_rn((vh - rh) * cd.sh), __float2half_rn((vg - rg) * cd.sg));
+        });
+    }
+}
+
+// FP16S, first pass of a state upload: the rest populations and the moments word of
+// site s from its pre-collision populations (the same sums a gathered site forms)
+template <class L>
+__device__ __forceinline__ void set_mom_site(const Geom& G, uint32_t N, uint32_t s,
+                                             const float* __restrict__ h,
+                                             const float* __restrict__ g,
+                                             char* __restrict__ b) {
+    MomAcc acc;
+    float Sg = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
     static_for<0, L::Q>([&](auto I) {
-        constexpr int j = decltype(I)::value;
-        const int xx = x + L::cx(j), yy = y + L::cy(j), zz = z + L::cz(j);
-        const bool solid = (G.wx && (xx < 0 || xx >= G.nx)) || (G.wy && (yy < 0 || yy >= G.ny)) ||
-                           (G.wz && (zz < 0 || zz >= G.nz));
-        if (solid) {
-            fh[j] = h[(size_t)opp(j) * N + s];
-            fg[j] = g[(size_t)opp(j) * N + s];
-        } else {
-            const uint32_t t = site_of(G, map_coord(xx, G.nx, 0), map_coord(yy, G.ny, 0),
-                                       map_coord(zz, G.nz, 0));
-            fh[j] = h[(size_t)j * N + t];
-            fg[j] = g[(size_t)j * N + t];
-        }
+        constexpr int i = decltype(I)::value;
+        const float hv = h[(size_t)i * N + s], gv = g[(size_t)i * N + s];
+        if constexpr (i > 0) acc.template add_h<L, i>(hv);
+        Sg += gv;
+        if constexpr (L::cx(i) > 0) Jx += gv;
+        if constexpr (L::cx(i) < 0) Jx -= gv;
+        if constexpr (L::cy(i) > 0) Jy += gv;
+        if constexpr (L::cy(i) < 0) Jy -= gv;
+        if constexpr (L::cz(i) > 0) Jz += gv;
+        if constexpr (L::cz(i) < 0) Jz -= gv;
     });
-    encode_site<L, ST>(b, s, G.S, fh, fg, cd);
+    const float h0 = h[s];
+    reinterpret_cast<float2*>(b)[s] = make_float2(h0, g[s]);
+    reinterpret_cast<uint4*>(b + StoreF16S::mom_off(G.S))[s] =
+        pack_mom(h0 + acc.S, Sg, acc.jx, acc.jy, acc.jz, Jx, Jy, Jz);
+}
+
+template <class L>
+__global__ void __launch_bounds__(256)
+k_set_mom(Geom G, uint32_t N, const float* __restrict__ h, const float* __restrict__ g,
+          char* __restrict__ b) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    set_mom_site<L>(G, N, s, h, g, b);
+}
+
+template <class L>
+__global__ void __launch_bounds__(256) k_set_mom_b(Geom G, uint32_t N, Batch bt) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= N) return;
+    const BatchEnt& e = bt.e[blockIdx.y];
+    set_mom_site<L>(G, N, s, e.work, e.work + (size_t)L::Q * N, e.state);
 }
 
 template <class L, class ST>
@@ -428,32 +539,35 @@ __global__ void __launch_bounds__(256) k_macro_b(Geom G, uint32_t N, Batch bt) {
 constexpr int MASS_BLOCKS = 1024;
 constexpr int MASS_THREADS = 256;
 
-template <class L, class ST>
-__device__ __forceinline__ double slot_sum(const char* b, uint32_t s, uint32_t S,
+template <class L, class ST, int WALLS>
+__device__ __forceinline__ double slot_sum(const Geom& G, const char* b, uint32_t s,
                                            const Codec& cd, bool& bad) {
     double acc = 0.0;
     if constexpr (!ST::HALF) {
+        // FP32: the slots of site s in storage order (each slot is gathered once)
         static_for<0, L::Q>([&](auto I) {
             const float2 v =
-                reinterpret_cast<const float2*>(b)[(size_t)decltype(I)::value * S + s];
+                reinterpret_cast<const float2*>(b)[(size_t)decltype(I)::value * G.S + s];
             bad |= !isfinite(v.x) || !isfinite(v.y);
             acc += (double)v.x;
         });
     } else {
-        const float2 R = reinterpret_cast<const float2*>(b)[s];
-        bad |= !isfinite(R.x) || !isfinite(R.y);
-        const __half2* dev = reinterpret_cast<const __half2*>(b + (size_t)S * 8);
-        static_for<0, L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const float2 d = __half22float2(dev[(size_t)i * S + s]);
-            bad |= !isfinite(d.x) || !isfinite(d.y);
-            acc += (double)L::r(i) * (double)R.x + (double)d.x * (double)cd.ish;
-        });
+        // FP16S: a slot decodes with its reader's reference, so the sum follows the
+        // gather: phi of site s as the step forms it
+        int x, y, z;
+        site_coords(G, s, x, y, z);
+        MomAcc ma;
+        const float phi = gather16<L, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, ma,
+                                             [&](auto, float hv, float gv) {
+                                                 bad |= !isfinite(hv) || !isfinite(gv);
+                                             });
+        bad |= !isfinite(phi);
+        acc = (double)phi;
     }
     return acc;
 }
 
-template <class L, class ST>
+template <class L, class ST, int WALLS>
 __global__ void __launch_bounds__(MASS_THREADS)
 k_mass_partial(Geom G, Codec cd, uint32_t N, const char* __restrict__ b,
                double* __restrict__ part, int* __restrict__ flag) {
@@ -463,7 +577,7 @@ k_mass_partial(Geom G, Codec cd, uint32_t N, const char* __restrict__ b,
     bool bad = false;
     for (uint32_t s = blockIdx.x * MASS_THREADS + threadIdx.x; s < N;
          s += MASS_BLOCKS * MASS_THREADS)
-        acc += slot_sum<L, ST>(b, s, G.S, cd, bad);
+        acc += slot_sum<L, ST, WALLS>(G, b, s, cd, bad);
     sd[threadIdx.x] = acc;
     sb[threadIdx.x] = bad ? 1 : 0;
     __syncthreads();
@@ -613,6 +727,8 @@ template <class L, class ST>
 static hipError_t reconstruct_batch_t(const Launch& a, uint32_t N, const Batch& bt, int n) {
     const dim3 grid((N + 255u) / 256u, n);
     hipLaunchKernelGGL((k_equilibrium_j_b<L>), grid, dim3(256), 0, a.stream, a.G, N, bt);
+    if constexpr (ST::HALF)
+        hipLaunchKernelGGL((k_set_mom_b<L>), grid, dim3(256), 0, a.stream, a.G, N, bt);
     hipLaunchKernelGGL((k_set_state_b<L, ST>), grid, dim3(256), 0, a.stream, a.G, N, bt);
     return hipGetLastError();
 }
@@ -629,6 +745,9 @@ hipError_t launch_reconstruct_batch(const Launch& a, uint32_t N, const Batch& bt
 template <class L, class ST>
 static hipError_t set_state_t(const Launch& a, uint32_t N, const float* h, const float* g,
                               void* b) {
+    if constexpr (ST::HALF)
+        hipLaunchKernelGGL((k_set_mom<L>), grid1(N), dim3(256), 0, a.stream, a.G, N, h, g,
+                           static_cast<char*>(b));
     hipLaunchKernelGGL((k_set_state<L, ST>), grid1(N), dim3(256), 0, a.stream, a.G, a.cd, N, h,
                        g, static_cast<char*>(b));
     return hipGetLastError();
@@ -719,8 +838,14 @@ template <class L, class ST>
 static hipError_t mass_t(const Launch& a, uint32_t N, const void* b, void* scratch) {
     double* part = static_cast<double*>(scratch);
     int* flag = reinterpret_cast<int*>(part + MASS_BLOCKS + 1);
-    hipLaunchKernelGGL((k_mass_partial<L, ST>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0,
-                       a.stream, a.G, a.cd, N, static_cast<const char*>(b), part, flag);
+    if (wallset(a.G))
+        hipLaunchKernelGGL((k_mass_partial<L, ST, WALLS_XYZ>), dim3(MASS_BLOCKS),
+                           dim3(MASS_THREADS), 0, a.stream, a.G, a.cd, N,
+                           static_cast<const char*>(b), part, flag);
+    else
+        hipLaunchKernelGGL((k_mass_partial<L, ST, WALLS_NONE>), dim3(MASS_BLOCKS),
+                           dim3(MASS_THREADS), 0, a.stream, a.G, a.cd, N,
+                           static_cast<const char*>(b), part, flag);
     hipLaunchKernelGGL(k_mass_final, dim3(1), dim3(MASS_BLOCKS), 0, a.stream, part, flag,
                        part + MASS_BLOCKS, flag + MASS_BLOCKS);
     return hipGetLastError();

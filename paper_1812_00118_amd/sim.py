@@ -169,6 +169,11 @@ class Sim:
     def step(self, n=1):
         self._check(self.L.pflb_step(self.ctx, int(n), self._stream()))
 
+    def step_graph(self, n=1):
+        """step(n) replayed from a captured HIP graph (pflb_step_graph); needs torch's
+        current stream to be a created stream, not the null stream."""
+        self._check(self.L.pflb_step_graph(self.ctx, int(n), self._stream()))
+
     @staticmethod
     def step_many(sims, n=1):
         """Advance several Sims by n steps each (pflb_step_many): one launch per step for

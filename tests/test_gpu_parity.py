@@ -131,9 +131,10 @@ def test_one_step_moving_walls(name, q, shape, bc, wall, storage):
         assert np.abs(h1 - hr).max() <= 2e-3 * np.abs(hr).max()
         assert np.abs(g1 - gr).max() <= 2e-3 * np.abs(gr).max()
         # sum(phi) changes as the oracle's does (at an edge or corner between walls moving
-        # differently the corrections do not cancel, in the method as in the oracle); the
-        # change is compared because the oracle starts from the float32-rounded decoding
-        assert abs((m1 - m0) - (O.mass(hr) - O.mass(h0d))) <= 1e-10 * abs(m0)
+        # differently the corrections do not cancel, in the method as in the oracle), to
+        # the float32 rounding of each site's complement; the change is compared because
+        # the oracle starts from the float32-rounded decoding
+        assert abs((m1 - m0) - (O.mass(hr) - O.mass(h0d))) <= 1e-8 * abs(m0)
 
 
 @pytest.mark.parametrize("q,storage", [(9, "fp32"), (19, "fp32"), (9, "fp16s")])
@@ -172,9 +173,9 @@ def test_couette_matches_oracle_and_closed_form(q, storage):
     assert np.abs(ux - uo).max() <= bar
     # FP32 rounds the corrected pair (h - c, h' + c) separately: a small systematic drift
     # in a steady state.  FP16S: the opposite corrections cancel exactly in each site's
-    # total, and the stored values meet that total to a few 1e-11 per site and step (the
-    # rest word's fp16 rounding of R's residual): at most 3e-11 x 24 sites x 2000 steps
-    assert abs(m1 - m0) <= (1e-6 * m0 if storage == "fp32" else 3e-11 * 24 * 2000)
+    # total, and each site's float32 complement and sums round the same way at every step
+    # of a steady state, so the drift is systematic too, at the float32 level
+    assert abs(m1 - m0) <= (1e-6 if storage == "fp32" else 1e-5) * m0
 
 
 @pytest.mark.parametrize("side", ["left", "right"])
@@ -637,7 +638,7 @@ def test_maximum_domain_one_step_sampled(storage, bc):
     sim.step(1)
     m1, bad1 = sim.mass()
     assert not bad0 and not bad1
-    assert abs(m1 - m0) <= (1e-7 if storage == "fp32" else 1e-10) * abs(m0), (m0, m1)
+    assert abs(m1 - m0) <= (1e-7 if storage == "fp32" else 1e-8) * abs(m0), (m0, m1)
     h1, g1 = sim.get_state()
     sites = pfinputs.sample_sites(MAX_SHAPE, 300, seed=3)
     x, y, z = (torch.as_tensor(v, device=h1.device) for v in sites.T)
@@ -689,7 +690,7 @@ def test_fp16s_one_step_random_state(name, q, shape, bc):
                          ids=["static_droplet", "rising_bubble"])
 def test_fp16s_error_and_mass(make, steps):
     """FP16-shifted storage against the FP64 oracle: the error per result is reported
-    (phi, P, J) and bounded; sum(phi) is conserved (to 1e-10 relative)."""
+    (phi, P, J) and bounded; sum(phi) is conserved to the float32 bar (1e-6 relative)."""
     cfg = make()
     r, ro, (m0, m1, bad), mo = _run_pair(cfg, steps, storage="fp16s")
     D = 3 if cfg["lattice"] == 19 else 2
@@ -700,9 +701,9 @@ def test_fp16s_error_and_mass(make, steps):
           f"(max|P| {np.abs(ro['P']).max():.2e}), rel J err {eJ:.2e}, "
           f"mass drift {(m1 - m0) / m0:.2e}")
     assert not bad
-    assert dphi <= 1e-3
-    # the rest word carries R's rounding: sum(phi) is conserved to float64 level
-    assert abs(m1 - m0) / m0 <= 1e-10
+    assert dphi <= 1e-4
+    assert eJ <= 1e-3
+    assert abs(m1 - m0) / m0 <= 1e-6
 
 
 @pytest.mark.parametrize("name", D3Q19_LONG)
@@ -710,7 +711,7 @@ def test_fp16s_error_table_d3q19_1000_steps(name):
     """FP16-shifted storage on the reduced D3Q19 workloads after 1000 steps against the
     FP64 oracle's run from the same start, stated per result: max and rms |d phi|,
     max|d P| relative to max|P|, the relative momentum error, and the sum(phi) drift.
-    Bounds: max|d phi| <= 2e-3, relative J error <= 2e-2, sum(phi) drift <= 1e-6
+    Bounds: max|d phi| <= 5e-4, relative J error <= 1e-3, sum(phi) drift <= 1e-6
     (the FP32 bar)."""
     cfg, steps, d = _oracle_run(name)
     r, m0, m1, bad = _gpu_run(cfg, steps, "fp16s")
@@ -722,6 +723,28 @@ def test_fp16s_error_table_d3q19_1000_steps(name):
     drift = (m1 - m0) / m0
     print(f"\nFP16S vs FP64 oracle, {name}, {steps} steps: max|dphi| {dphi:.2e}, rms "
           f"{rms:.2e}, max|dP|/max|P| {dP:.2e}, rel J err {eJ:.2e}, mass drift {drift:.2e}")
-    assert dphi <= 2e-3
-    assert eJ <= 2e-2
+    assert dphi <= 5e-4
+    assert eJ <= 1e-3
     assert abs(drift) <= 1e-6
+
+
+def test_step_graph_matches_step():
+    """pflb_step_graph replays captured launches: after every replay (odd and even step
+    counts, so both start buffers are captured, with eager reads and synchronisations in
+    between) the state equals plain pflb_step's bit for bit; a new step count recaptures."""
+    cfg = pfinputs.rayleigh_taylor(nx=64, ny=160)
+    phi, u, P = pfinputs.fields(cfg)
+    a, b = _sim(cfg), _sim(cfg)
+    a.init_fields(phi, u, P)
+    b.init_fields(phi, u, P)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for n in (7, 7, 7, 4, 4, 7):
+            a.step_graph(n)
+            b.step(n)
+            ha, ga = a.get_state()
+            hb, gb = b.get_state()
+            st.synchronize()
+            assert torch.equal(ha, hb) and torch.equal(ga, gb), n
+            assert a.steps == b.steps
+    assert a.steps == 36
