@@ -539,12 +539,15 @@ __device__ __forceinline__ GMom g_moments(const float (&g)[L::Q]) {
 template <class L, int WALLS, class F>
 __device__ __forceinline__ float gather16(const char* __restrict__ b, const Geom& G,
                                           const Col& c, const ZRow& r, const Codec& cd,
-                                          MomAcc& acc, F&& f) {
+                                          MomAcc& acc, F&& f, MomF* mom_out = nullptr) {
     const uint32_t site = c.base + r.base;
     const float2 rest = reinterpret_cast<const float2*>(b)[site];
     const MomF m =
         unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[site]);
-    f(std::integral_constant<int, 0>{}, rest.x, rest.y);
+    if (mom_out) *mom_out = m;
+    // f(I, h_I, g_I, raw g deviation): the decoded g and its reference are computed only
+    // where a caller uses them
+    f(std::integral_constant<int, 0>{}, rest.x, rest.y, 0.0f);
     // deviation of population pop >= 1 at dev_off + (pop - 1) S 4
     const char* base0 = b + StoreF16S::dev_off(G.S) - (size_t)G.S * 4;
     static_for<1, L::Q>([&](auto I) {
@@ -560,9 +563,32 @@ __device__ __forceinline__ float gather16(const char* __restrict__ b, const Geom
         const float hv = fmaf(q.x, cd.ish, rh);
         const float gv = fmaf(q.y, cd.isg, rg);
         acc.template add_h<L, i>(hv);
-        f(I, hv, gv);
+        f(I, hv, gv, q.y);
     });
     return rest.x + acc.S;
+}
+
+// Raw moments of the g set of a FP16S site from its moments word and the moments of
+// its raw g deviations over the moving directions: the references w_i (Psi + 3 c_i . Jg)
+// contribute (1 - w_0) Psi, Jg and Psi/3 per lattice axis (the lattice's second moment
+// is 1/3, its first and third vanish), the deviations dg the rest, scaled once.
+template <class L>
+__device__ __forceinline__ GMom g_moments16(float g0, const MomF& m, const GMom& d,
+                                            const Codec& cd) {
+    constexpr float wsum = (float)(1.0 - (L::Q == 19 ? 1.0 / 3.0 : 4.0 / 9.0));
+    constexpr float third = 1.0f / 3.0f;
+    GMom gm;
+    gm.s = g0 + fmaf(wsum, m.Psi, cd.isg * d.s);
+    gm.jx = fmaf(cd.isg, d.jx, m.Jx);
+    gm.jy = L::USES_Y ? fmaf(cd.isg, d.jy, m.Jy) : 0.0f;
+    gm.jz = fmaf(cd.isg, d.jz, m.Jz);
+    gm.xx = fmaf(third, m.Psi, cd.isg * d.xx);
+    gm.yy = L::USES_Y ? fmaf(third, m.Psi, cd.isg * d.yy) : 0.0f;
+    gm.zz = fmaf(third, m.Psi, cd.isg * d.zz);
+    gm.xy = cd.isg * d.xy;
+    gm.xz = cd.isg * d.xz;
+    gm.yz = cd.isg * d.yz;
+    return gm;
 }
 
 // Gather the Q pre-collision populations of both sets of one site and its phi.
@@ -572,7 +598,8 @@ __device__ __forceinline__ double pull_site(const char* __restrict__ b, const Ge
                                             float (&h)[L::Q], float (&g)[L::Q]) {
     if constexpr (ST::HALF) {
         MomAcc acc;
-        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float gv) {
+        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc,
+                                          [&](auto I, float hv, float gv, float) {
             h[decltype(I)::value] = hv;
             g[decltype(I)::value] = gv;
         });
@@ -599,7 +626,8 @@ __device__ __forceinline__ double pull_site_h(const char* __restrict__ b, const 
                                               float (&h)[L::Q]) {
     if constexpr (ST::HALF) {
         MomAcc acc;
-        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float) {
+        return (double)gather16<L, WALLS>(b, G, c, r, cd, acc,
+                                          [&](auto I, float hv, float, float) {
             h[decltype(I)::value] = hv;
         });
     } else {
@@ -645,11 +673,17 @@ __device__ __forceinline__ float pull_site_m16(const char* __restrict__ b, const
                                                const Col& c, const ZRow& r, const Codec& cd,
                                                float (&h)[L::Q], GMom& gm, uint4& mom) {
     MomAcc acc;
-    gm = GMom{};
-    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float hv, float gv) {
-        h[decltype(I)::value] = hv;
-        add_moment<L, decltype(I)::value>(gm, gv);
-    });
+    GMom d;
+    float g0 = 0.f;
+    MomF m;
+    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc,
+                                         [&](auto I, float hv, float gv, float qg) {
+        constexpr int i = decltype(I)::value;
+        h[i] = hv;
+        if constexpr (i == 0) g0 = gv;
+        else add_moment<L, i>(d, qg);
+    }, &m);
+    gm = g_moments16<L>(g0, m, d, cd);
     mom = pack_mom(phi, gm.s, acc.jx, acc.jy, acc.jz, gm.jx, gm.jy, gm.jz);
     return phi;
 }
@@ -661,17 +695,29 @@ __device__ __forceinline__ float pull_site_mom16(const char* __restrict__ b, con
                                                  const Col& c, const ZRow& r, const Codec& cd,
                                                  uint4& mom) {
     MomAcc acc;
-    float Sg = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
-    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc, [&](auto I, float, float gv) {
+    float g0 = 0.f, Sg = 0.f, Jx = 0.f, Jy = 0.f, Jz = 0.f;
+    MomF m;
+    const float phi = gather16<L, WALLS>(b, G, c, r, cd, acc,
+                                         [&](auto I, float, float gv, float qg) {
         constexpr int i = decltype(I)::value;
-        Sg += gv;
-        if constexpr (L::cx(i) > 0) Jx += gv;
-        if constexpr (L::cx(i) < 0) Jx -= gv;
-        if constexpr (L::cy(i) > 0) Jy += gv;
-        if constexpr (L::cy(i) < 0) Jy -= gv;
-        if constexpr (L::cz(i) > 0) Jz += gv;
-        if constexpr (L::cz(i) < 0) Jz -= gv;
-    });
+        if constexpr (i == 0) {
+            g0 = gv;
+        } else {
+            Sg += qg;
+            if constexpr (L::cx(i) > 0) Jx += qg;
+            if constexpr (L::cx(i) < 0) Jx -= qg;
+            if constexpr (L::cy(i) > 0) Jy += qg;
+            if constexpr (L::cy(i) < 0) Jy -= qg;
+            if constexpr (L::cz(i) > 0) Jz += qg;
+            if constexpr (L::cz(i) < 0) Jz -= qg;
+        }
+    }, &m);
+    // the moments of the g references as in g_moments16
+    constexpr float wsum = (float)(1.0 - (L::Q == 19 ? 1.0 / 3.0 : 4.0 / 9.0));
+    Sg = g0 + fmaf(wsum, m.Psi, cd.isg * Sg);
+    Jx = fmaf(cd.isg, Jx, m.Jx);
+    Jy = L::USES_Y ? fmaf(cd.isg, Jy, m.Jy) : 0.0f;
+    Jz = fmaf(cd.isg, Jz, m.Jz);
     mom = pack_mom(phi, Sg, acc.jx, acc.jy, acc.jz, Jx, Jy, Jz);
     return phi;
 }
@@ -706,12 +752,12 @@ struct SiteWriter32 {
 
 // FP16S writer.  A moving population is stored as the fp16 deviation from the reference
 // of its reader, formed from the reader's moments in the workgroup's LDS planes
-// (mom(DX, DY, DZ) gives the moments word of site + (DX, DY, DZ)); a population sent
+// (mom(K, DX, DY, DZ) is the moment pair K of site + (DX, DY, DZ)); a population sent
 // into a wall face is read back by the site itself as opp(I), with the site's own
 // moments and the reference of opp(I).  h_0 is written last as the complement T - (sum
 // of the decoded moving values, in index order), so that the decoded values the site
-// sends out sum to its h total; the site's moments word (the same fp16 values the
-// writers of its incoming populations used) is written beside it.
+// sends out sum to its h total.  (The site's moments word is written when it is
+// gathered.)
 template <class L, int WALLS, class MomAt>
 struct SiteWriter16 {
     char* __restrict__ b;
@@ -729,12 +775,17 @@ struct SiteWriter16 {
         } else {
             constexpr int ex = L::cx(I), ey = L::cy(I), ez = L::cz(I);
             const bool back = dest_beyond<L, I, WALLS>(solid);
-            const MomF m = unpack_mom(back ? mom(0, 0, 0) : mom(ex, ey, ez));
+            // the reader's moments: (Phi, Psi) and the (jh, Jg) pairs of the axes c_I spans
+            auto at = [&](int k) { return back ? mom(k, 0, 0, 0) : mom(k, ex, ey, ez); };
+            const float2 p0 = at(0);
+            const float2 px = ex ? at(1) : make_float2(0.f, 0.f);
+            const float2 py = ey ? at(2) : make_float2(0.f, 0.f);
+            const float2 pz = ez ? at(3) : make_float2(0.f, 0.f);
             // reference of population I at the reader, or of opp(I) (c = -c_I) at the site
             constexpr float w = L::w(I);
             const float sgn = back ? -3.0f : 3.0f;
-            const float rh = w * fmaf(sgn, cdot<L, I>(m.jx, m.jy, m.jz), m.Phi);
-            const float rg = w * fmaf(sgn, cdot<L, I>(m.Jx, m.Jy, m.Jz), m.Psi);
+            const float rh = w * fmaf(sgn, cdot<L, I>(px.x, py.x, pz.x), p0.x);
+            const float rg = w * fmaf(sgn, cdot<L, I>(px.y, py.y, pz.y), p0.y);
             const __half qh = __float2half_rn((h - rh) * cd.sh);
             const __half qg = __float2half_rn((g - rg) * cd.sg);
             const float dec = fmaf(__half2float(qh), cd.ish, rh);
@@ -750,7 +801,6 @@ struct SiteWriter16 {
     __device__ __forceinline__ void shift_h_total(double d) { D += (float)d; }
     __device__ __forceinline__ void finish() {
         store_nt(b + (size_t)site * 8u, (T - Sout) + D, g0);
-        store_nt(b + StoreF16S::mom_off(S) + (size_t)site * 16u, mom(0, 0, 0));
     }
 };
 

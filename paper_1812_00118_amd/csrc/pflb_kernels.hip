@@ -76,8 +76,19 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     static_assert(NR <= TX * TY, "ring larger than the workgroup");
     constexpr bool HALF = ST::HALF;
     __shared__ float sphi[4][HY][HX];
-    // FP16S: the moments words of the same positions (the references of the writers)
-    __shared__ uint4 smom[HALF ? 4 : 1][HALF ? HY : 1][HALF ? HX : 1];
+    // FP16S: the moments of the same positions as the writers use them (the fp16 values
+    // of each site's moments word, held as floats), one array per pair (Phi, Psi),
+    // (jh_x, Jg_x), (jh_y, Jg_y), (jh_z, Jg_z) so that neighbouring lanes read
+    // neighbouring words
+    __shared__ float2 smom[HALF ? 4 : 1][4][HALF ? HY : 1][HALF ? HX : 1];
+    auto put_mom = [&](int zr, int py, int px, const uint4& mw) {
+        if constexpr (HALF) {
+            smom[zr & 3][0][py][px] = unpack_h2(mw.x);
+            smom[zr & 3][1][py][px] = unpack_h2(mw.y);
+            smom[zr & 3][2][py][px] = unpack_h2(mw.z);
+            smom[zr & 3][3][py][px] = unpack_h2(mw.w);
+        }
+    };
 
     const int t = xcd_tile(blockIdx.x, nblk);
     const int bx = t % ntx;
@@ -123,7 +134,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             uint4 mw;
             const float ph = pull_site_mom16<L, WALLS>(src, G, cc, r, cd, mw);
             sphi[zr & 3][py][px] = wet(ph, vx, vy, zr);
-            smom[zr & 3][py][px] = mw;
+            put_mom(zr, py, px, mw);
         } else {
             float f[Q];
             sphi[zr & 3][py][px] = wet((float)pull_site_h<L, ST, WALLS>(src, G, cc, r, cd, f), vx, vy, zr);
@@ -136,7 +147,10 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             const float ph = pull_site_m16<L, WALLS>(src, G, own, r, cd, hv, gv, mw);
             lo = 0.0f;
             sphi[zr & 3][ty + OY][tx + 1] = wet(ph, x, y, zr);
-            smom[zr & 3][ty + OY][tx + 1] = mw;
+            put_mom(zr, ty + OY, tx + 1, mw);
+            // the site's moments word of this step, read back by the site at the next one
+            if (active)
+                store_nt(dst + StoreF16S::mom_off(G.S) + (size_t)(own.base + r.base) * 16u, mw);
         } else {
             sphi[zr & 3][ty + OY][tx + 1] =
                 wet(split_hi_lo(pull_site_m<L, WALLS>(src, G, own, r, hv, gv), lo), x, y, zr);
@@ -192,8 +206,9 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                 }
             };
             if constexpr (HALF) {
-                auto mom_at = [&](int dx, int dy, int dz) {
-                    return smom[(z + dz) & 3][ty + OY + dy][tx + 1 + dx];
+                // the moment pair k of site + (dx, dy, dz)
+                auto mom_at = [&](int k, int dx, int dy, int dz) -> float2 {
+                    return smom[(z + dz) & 3][k][ty + OY + dy][tx + 1 + dx];
                 };
                 SiteWriter16<L, WALLS, decltype(mom_at)> out{dst, own.base + r.base, G.S, cd,
                                                              mom_at, solid, a.phi};
@@ -558,7 +573,7 @@ __device__ __forceinline__ double slot_sum(const Geom& G, const char* b, uint32_
         site_coords(G, s, x, y, z);
         MomAcc ma;
         const float phi = gather16<L, WALLS>(b, G, make_col(G, x, y), make_zrow(G, z), cd, ma,
-                                             [&](auto, float hv, float gv) {
+                                             [&](auto, float hv, float gv, float) {
                                                  bad |= !isfinite(hv) || !isfinite(gv);
                                              });
         bad |= !isfinite(phi);
