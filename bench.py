@@ -62,7 +62,7 @@ def parse_args():
                     default="rising_bubble")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the other storage mode and the CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--sur-train-steps", type=int, default=6000)
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-profile", action="store_true",
@@ -110,6 +110,30 @@ def time_storage(cfg, storage, steps, warmup):
     phi_out = sim.read(fields=("phi",))["phi"]
     return dict(kernel_ms=kernel_ms, wall_s=wall, mass=mass, nonfinite=bad, phi=phi_out,
                 steps_done=sim.steps)
+
+
+def time_graph(cfg, storage, steps, warmup):
+    """Kernel time per step when the steps are replayed from one captured HIP graph
+    (pflb_step_graph) on a created stream."""
+    import torch
+    from paper_1812_00118_amd import Sim
+    import pfinputs
+    sim = Sim(cfg, storage=storage)
+    sim.init_fields(*pfinputs.fields(cfg))
+    sim.release_work()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        sim.step_graph(steps)            # capture and first replay
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        sim.step_graph(steps)
+        e1.record(st)
+        st.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def largest_domain_block(steps=20, warmup=5):
@@ -178,30 +202,52 @@ def read_traffic(storage):
     return float(v) if v else None
 
 
-def cpu_baseline(seconds):
-    """The FP64 oracle on a bounded sub-box of the same workload (same fluid parameters,
-    48^3 sites with the bubble scaled to R = 6), timed on the host."""
+def _oracle_rate(n, R, seconds, min_steps=2):
+    """Whole-domain FP64 oracle steps of the rising bubble on n^3 sites (same fluid
+    parameters, bubble radius R) for about `seconds`: (sites, steps, elapsed)."""
     import numpy as np
     import pfinputs
     from oracle import pflbm as O
-    cfg = pfinputs.rising_bubble(n=48, R=6.0)
+    cfg = pfinputs.rising_bubble(n=n, R=R)
     prm = O.Params.from_dict(pfinputs.model_params(cfg))
     phi, u, P = pfinputs.fields(cfg)
     h, g = O.init(prm, phi.astype(np.float64), u.astype(np.float64), P.astype(np.float64))
     h, g = O.step(prm, h, g)            # warm-up
-    n = 0
-    t0 = time.perf_counter()
+    k, t0 = 0, time.perf_counter()
     while True:
         h, g = O.step(prm, h, g)
-        n += 1
+        k += 1
         el = time.perf_counter() - t0
-        if el >= seconds:
+        if el >= seconds and k >= min_steps:
             break
-    sites = 48 ** 3
-    out = {"value": sites * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-           "sample": f"rising bubble sub-box 48^3 (R 6, same fluid parameters), {n} "
-                     f"whole-domain FP64 steps in {el:.1f} s, numpy single thread"}
-    # the host, and the oracle on the two D2Q9 workloads (a few seconds each)
+    return n ** 3, k, el
+
+
+def _oracle_worker(args):
+    n, R, seconds = args
+    return _oracle_rate(n, R, seconds)
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle timed on the host, before the GPU is touched.
+    All cores: one oracle process per core, each stepping a 48^3 sub-box of the rising
+    bubble (same fluid parameters, bubble scaled to R = 6); the value is their summed
+    rate.  One core: the oracle stepping the full 128^3 rising bubble (the benchmark's
+    own workload) for a few whole-domain steps."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                       else (os.cpu_count() or 1)))
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(48, 6.0, seconds)] * cores)
+    agg = sum(s * k / el for s, k, el in res) / 1e6
+    out = {"value": round(agg, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{cores} oracle processes (numpy, one thread each) side by side, each "
+                     f"stepping a 48^3 sub-box of the rising bubble (R 6, same fluid "
+                     f"parameters) for ~{seconds:.0f} s; value = summed sites x steps / s"}
+    sites, k, el = _oracle_rate(128, 16.0, seconds, min_steps=1)
+    out["single_core"] = {"mlups": round(sites * k / el / 1e6, 3), "steps": k,
+                          "seconds": round(el, 2),
+                          "sample": "the full 128^3 rising bubble, numpy single thread"}
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -209,26 +255,7 @@ def cpu_baseline(seconds):
                          "")
     except OSError:
         pass
-    out["host"] = {"cpu_model": model, "logical_cpus": os.cpu_count()}
-    d2 = {}
-    for name, cfg2, budget in (("static_droplet D2Q9 64x64", pfinputs.static_droplet(), 3.0),
-                               ("rayleigh_taylor D2Q9 256x1024",
-                                pfinputs.rayleigh_taylor(), 6.0)):
-        prm2 = O.Params.from_dict(pfinputs.model_params(cfg2))
-        f2 = pfinputs.fields(cfg2)
-        h2, g2 = O.init(prm2, *(a.astype(np.float64) for a in f2))
-        h2, g2 = O.step(prm2, h2, g2)
-        k, t1 = 0, time.perf_counter()
-        while True:
-            h2, g2 = O.step(prm2, h2, g2)
-            k += 1
-            e2 = time.perf_counter() - t1
-            if e2 >= budget:
-                break
-        nx, ny, nz = cfg2["shape"]
-        d2[name] = {"mlups": round(nx * ny * nz * k / e2 / 1e6, 3), "steps": k,
-                    "seconds": round(e2, 2)}
-    out["d2q9_oracle"] = d2
+    out["host"] = {"cpu_model": model, "logical_cpus": os.cpu_count(), "cores_used": cores}
     return out
 
 
@@ -311,11 +338,13 @@ def surrogate_block(train_steps):
                 sm.step(64)
                 lst.append(sm)
         torch.cuda.synchronize()
+        m_start = [sm.mass()[0] for sm in a]
         t0 = time.time()
         nf = sur.advance_guarded(a, 8, mass_tol=1e-3, phi_tol=0.05, check_every=4,
                                  u_max=0.1)
         torch.cuda.synchronize()
         g_ms = (time.time() - t0) * 1e3
+        drift = max(abs(sm.mass()[0] - m0) / m0 for sm, m0 in zip(a, m_start))
         # plain stepping, batched (the fair baseline), and one domain after another
         t0 = time.time()
         Sim.step_many(b, 128)
@@ -343,7 +372,8 @@ def surrogate_block(train_steps):
                                  "plain_lb_ms_one_domain_at_a_time": round(p1_ms, 3),
                                  "max_abs_dphi_vs_lb_after_128_steps": dphi,
                                  "mean_abs_dphi_vs_lb_after_128_steps": mphi,
-                                 "share_of_sites_abs_dphi_over_0.1": frac}
+                                 "share_of_sites_abs_dphi_over_0.1": frac,
+                                 "max_rel_sum_phi_drift_over_128_steps": drift}
         print(f"[bench] guarded batch {nb}: {g_ms:.1f} ms vs plain {p_ms:.1f} ms batched "
               f"({p1_ms:.1f} ms one domain at a time), fallbacks "
               f"{nf}/{8 * nb}, max|dphi| {dphi:.3e}, mean|dphi| {mphi:.2e}, "
@@ -398,6 +428,14 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               f"decomposition is a design note, not part of this build.", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not args.no_compare:
+        # the oracle's worker processes are forked before this process touches the GPU
+        t0 = time.time()
+        cpu = cpu_baseline(args.cpu_seconds)
+        print(f"[bench] cpu baseline: {cpu['value']} MLUPS on {cpu['cores']} cores, "
+              f"{cpu['single_core']['mlups']} MLUPS one core ({time.time() - t0:.0f} s)",
+              file=sys.stderr, flush=True)
     import torch
     import pfinputs
     if not torch.cuda.is_available():
@@ -497,8 +535,12 @@ def main():
                            "kernel_ms": round(r3["kernel_ms"], 5),
                            "effective_GBs": round(BYTES_PER_SITE[("9", st)] * n3 /
                                                   (r3["kernel_ms"] * 1e-3) / 1e9, 1)}
-                print(f"[bench] rayleigh_taylor {st}: {r3['kernel_ms']:.4f} ms/step",
-                      file=sys.stderr, flush=True)
+                gms = time_graph(cfg3, st, max(200, args.steps), args.warmup)
+                blk[st]["graph_kernel_ms"] = round(gms, 5)
+                print(f"[bench] rayleigh_taylor {st}: {r3['kernel_ms']:.4f} ms/step "
+                      f"({gms:.4f} replayed from a HIP graph)", file=sys.stderr, flush=True)
+            blk["graph"] = ("graph_kernel_ms: the same steps captured once with "
+                            "pflb_step_graph and replayed as one graph launch")
             out["rayleigh_taylor"] = blk
             # moving walls: the rising-bubble domain with its top wall sliding along x
             # (the step variant with momentum-corrected bounce-back)
@@ -542,7 +584,7 @@ def main():
             out["contact_angles"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
