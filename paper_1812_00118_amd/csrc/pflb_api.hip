@@ -54,8 +54,8 @@ std::string check_params(const pflb_params* p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "nx, ny, nz must be >= 1";
     if (p->lattice == 9 && p->nz != 1) return "D2Q9 needs nz = 1";
     const double n = (double)p->nx * p->ny * p->nz;
-    // population addresses are 32-bit byte offsets from a per-direction base
-    if (n > 268435456.0 - 64.0) return "domain larger than 2^28 - 64 sites";
+    // site indices are 32-bit (beyond 2^28 - 64 sites the kernels form 64-bit addresses)
+    if (n > 4294967296.0 - 64.0) return "domain larger than 2^32 - 64 sites";
     for (int a = 0; a < 3; ++a)
         if (p->bc[a] != PFLB_BC_PERIODIC && p->bc[a] != PFLB_BC_WALL) return "bc must be 0 or 1";
     if (!(finite(p->rho_L) && p->rho_L > 0) || !(finite(p->rho_H) && p->rho_H > 0))
@@ -244,6 +244,7 @@ void derive(pflb_ctx* c) {
     const char* tenv = getenv("PFLB_TILE");
     if (tenv && atoi(tenv) >= 0 && atoi(tenv) <= 3) c->L.tile = atoi(tenv);
     c->L.bz = pick_bz(G, p.lattice, 1);
+    c->L.wide = G.S > (1u << 28) - 64u;
 }
 
 int fail(pflb_ctx* c, int code, const std::string& what) {
@@ -743,7 +744,7 @@ extern "C" int pflb_step_many(pflb_ctx* const* c, int n, int nsteps, void* strea
     // differently).
     std::vector<pflb_ctx*> gr;
     for (int k = 0; k < n; ++k) {
-        if (!c[k]->L.m.moving && !c[k]->L.m.wetting) {
+        if (!c[k]->L.m.moving && !c[k]->L.m.wetting && !c[k]->L.wide) {
             gr.push_back(c[k]);
         } else if ((r = pflb_step(c[k], nsteps, stream))) {
             if (c[k] != c[0]) fail(c[0], r, pflb_last_error(c[k]));

@@ -370,24 +370,27 @@ __device__ __forceinline__ float wet_ghost(const Geom& G, const Model& m, int vx
 }
 
 // Upstream offsets of an (x, y) column: source x - 1 (for c_x = +1) and x + 1 (c_x = -1)
+// Site offsets are added modulo 2^32 (a step back is 2^32 - 1): every site index and
+// every sum that names a site stays below 2^32.
 struct Col {
-    uint32_t base;            // y*nx + x
-    int dxm, dxp, dym, dyp;   // site offsets to the upstream site
-    uint32_t solid;           // bit0: x-1 beyond a wall, bit1: x+1, bit2: y-1, bit3: y+1
+    uint32_t base;                 // y*nx + x
+    uint32_t dxm, dxp, dym, dyp;   // site offsets to the upstream site
+    uint32_t solid;                // bit0: x-1 beyond a wall, bit1: x+1, bit2: y-1, bit3: y+1
 };
 struct ZRow {
-    uint32_t base;            // z*nx*ny
-    int dzm, dzp;
-    uint32_t solid;           // bit4: z-1 beyond a wall, bit5: z+1
+    uint32_t base;                 // z*nx*ny
+    uint32_t dzm, dzp;
+    uint32_t solid;                // bit4: z-1 beyond a wall, bit5: z+1
 };
 
 __device__ __forceinline__ Col make_col(const Geom& G, int x, int y) {
     Col c;
     c.base = (uint32_t)y * (uint32_t)G.nx + (uint32_t)x;
-    c.dxm = (x == 0) ? G.nx - 1 : -1;
-    c.dxp = (x == G.nx - 1) ? -(G.nx - 1) : 1;
-    c.dym = (y == 0) ? (G.ny - 1) * G.nx : -G.nx;
-    c.dyp = (y == G.ny - 1) ? -(G.ny - 1) * G.nx : G.nx;
+    const uint32_t nx = (uint32_t)G.nx, ny = (uint32_t)G.ny;
+    c.dxm = (x == 0) ? nx - 1u : 0u - 1u;
+    c.dxp = (x == G.nx - 1) ? 0u - (nx - 1u) : 1u;
+    c.dym = (y == 0) ? (ny - 1u) * nx : 0u - nx;
+    c.dyp = (y == G.ny - 1) ? 0u - (ny - 1u) * nx : nx;
     c.solid = 0;
     if (G.wx) c.solid |= (x == 0 ? 1u : 0u) | (x == G.nx - 1 ? 2u : 0u);
     if (G.wy) c.solid |= (y == 0 ? 4u : 0u) | (y == G.ny - 1 ? 8u : 0u);
@@ -397,8 +400,9 @@ __device__ __forceinline__ Col make_col(const Geom& G, int x, int y) {
 __device__ __forceinline__ ZRow make_zrow(const Geom& G, int z) {
     ZRow r;
     r.base = (uint32_t)z * G.sxy;
-    r.dzm = (z == 0) ? (int)((G.nz - 1) * G.sxy) : -(int)G.sxy;
-    r.dzp = (z == G.nz - 1) ? -(int)((G.nz - 1) * G.sxy) : (int)G.sxy;
+    const uint32_t nz = (uint32_t)G.nz;
+    r.dzm = (z == 0) ? (nz - 1u) * G.sxy : 0u - G.sxy;
+    r.dzp = (z == G.nz - 1) ? 0u - (nz - 1u) * G.sxy : G.sxy;
     r.solid = 0;
     if (G.wz) r.solid = (z == 0 ? 16u : 0u) | (z == G.nz - 1 ? 32u : 0u);
     return r;
@@ -407,6 +411,10 @@ __device__ __forceinline__ ZRow make_zrow(const Geom& G, int z) {
 // Which boundaries a kernel variant handles: walls across x or y (a per-lane test) and
 // walls across z (uniform over a plane, so a scalar test in the z-marching kernel).
 enum WallSet { WALLS_NONE = 0, WALLS_Z = 1, WALLS_XY = 2, WALLS_XYZ = 3 };
+// Added to a kernel's wall set for domains whose slot byte offsets need 64 bits (more
+// than 2^28 - 64 sites): addresses are then formed as 64-bit sums per lane instead of
+// a uniform base plus a 32-bit lane offset.
+constexpr int ADDR64 = 8;
 
 // Upstream slot of direction I for the site (c, r): (site - c_I, I), or (site, opp(I))
 // when the upstream site lies beyond a wall (flip = true).
@@ -428,7 +436,7 @@ __device__ __forceinline__ void upstream(const Col& c, const ZRow& r, uint32_t& 
                                          bool& flip) {
     using U = Up<L, I, WALLS>;
     const uint32_t site = c.base + r.base;
-    int off = 0;
+    uint32_t off = 0u;
     if constexpr (U::ex > 0) off += c.dxm;
     if constexpr (U::ex < 0) off += c.dxp;
     if constexpr (U::ey > 0) off += c.dym;
@@ -456,7 +464,16 @@ __device__ __forceinline__ const char* slot_addr(const char* __restrict__ base0,
                                                  uint32_t& off) {
     using U = Up<L, I, WALLS>;
     const size_t stride = (size_t)S * ESIZE;
-    if constexpr (!U::MAYFLIP) {
+    if constexpr ((WALLS & ADDR64) != 0) {
+        off = 0u;
+        if constexpr (!U::MAYFLIP) {
+            return base0 + (size_t)I * stride + (size_t)slot_site * ESIZE;
+        } else {
+            const bool second = flip ? (I == U::LO) : (I != U::LO);
+            return base0 + (size_t)U::LO * stride + (second ? stride : (size_t)0) +
+                   (size_t)slot_site * ESIZE;
+        }
+    } else if constexpr (!U::MAYFLIP) {
         off = slot_site * (uint32_t)ESIZE;
         return base0 + (size_t)I * stride;
     } else {
@@ -465,6 +482,14 @@ __device__ __forceinline__ const char* slot_addr(const char* __restrict__ base0,
         off = slot_site * (uint32_t)ESIZE + (second ? (uint32_t)stride : 0u);
         return base0 + (size_t)U::LO * stride;
     }
+}
+
+// byte offset of element `site` of size E: 32-bit (a uniform base plus a lane offset)
+// unless the wall set carries ADDR64
+template <int WALLS, int E>
+__device__ __forceinline__ size_t elem_off(uint32_t site) {
+    if constexpr ((WALLS & ADDR64) != 0) return (size_t)site * E;
+    else return (size_t)(site * (uint32_t)E);
 }
 
 // FP32 storage: slot pair (h, g), or h alone, of direction I.
@@ -736,15 +761,15 @@ __device__ __forceinline__ bool dest_beyond(uint32_t solid) {
 
 // Streaming writer of one site's post-collision pairs (pairs arrive rest population
 // first), FP32 storage.
-template <class L>
+template <class L, int WALLS>
 struct SiteWriter32 {
     char* __restrict__ b;
-    uint32_t off8;                 // site * 8
+    uint32_t site;
     uint32_t S;
     template <int I>
     __device__ __forceinline__ void put(float h, float g) {
         char* base = b + (size_t)I * ((size_t)S * 8);
-        store_nt(base + off8, h, g);
+        store_nt(base + elem_off<WALLS, 8>(site), h, g);
     }
     __device__ __forceinline__ void finish() {}
     __device__ __forceinline__ void shift_h_total(double) {}
@@ -790,7 +815,8 @@ struct SiteWriter16 {
             const __half qg = __float2half_rn((g - rg) * cd.sg);
             const float dec = fmaf(__half2float(qh), cd.ish, rh);
             Sout = I == 1 ? dec : Sout + dec;
-            store_nt(b + StoreF16S::dev_off(S) + (size_t)(I - 1) * ((size_t)S * 4) + site * 4u,
+            store_nt(b + StoreF16S::dev_off(S) + (size_t)(I - 1) * ((size_t)S * 4) +
+                         elem_off<WALLS, 4>(site),
                      __halves2half2(qh, qg));
         }
     }
@@ -800,7 +826,7 @@ struct SiteWriter16 {
     // (exact when Sout is within a factor two of T) untouched
     __device__ __forceinline__ void shift_h_total(double d) { D += (float)d; }
     __device__ __forceinline__ void finish() {
-        store_nt(b + (size_t)site * 8u, (T - Sout) + D, g0);
+        store_nt(b + elem_off<WALLS, 8>(site), (T - Sout) + D, g0);
     }
 };
 

@@ -14,6 +14,7 @@ struct Launch {
     bool half;          // FP16S storage
     int bz;             // planes per workgroup in the fused step
     int tile;           // D3Q19 tile shape: 0: 64x4, 1: 64x8, 2: 32x8, 3: 32x4
+    bool wide;          // more than 2^28 - 64 sites: 64-bit slot addresses
     Geom G;
     Model m;
     Codec cd;

@@ -68,6 +68,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         dst = e.dst;
     }
     constexpr int Q = L::Q;
+    constexpr int WS = WALLS & WALLS_XYZ;   // the wall set without the addressing flag
     constexpr int HX = TX + 2;
     constexpr int HY = L::USES_Y ? TY + 2 : 1;
     constexpr int OY = L::USES_Y ? 1 : 0;
@@ -122,7 +123,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     // the wetting rule
     const int rrx = x0 - 1 + rhx, rry = L::USES_Y ? y0 - 1 + rhy : 0;
     auto wet = [&](float v, int vx, int vy, int vz) {
-        if constexpr (WALLS != WALLS_NONE && XBC) {
+        if constexpr (WS != WALLS_NONE && XBC) {
             if (m.wetting) return wet_ghost(G, m, vx, vy, vz, v);
         }
         return v;
@@ -150,7 +151,8 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             put_mom(zr, ty + OY, tx + 1, mw);
             // the site's moments word of this step, read back by the site at the next one
             if (active)
-                store_nt(dst + StoreF16S::mom_off(G.S) + (size_t)(own.base + r.base) * 16u, mw);
+                store_nt(dst + StoreF16S::mom_off(G.S) + elem_off<WALLS, 16>(own.base + r.base),
+                         mw);
         } else {
             sphi[zr & 3][ty + OY][tx + 1] =
                 wet(split_hi_lo(pull_site_m<L, WALLS>(src, G, own, r, hv, gv), lo), x, y, zr);
@@ -195,7 +197,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
             const Macro a = macros<L>(m, pn, gc);
             const uint32_t solid = own.solid | r.solid;
             auto collide_to = [&](auto& out) {
-                if constexpr (WALLS == WALLS_NONE || !XBC) {
+                if constexpr (WS == WALLS_NONE || !XBC) {
                     collide_stream<L>(m, a, lo_c, hc, gc, out);
                 } else {
                     const bool on =
@@ -214,7 +216,7 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                                                              mom_at, solid, a.phi};
                 collide_to(out);
             } else {
-                SiteWriter32<L> out{dst, (own.base + r.base) * 8u, G.S};
+                SiteWriter32<L, WALLS> out{dst, own.base + r.base, G.S};
                 collide_to(out);
             }
         }
@@ -672,14 +674,19 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
 
 template <class L, class ST, int WALLS>
 static hipError_t launch_step_t(const Launch& a, const StepArgs& x) {
-    if constexpr (WALLS != WALLS_NONE) {
+    if constexpr ((WALLS & WALLS_XYZ) != WALLS_NONE) {
         // moving walls or contact angles: one tile shape per lattice
         if (a.m.moving || a.m.wetting) {
             if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, x);
             else return launch_tile<L, ST, WALLS, 64, 1, true>(a, x);
         }
     }
-    if constexpr (L::USES_Y) {
+    if constexpr ((WALLS & ADDR64) != 0) {
+        // domains beyond 2^28 sites: the default tile only, stepped one context at a time
+        if (x.bt) return hipErrorInvalidValue;
+        if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4>(a, x);
+        else return launch_tile<L, ST, WALLS, 64, 1>(a, x);
+    } else if constexpr (L::USES_Y) {
         switch (a.tile) {
             case 1: return launch_tile<L, ST, WALLS, 64, 8>(a, x);
             case 2: return launch_tile<L, ST, WALLS, 32, 8>(a, x);
@@ -697,6 +704,14 @@ static inline int wallset(const Geom& G) {
 
 template <class L, class ST>
 static hipError_t dispatch_walls(const Launch& a, const StepArgs& x) {
+    if (a.wide) {
+        switch (wallset(a.G)) {
+            case WALLS_XYZ: return launch_step_t<L, ST, WALLS_XYZ | ADDR64>(a, x);
+            case WALLS_XY: return launch_step_t<L, ST, WALLS_XY | ADDR64>(a, x);
+            case WALLS_Z: return launch_step_t<L, ST, WALLS_Z | ADDR64>(a, x);
+            default: return launch_step_t<L, ST, WALLS_NONE | ADDR64>(a, x);
+        }
+    }
     switch (wallset(a.G)) {
         case WALLS_XYZ: return launch_step_t<L, ST, WALLS_XYZ>(a, x);
         case WALLS_XY: return launch_step_t<L, ST, WALLS_XY>(a, x);
@@ -786,6 +801,9 @@ static hipError_t get_state_t(const Launch& a, uint32_t N, const void* b, float*
 
 template <class L, class ST>
 static hipError_t get_state_w(const Launch& a, uint32_t N, const void* b, float* h, float* g) {
+    if (a.wide)
+        return wallset(a.G) ? get_state_t<L, ST, WALLS_XYZ | ADDR64>(a, N, b, h, g)
+                            : get_state_t<L, ST, WALLS_NONE | ADDR64>(a, N, b, h, g);
     if (wallset(a.G)) return get_state_t<L, ST, WALLS_XYZ>(a, N, b, h, g);
     return get_state_t<L, ST, WALLS_NONE>(a, N, b, h, g);
 }
@@ -812,6 +830,9 @@ static hipError_t read_t(const Launch& a, uint32_t N, const void* b, float* phi,
 template <class L, class ST>
 static hipError_t read_w(const Launch& a, uint32_t N, const void* b, float* phi, float* P,
                          float* J, float* U) {
+    if (a.wide)
+        return wallset(a.G) ? read_t<L, ST, WALLS_XYZ | ADDR64>(a, N, b, phi, P, J, U)
+                            : read_t<L, ST, WALLS_NONE | ADDR64>(a, N, b, phi, P, J, U);
     if (wallset(a.G)) return read_t<L, ST, WALLS_XYZ>(a, N, b, phi, P, J, U);
     return read_t<L, ST, WALLS_NONE>(a, N, b, phi, P, J, U);
 }
@@ -836,6 +857,7 @@ static hipError_t read_batch_t(const Launch& a, uint32_t N, const Batch& bt, int
 
 template <class L, class ST>
 static hipError_t read_batch_w(const Launch& a, uint32_t N, const Batch& bt, int n, bool macro) {
+    if (a.wide) return hipErrorInvalidValue;    // batches hold small domains only
     if (wallset(a.G)) return read_batch_t<L, ST, WALLS_XYZ>(a, N, bt, n, macro);
     return read_batch_t<L, ST, WALLS_NONE>(a, N, bt, n, macro);
 }
@@ -853,7 +875,11 @@ template <class L, class ST>
 static hipError_t mass_t(const Launch& a, uint32_t N, const void* b, void* scratch) {
     double* part = static_cast<double*>(scratch);
     int* flag = reinterpret_cast<int*>(part + MASS_BLOCKS + 1);
-    if (wallset(a.G))
+    if (a.wide)
+        hipLaunchKernelGGL((k_mass_partial<L, ST, WALLS_XYZ | ADDR64>), dim3(MASS_BLOCKS),
+                           dim3(MASS_THREADS), 0, a.stream, a.G, a.cd, N,
+                           static_cast<const char*>(b), part, flag);
+    else if (wallset(a.G))
         hipLaunchKernelGGL((k_mass_partial<L, ST, WALLS_XYZ>), dim3(MASS_BLOCKS),
                            dim3(MASS_THREADS), 0, a.stream, a.G, a.cd, N,
                            static_cast<const char*>(b), part, flag);

@@ -610,23 +610,29 @@ def test_full_size_one_step_sampled(make):
     _close(gg, gr)
 
 
-# the largest domain the library accepts is 2^28 - 64 sites (byte offsets within one
-# direction's array stay below 2^31); this one is 2.68e8 sites, ragged in x (1000 = 15 * 64
-# + 40), so the last sites' slots sit within 4 MB of that limit
-MAX_SHAPE = (1000, 1000, 268)
+# Up to 2^28 - 64 sites the step addresses a slot as a uniform base plus a 32-bit lane
+# offset; 1000 x 1000 x 268 = 2.68e8 sites is just below, ragged in x (1000 = 15 * 64 +
+# 40), so the last sites' slots sit within 4 MB of the 2^31-byte offset range.  Beyond
+# that the kernels form 64-bit addresses: 1100 x 1000 x 268 = 2.95e8 sites (FP32, 90 GB
+# of state) and 1500 x 1000 x 300 = 4.5e8 sites (FP16S, 86 GB).
+MAX_CASES = [("fp32", (P_, P_, W_), (1000, 1000, 268), 130),
+             ("fp16s", (W_, W_, W_), (1000, 1000, 268), 90),
+             ("fp32", (P_, P_, W_), (1100, 1000, 268), 145),
+             ("fp16s", (W_, W_, W_), (1500, 1000, 300), 165)]
 
 
-@pytest.mark.parametrize("storage,bc", [("fp32", (P_, P_, W_)), ("fp16s", (W_, W_, W_))],
-                         ids=["fp32-walls-z", "fp16s-walls-all"])
-def test_maximum_domain_one_step_sampled(storage, bc):
-    """At the largest domain the library accepts: one step from a hashed state filled on
-    the GPU, checked at sampled sites (random, box corners and face centres, so also the
-    last slots of every direction's array) against the oracle's site-by-site evaluation
-    of the same hashed values; sum(phi) is conserved and finite."""
-    need = (130 if storage == "fp32" else 90) * 2 ** 30
+@pytest.mark.parametrize("storage,bc,shape,gib", MAX_CASES,
+                         ids=["fp32-walls-z-2.68e8", "fp16s-walls-all-2.68e8",
+                              "fp32-walls-z-2.95e8-addr64", "fp16s-walls-all-4.5e8-addr64"])
+def test_maximum_domain_one_step_sampled(storage, bc, shape, gib):
+    """On domains at and beyond 2^28 sites: one step from a hashed state filled on the
+    GPU, checked at sampled sites (random, box corners and face centres, so also the last
+    slots of every direction's array) against the oracle's site-by-site evaluation of the
+    same hashed values; sum(phi) is conserved and finite."""
+    need = gib * 2 ** 30
     if torch.cuda.mem_get_info()[0] < need:
-        pytest.skip("needs about %d GiB of free device memory" % (need >> 30))
-    assert MAX_SHAPE[0] * MAX_SHAPE[1] * MAX_SHAPE[2] <= 2 ** 28 - 64
+        pytest.skip("needs about %d GiB of free device memory" % gib)
+    MAX_SHAPE = shape
     cfg = _cfg(19, MAX_SHAPE, bc, g=(2e-5, -1e-5, 3e-5))
     st = pfinputs.HashedState(19, MAX_SHAPE, seed=29)
     sim = _sim(cfg, storage=storage)
