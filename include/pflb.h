@@ -73,7 +73,7 @@ extern "C" {
 /*
  * Model and domain parameters (Section 2; Section 4 gives values per case).
  *   lattice      9 (D2Q9) or 19 (D3Q19)
- *   nx, ny, nz   sites per axis (nz = 1 for D2Q9), each >= 1, at most 2^28 - 64 sites
+ *   nx, ny, nz   sites per axis (nz = 1 for D2Q9), each >= 1, at most 2^32 - 64 sites
  *   bc[3]        boundary per axis x, y, z: PFLB_BC_PERIODIC or PFLB_BC_WALL (both
  *                faces of an axis alike; walls: halfway bounce-back for h and g,
  *                phi outside a wall equals phi at the adjacent site)

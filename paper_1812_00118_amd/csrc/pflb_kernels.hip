@@ -178,11 +178,18 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
         // reaching it ahead of other waves' collision arithmetic (measured: 1-3% faster);
         // back to normal after the barrier
         __builtin_amdgcn_s_setprio(2);
-        if (z + 1 < zend) {
-            own_site(rn, z + 1, hn, gn, lo_n);
+        if constexpr (HALF) {
+            if (z + 1 < zend) {
+                own_site(rn, z + 1, hn, gn, lo_n);
+            } else {
+                // the plane above the chunk, for the neighbours only
+                side_site(own, rn, z + 1, ty + OY, tx + 1, x, y);
+            }
         } else {
-            // the plane above the chunk, for the neighbours only
-            side_site(own, rn, z + 1, ty + OY, tx + 1, x, y);
+            // (one phi store after either gather: measured faster than a store per branch)
+            const double pn64 = (z + 1 < zend) ? pull_site_m<L, WALLS>(src, G, own, rn, hn, gn)
+                                               : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
+            sphi[(z + 1) & 3][ty + OY][tx + 1] = wet(split_hi_lo(pn64, lo_n), x, y, z + 1);
         }
         if (has_ring) side_site(ring, rn, z + 1, rhy, rhx, rrx, rry);
         lds_barrier();

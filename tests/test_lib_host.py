@@ -130,7 +130,7 @@ def _params(**kw):
                                  dict(nx=0), dict(lattice=9), dict(sigma=float("nan")),
                                  dict(storage=3), dict(storage=1, scale=(30, 0)),
                                  dict(hoc=2), dict(eps=0.0),
-                                 dict(nx=1024, ny=1024, nz=256),
+                                 dict(nx=4096, ny=4096, nz=256),
                                  dict(wall=(0, 1, 0.01)), dict(wall=(4, 2, 0.01)),
                                  dict(wall=(5, 0, float("nan"))),
                                  dict(lattice=9, nz=1, wall=(4, 0, 0.01)),
@@ -139,7 +139,7 @@ def _params(**kw):
                                  dict(lattice=9, nz=1, bc=(1, 1, 0), wet=(4, 0.5))])
 def test_create_rejects_bad_params(L, bad):
     """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1,
-    domains beyond 2^28 - 64 sites, wall velocities on periodic faces, normal to
+    domains beyond 2^32 - 64 sites, wall velocities on periodic faces, normal to
     their face, non-finite or on faces D2Q9 does not have, and contact-angle cosines
     outside [-1, 1], non-finite, on periodic faces or on faces D2Q9 does not have return
     PFLB_ERR_PARAM and leave *out NULL."""
@@ -172,12 +172,15 @@ def test_required_bytes_and_unbound_errors(L):
     assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
     try:
         N = 8 * 8 * 8
-        # a state buffer holds both sets: 19 float pairs per site, or a float pair plus
-        # 19 half pairs per site in FP16S storage
+        # a state buffer holds both sets: 19 float pairs per site, or in FP16S storage a
+        # float pair (the rest populations), a 16-byte moments word and 18 half pairs
         assert L.pflb_required_bytes(ctypes.byref(p), 0) >= 19 * N * 8
         p16 = _params(storage=1, scale=(16, 8))
-        assert L.pflb_required_bytes(ctypes.byref(p16), 1) >= N * 8 + 19 * N * 4
+        assert L.pflb_required_bytes(ctypes.byref(p16), 1) >= N * (8 + 16 + 18 * 4)
         assert L.pflb_required_bytes(ctypes.byref(p16), 1) < 19 * N * 8
+        # a domain beyond 2^28 sites (64-bit slot addresses) is accepted
+        big = _params(nx=2048, ny=1024, nz=256)
+        assert L.pflb_required_bytes(ctypes.byref(big), 0) == 19 * 8 * 2048 * 1024 * 256
         assert L.pflb_required_bytes(ctypes.byref(p), 2) > 0
         assert L.pflb_required_bytes(ctypes.byref(p), 9) == 0
         # every state call before pflb_bind reports PFLB_ERR_UNBOUND without GPU work
