@@ -36,7 +36,9 @@ class Params(ctypes.Structure):
                 ("storage", ctypes.c_int),
                 ("scale_log2", ctypes.c_int * 2),
                 ("wall_u", ctypes.c_double * 18),
-                ("wet_cos", ctypes.c_double * 6)]
+                ("wet_cos", ctypes.c_double * 6),
+                ("open", ctypes.c_int * 6),
+                ("open_P", ctypes.c_double * 6)]
 
 
 class SurCfg(ctypes.Structure):

@@ -94,13 +94,49 @@ std::string check_params(const pflb_params* p) {
         if (axis >= naxes) return "contact angle on an axis the lattice does not have";
         if (p->bc[axis] != PFLB_BC_WALL) return "contact angle given for a face of a periodic axis";
     }
+    bool any_open = false, any_moving = false;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a) any_moving = any_moving || p->wall_u[f][a] != 0.0;
+    for (int f = 0; f < 6; ++f) {
+        if (p->open[f] != 0 && p->open[f] != 1) return "open must be 0 or 1";
+        if (!p->open[f]) continue;
+        any_open = true;
+        // the z axis of the lattice (D2Q9: the user's y axis)
+        const int zaxis = p->lattice == 9 ? 1 : 2;
+        if (f / 2 != zaxis) return "only the faces of the z axis (D2Q9: y) may be open";
+        if (p->bc[zaxis] != PFLB_BC_WALL) return "an open face must be on a wall axis";
+        if ((p->lattice == 9 ? p->ny : p->nz) < 2) return "an open face needs at least 2 sites along its axis";
+        if (!finite(p->open_P[f])) return "open-face pressure must be finite";
+        if (p->wet_cos[f] != 0.0) return "a contact angle given for an open face";
+    }
+    if (any_open && any_moving) return "moving walls and open faces together are not supported";
     return "";
+}
+
+bool has_open(const pflb_params* p) {
+    for (int f = 0; f < 6; ++f)
+        if (p->open[f]) return true;
+    return false;
 }
 
 uint32_t pop_stride(uint32_t N) { return (N + 63u) & ~63u; }
 
+// the pressures of the two boundary layers of the z axis (open faces only): one float
+// per site of a layer, each layer of stride side_stride
+uint32_t side_stride(const pflb_params* p) {
+    const uint32_t layer = p->lattice == 9 ? (uint32_t)p->nx : (uint32_t)p->nx * (uint32_t)p->ny;
+    return (layer + 63u) & ~63u;
+}
+
+size_t side_offset(const pflb_params* p, uint32_t N) {
+    const size_t b = state_bytes(p->lattice, p->storage == PFLB_STORE_FP16S, pop_stride(N));
+    return (b + 255) & ~(size_t)255;
+}
+
 size_t set_bytes(const pflb_params* p, uint32_t N) {
-    return state_bytes(p->lattice, p->storage == PFLB_STORE_FP16S, pop_stride(N));
+    if (!has_open(p))
+        return state_bytes(p->lattice, p->storage == PFLB_STORE_FP16S, pop_stride(N));
+    return side_offset(p, N) + 2 * (size_t)side_stride(p) * 4;
 }
 
 size_t scratch_bytes() {
@@ -191,6 +227,12 @@ void derive(pflb_ctx* c) {
     }
     G.S = pop_stride(c->N);
     G.sxy = (uint32_t)G.nx * (uint32_t)G.ny;
+    G.open = 0;
+    const int zf = p.lattice == 19 ? 4 : 2;   // the z- face in the user's rows
+    if (p.open[zf]) G.open |= 16u;
+    if (p.open[zf + 1]) G.open |= 32u;
+    G.SL = side_stride(&p);
+    G.side_off = side_offset(&p, c->N);
     Model& m = c->L.m;
     const double tau_L = p.nu_L / kT + 0.5, tau_H = p.nu_H / kT + 0.5;
     const double tau_phi = p.M / kT + 0.5;
@@ -210,6 +252,8 @@ void derive(pflb_ctx* c) {
         m.gx = (float)p.g[0]; m.gy = 0.0f; m.gz = (float)p.g[1];
     }
     m.beta = p.hoc ? 1.0f : 0.0f;
+    m.Pf[0] = p.open[zf] ? (float)p.open_P[zf] : 0.0f;
+    m.Pf[1] = p.open[zf + 1] ? (float)p.open_P[zf + 1] : 0.0f;
     // wall faces and velocity components in internal axes (D2Q9: user y is internal z)
     m.moving = 0;
     m.wetting = 0;
@@ -272,13 +316,15 @@ struct FileHeader {
     int lattice, nx, ny, nz, bc[3], storage, scale_log2[2], hoc;
     double rho_L, rho_H, nu_L, nu_H, M, W, sigma, g[3], eps, dtheta_C;
     double wall_u[6][3], wet_cos[6];
+    int open[6];
+    double open_P[6];
     long long steps;
     unsigned long long set_bytes;
 };
 
 void fill_header(const pflb_ctx* c, FileHeader* h) {
     memset(h, 0, sizeof(*h));
-    memcpy(h->magic, "PFLBCK03", 8);
+    memcpy(h->magic, "PFLBCK04", 8);
     const pflb_params& p = c->p;
     h->lattice = p.lattice; h->nx = p.nx; h->ny = p.ny; h->nz = p.nz;
     for (int a = 0; a < 3; ++a) { h->bc[a] = p.bc[a]; h->g[a] = p.g[a]; }
@@ -291,6 +337,8 @@ void fill_header(const pflb_ctx* c, FileHeader* h) {
     for (int f = 0; f < 6; ++f) {
         for (int a = 0; a < 3; ++a) h->wall_u[f][a] = p.wall_u[f][a];
         h->wet_cos[f] = p.wet_cos[f];
+        h->open[f] = p.open[f];
+        h->open_P[f] = p.open[f] ? p.open_P[f] : 0.0;
     }
     h->steps = c->steps;
     h->set_bytes = set_bytes(&c->p, c->N);
@@ -744,7 +792,7 @@ extern "C" int pflb_step_many(pflb_ctx* const* c, int n, int nsteps, void* strea
     // differently).
     std::vector<pflb_ctx*> gr;
     for (int k = 0; k < n; ++k) {
-        if (!c[k]->L.m.moving && !c[k]->L.m.wetting && !c[k]->L.wide) {
+        if (!c[k]->L.m.moving && !c[k]->L.m.wetting && !c[k]->L.wide && !c[k]->L.G.open) {
             gr.push_back(c[k]);
         } else if ((r = pflb_step(c[k], nsteps, stream))) {
             if (c[k] != c[0]) fail(c[0], r, pflb_last_error(c[k]));

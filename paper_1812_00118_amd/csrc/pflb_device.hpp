@@ -101,6 +101,9 @@ struct Geom {
     int wx, wy, wz;     // 1: wall on both faces of the axis, 0: periodic
     uint32_t S;         // population stride of a set, in sites
     uint32_t sxy;       // nx * ny
+    uint32_t open;      // open (pressure) faces of the z axis: 16 z-, 32 z+ (wall bits)
+    uint32_t SL;        // stride of a face's side array, in sites (nx * ny rounded up)
+    size_t side_off;    // byte offset of the side arrays in a state buffer
 };
 
 struct Model {
@@ -117,6 +120,7 @@ struct Model {
     int moving;               // 1 if any wall moves
     float wk[6];              // wetting: (4/W) cos(contact angle) per face (internal)
     int wetting;              // 1 if any face has a contact angle other than 90 degrees
+    float Pf[2];              // pressure of the open z- and z+ faces
 };
 
 struct Codec {                // FP16S: power-of-two scales of the fp16 deviations
@@ -381,6 +385,7 @@ struct ZRow {
     uint32_t base;                 // z*nx*ny
     uint32_t dzm, dzp;
     uint32_t solid;                // bit4: z-1 beyond a wall, bit5: z+1
+    uint32_t open;                 // the bits of solid whose face is open
 };
 
 __device__ __forceinline__ Col make_col(const Geom& G, int x, int y) {
@@ -405,6 +410,7 @@ __device__ __forceinline__ ZRow make_zrow(const Geom& G, int z) {
     r.dzp = (z == G.nz - 1) ? 0u - (nz - 1u) * G.sxy : G.sxy;
     r.solid = 0;
     if (G.wz) r.solid = (z == 0 ? 16u : 0u) | (z == G.nz - 1 ? 32u : 0u);
+    r.open = r.solid & G.open;
     return r;
 }
 

@@ -202,6 +202,13 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                 pn[i] = sphi[(z + L::cz(i)) & 3][ty + OY + L::cy(i)][tx + 1 + L::cx(i)];
             });
             const Macro a = macros<L>(m, pn, gc);
+            if constexpr (XBC && (WS & WALLS_Z) != 0) {
+                // a site next to an open face keeps its pressure of this step for the
+                // populations that enter through the face (k_open)
+                if (r.open)
+                    reinterpret_cast<float*>(dst + G.side_off)[(r.open & 32u ? (size_t)G.SL : 0) +
+                                                               own.base] = a.P;
+            }
             const uint32_t solid = own.solid | r.solid;
             auto collide_to = [&](auto& out) {
                 if constexpr (WS == WALLS_NONE || !XBC) {
@@ -640,6 +647,85 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 }
 
 // ---------------------------------------------------------------------------
+// open (pressure) faces of the z axis, after a step has written dst.  A population i
+// that enters site x through an open face comes from the boundary-layer site s' = x -
+// c_i with its z put back into the layer, as its post-collision value there, and for g
+// plus 2 w_i (P_f - P(s'))/T: the ghost beyond the face copies the layer (zero normal
+// gradient of phi and u) with the pressure taken linearly to P_f at the face.  The step
+// stored that value's source slot (s', i), read by the site one plane inwards, and
+// treated the face as a wall: x reads the incoming value as the bounce-back of i, from
+// its own slot (x, opp(i)), which this kernel overwrites.  A population whose source
+// also crosses a closed x or y wall keeps its bounce-back.  The kernel reads slots that
+// move into the domain and writes slots that leave it, so no slot is both read and
+// written; every slot is still read exactly once by the next step.
+// One thread per site of a face, blockIdx.y = face (0: z-, 1: z+).
+// ---------------------------------------------------------------------------
+template <class L, class ST, int DIRZ>
+__device__ __forceinline__ void open_site(const Geom& G, const Model& m, const Codec& cd,
+                                          char* __restrict__ b, int x, int y, int face) {
+    const int z = face ? G.nz - 1 : 0;
+    const size_t S = G.S;
+    const size_t xs = site_of(G, x, y, z);
+    const float* Pside = reinterpret_cast<const float*>(b + G.side_off) + (face ? (size_t)G.SL : 0);
+    const float Pf = m.Pf[face];
+    MomF mx{};
+    if constexpr (ST::HALF)
+        mx = unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[xs]);
+    static_for<1, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::cz(i) == DIRZ) {
+            int sx = x - L::cx(i), sy = y - L::cy(i);
+            bool closed = false;
+            if (sx < 0 || sx >= G.nx) {
+                closed = closed || G.wx;
+                sx = sx < 0 ? sx + G.nx : sx - G.nx;
+            }
+            if (sy < 0 || sy >= G.ny) {
+                closed = closed || G.wy;
+                sy = sy < 0 ? sy + G.ny : sy - G.ny;
+            }
+            if (!closed) {
+                const size_t sp = site_of(G, sx, sy, z);          // s'
+                const float shift = 6.0f * L::w(i) * (Pf - Pside[(size_t)sy * G.nx + sx]);
+                if constexpr (!ST::HALF) {
+                    float2 v = reinterpret_cast<const float2*>(b)[(size_t)i * S + sp];
+                    v.y += shift;
+                    reinterpret_cast<float2*>(b)[(size_t)opp(i) * S + xs] = v;
+                } else {
+                    // decode with the reference of the slot's reader (one plane inwards),
+                    // encode with the one x applies to its bounce-back of i
+                    const size_t d = site_of(G, x, y, z + DIRZ);
+                    const MomF md =
+                        unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[d]);
+                    char* dev = b + StoreF16S::dev_off(G.S);
+                    const float2 q = __half22float2(
+                        reinterpret_cast<const __half2*>(dev + (size_t)(i - 1) * S * 4)[sp]);
+                    float rh, rg;
+                    ref_of<L, i>(md, rh, rg);
+                    const float hv = fmaf(q.x, cd.ish, rh);
+                    const float gv = fmaf(q.y, cd.isg, rg) + shift;
+                    ref_of<L, i>(mx, rh, rg);
+                    reinterpret_cast<__half2*>(dev + (size_t)(opp(i) - 1) * S * 4)[xs] =
+                        __halves2half2(__float2half_rn((hv - rh) * cd.sh),
+                                       __float2half_rn((gv - rg) * cd.sg));
+                }
+            }
+        }
+    });
+}
+
+template <class L, class ST>
+__global__ void __launch_bounds__(256) k_open(Geom G, Model m, Codec cd, char* __restrict__ b) {
+    const int face = blockIdx.y;
+    if (!(G.open & (face ? 32u : 16u))) return;
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= G.sxy) return;
+    const int y = (int)(t / (uint32_t)G.nx), x = (int)(t - (uint32_t)y * (uint32_t)G.nx);
+    if (face) open_site<L, ST, -1>(G, m, cd, b, x, y, 1);
+    else open_site<L, ST, 1>(G, m, cd, b, x, y, 0);
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 static inline dim3 grid1(uint32_t N) { return dim3((N + 255u) / 256u); }
@@ -682,8 +768,8 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
 template <class L, class ST, int WALLS>
 static hipError_t launch_step_t(const Launch& a, const StepArgs& x) {
     if constexpr ((WALLS & WALLS_XYZ) != WALLS_NONE) {
-        // moving walls or contact angles: one tile shape per lattice
-        if (a.m.moving || a.m.wetting) {
+        // moving walls, contact angles or open faces: one tile shape per lattice
+        if (a.m.moving || a.m.wetting || a.G.open) {
             if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, x);
             else return launch_tile<L, ST, WALLS, 64, 1, true>(a, x);
         }
@@ -736,9 +822,20 @@ static hipError_t dispatch_step(const Launch& a, const StepArgs& x) {
     return dispatch_walls<LatD2Q9, StoreF32>(a, x);
 }
 
+template <class L, class ST>
+static hipError_t open_t(const Launch& a, void* b) {
+    hipLaunchKernelGGL((k_open<L, ST>), dim3((a.G.sxy + 255u) / 256u, 2), dim3(256), 0, a.stream,
+                       a.G, a.m, a.cd, static_cast<char*>(b));
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const Launch& a, const void* src, void* dst) {
-    return dispatch_step(a, StepArgs{static_cast<const char*>(src), static_cast<char*>(dst),
-                                     nullptr, 0});
+    const hipError_t e = dispatch_step(
+        a, StepArgs{static_cast<const char*>(src), static_cast<char*>(dst), nullptr, 0});
+    if (e != hipSuccess || !a.G.open) return e;
+    if (a.q == 19)
+        return a.half ? open_t<LatD3Q19, StoreF16S>(a, dst) : open_t<LatD3Q19, StoreF32>(a, dst);
+    return a.half ? open_t<LatD2Q9, StoreF16S>(a, dst) : open_t<LatD2Q9, StoreF32>(a, dst);
 }
 
 hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n) {

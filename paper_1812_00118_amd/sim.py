@@ -65,8 +65,15 @@ class Sim:
             for k in range(6):
                 p.wet_cos[k] = wc[k]
         op = cfg.get("open_P")
-        if op is not None and not all(math.isnan(float(v)) for v in op):
-            raise ValueError("open (pressure) faces are not supported by the library")
+        if op is not None:
+            # faces with a finite pressure are open (NaN: a closed wall), rows as wall_u
+            op = [float(v) for v in np.asarray(op, dtype=np.float64).reshape(-1)]
+            if len(op) != 6:
+                raise ValueError("open_P: one value per face")
+            for k in range(6):
+                if not math.isnan(op[k]):
+                    p.open[k] = 1
+                    p.open_P[k] = op[k]
         self.params = p
         self.Q = p.lattice
         self.D = 3 if p.lattice == 19 else 2

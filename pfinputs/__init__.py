@@ -28,6 +28,11 @@ Workloads (lattice units, rho_L = 1):
                    wall, which prescribes a contact angle (rho_H = 10, nu = 0.1, M = 0.1,
                    W = 4, sigma = 0.05): the wetting check (not a case of the paper);
                    D3Q19 variant nx x nx x nz with a half ball on the z- wall.
+  dam_break        D3Q19 537x50x198 (Section 4.4's 537x198x50 with its height along z),
+                   no-slip walls, open top at P = 0, water column H = 100 by L = 200 (2 H;
+                   the text gives no length) against the x- wall, rho_H = 1000, g = 4e-6,
+                   W = 4, M = 0.02, nu_air = 8.3e-3, nu_water = 4.9e-6, sigma = 5.2e-3;
+                   hydrostatic start, P = 0 in the top layer.
   dense_bubble     D2Q9 80x40 periodic water (phi = 1) holding a dense bubble (a shallow
                    Gaussian dip, phi 0.93 at its centre, standard deviation 3 sites) and
                    a decent bubble (phi = 0 inside, R = 10) 40 sites apart; rho_H = 1000,
@@ -111,6 +116,19 @@ def droplet_impact(nx=256, ny=256, nz=128, R=32.0, film=16.0, U=0.05):
                 bc=(PERIODIC, PERIODIC, WALL), rho_L=1.0, rho_H=rho_H, nu_L=10.0 * nu_H,
                 nu_H=nu_H, M=0.1, W=4.0, sigma=sigma, g=(0.0, 0.0, 0.0), eps=1e-10,
                 hoc=1, dtheta_C=0.0, R=R, film=film, U=U, steps=5000)
+
+
+def dam_break(nx=537, ny=50, nz=198, H=100.0, L=200.0, g=4e-6):
+    """Section 4.4's dam break with the height along z: the paper's 537 x 198 x 50 box
+    (length, height, span) as nx x nz x ny here, since only z faces may be open.  No-slip
+    walls, an open top at P = 0, a water column of height H and length L (L is not in
+    the text; 2 H here) against the x- wall."""
+    nan = float("nan")
+    return dict(name="dam_break", lattice=19, shape=(nx, ny, nz),
+                bc=(WALL, WALL, WALL), rho_L=1.0, rho_H=1000.0, nu_L=8.3e-3,
+                nu_H=4.9e-6, M=0.02, W=4.0, sigma=5.2e-3, g=(0.0, 0.0, -g), eps=1e-10,
+                hoc=1, dtheta_C=0.0, open_P=[nan, nan, nan, nan, nan, 0.0], H=H, L=L,
+                steps=20000)
 
 
 def drops(seed, n=256):
@@ -280,13 +298,30 @@ def fields_sessile_drop(cfg):
     return _f32(phi), _f32(u), _f32(np.zeros_like(phi))
 
 
+def fields_dam_break(cfg):
+    """phi: the water column x < L, z < H (faces at L - 1/2 and H - 1/2) through the
+    tanh profile of its signed distance (Euclidean round the top corner); u = 0; P in
+    hydrostatic balance, 0 in the top layer."""
+    z, y, x = _grid(cfg["shape"])
+    dx = x - (cfg["L"] - 0.5)
+    dz = z - (cfg["H"] - 0.5)
+    out = np.sqrt(np.maximum(dx, 0.0) ** 2 + np.maximum(dz, 0.0) ** 2)
+    d = np.where((dx > 0) | (dz > 0), out, np.maximum(dx, dz))
+    phi = 0.5 - 0.5 * np.tanh(2.0 * d / cfg["W"])
+    u = np.zeros((3,) + phi.shape)
+    P = hydrostatic_pressure(cfg, phi)
+    P = P - P[-1:, :, :]
+    return _f32(phi), _f32(u), _f32(P)
+
+
 FIELDS = {"static_droplet": fields_static_droplet,
           "sessile_drop": fields_sessile_drop,
           "dense_bubble": fields_dense_bubble,
           "drops": fields_drops,
           "rayleigh_taylor": fields_rayleigh_taylor,
           "rising_bubble": fields_rising_bubble,
-          "droplet_impact": fields_droplet_impact}
+          "droplet_impact": fields_droplet_impact,
+          "dam_break": fields_dam_break}
 
 
 def fields(cfg):

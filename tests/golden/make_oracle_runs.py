@@ -33,11 +33,15 @@ from oracle import pflbm as O  # noqa: E402
 OUT = os.path.join(HERE, "oracle_runs")
 SOURCES = ("oracle/lattice.py", "oracle/pflbm.py")
 
-# reduced forms of the two D3Q19 workloads (walls in z, rho_H/rho_L = 1000)
+# reduced forms of the D3Q19 workloads (rho_H/rho_L = 1000)
 CASES = {
     "rising_bubble_24": (lambda: pfinputs.rising_bubble(n=24, R=5.0), 1000),
     "droplet_impact_36x28x30": (
         lambda: pfinputs.droplet_impact(nx=36, ny=28, nz=30, R=8.0, film=6.0), 1000),
+    # the dam break (walls, open top) at a fifth of its size, gravity raised five-fold
+    # so that the column collapses within the run
+    "dam_break_48x6x40": (
+        lambda: pfinputs.dam_break(nx=48, ny=6, nz=40, H=20.0, L=16.0, g=2e-5), 500),
 }
 
 

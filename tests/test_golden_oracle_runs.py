@@ -1,7 +1,7 @@
 """The stored oracle runs under tests/golden/oracle_runs (written by
 tests/golden/make_oracle_runs.py, which calls only the oracle and the input generators)
 belong to the sources in the tree, and their start and end satisfy what the method
-fixes: sum(phi) is conserved by the FP64 oracle to rounding."""
+fixes: sum(phi) is conserved by the FP64 oracle to rounding in a closed box."""
 import importlib.util
 import os
 
@@ -33,8 +33,12 @@ def test_oracle_run_fixture_is_current(name):
     assert int(d["steps"]) == steps
     nx, ny, nz = cfg["shape"]
     assert d["phi"].shape == (nz, ny, nx) and d["J"].shape == (3, nz, ny, nx)
-    # sum(phi) exact under the oracle's streaming with walls (bounce-back) and BGK
-    assert abs(float(d["mass1"]) - float(d["mass0"])) <= 1e-12 * float(d["mass0"])
+    if cfg.get("open_P") is None:
+        # sum(phi) exact under the oracle's streaming with walls (bounce-back) and BGK
+        assert abs(float(d["mass1"]) - float(d["mass0"])) <= 1e-12 * float(d["mass0"])
+    else:
+        # through an open face over light fluid (phi ~ 0 there) sum(phi) changes little
+        assert abs(float(d["mass1"]) - float(d["mass0"])) <= 1e-4 * float(d["mass0"])
     # the stored phi (float32) sums to the stored mass
     assert abs(d["phi"].astype(np.float64).sum() - float(d["mass1"])) <= 1e-6 * float(d["mass1"])
     assert np.isfinite(d["J"]).all() and np.isfinite(d["P"]).all()

@@ -120,6 +120,11 @@ def _params(**kw):
             p.wall_u[3 * v[0] + v[1]] = v[2]
         elif k == "wet":                       # (face, cos of the contact angle)
             p.wet_cos[v[0]] = v[1]
+        elif k == "open":                      # (face, pressure) of an open face
+            p.open[v[0]] = 1
+            p.open_P[v[0]] = v[1]
+        elif k == "open_flag":                 # (face, raw flag value)
+            p.open[v[0]] = v[1]
         else:
             setattr(p, k, v)
     return p
@@ -136,7 +141,19 @@ def _params(**kw):
                                  dict(lattice=9, nz=1, wall=(4, 0, 0.01)),
                                  dict(wet=(4, 1.5)), dict(wet=(5, float("nan"))),
                                  dict(wet=(0, 0.5)),
-                                 dict(lattice=9, nz=1, bc=(1, 1, 0), wet=(4, 0.5))])
+                                 dict(lattice=9, nz=1, bc=(1, 1, 0), wet=(4, 0.5)),
+                                 # open faces: z axis only (D2Q9: y), on a wall axis of
+                                 # at least 2 sites, finite pressure, no contact angle on
+                                 # the face, no moving wall anywhere, flag 0 or 1
+                                 dict(bc=(1, 0, 1), open=(0, 0.0)),
+                                 dict(bc=(0, 0, 0), open=(5, 0.0)),
+                                 dict(open=(5, float("nan"))), dict(open=(4, float("inf"))),
+                                 dict(open=(5, 0.0), wall=(4, 0, 0.01)),
+                                 dict(open=(5, 0.0), wet=(5, 0.5)),
+                                 dict(nz=1, open=(4, 0.0)),
+                                 dict(open_flag=(5, 2)),
+                                 dict(lattice=9, nz=1, bc=(1, 1, 0), open=(4, 0.0)),
+                                 dict(lattice=9, nz=1, ny=1, bc=(1, 1, 0), open=(3, 0.0))])
 def test_create_rejects_bad_params(L, bad):
     """tau <= 1/2 (nu <= 0), M/W <= 0, non-finite values, bad enums, D2Q9 with nz != 1,
     domains beyond 2^32 - 64 sites, wall velocities on periodic faces, normal to
@@ -164,6 +181,24 @@ def test_create_accepts_contact_angles_on_wall_faces(L, wet):
     ctx = ctypes.c_void_p()
     assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
     L.pflb_destroy(ctx)
+
+
+@pytest.mark.parametrize("kw", [dict(open=(5, 0.0)), dict(open=(4, -0.01), wet=(5, 0.3)),
+                                dict(lattice=9, nz=1, bc=(1, 1, 0), open=(3, 0.02)),
+                                dict(lattice=9, nz=1, bc=(0, 1, 0), open=(2, 0.0))])
+def test_create_accepts_open_faces(L, kw):
+    """Open z faces (D2Q9: y faces); the state buffers grow by the two boundary layers'
+    pressures (one float per layer site, layers of stride rounded up to 64 sites)."""
+    p = _params(**kw)
+    ctx = ctypes.c_void_p()
+    assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    L.pflb_destroy(ctx)
+    closed = _params(**{k: v for k, v in kw.items() if k != "open"})
+    layer = p.nx * (p.ny if p.lattice == 19 else 1)
+    side = 2 * 4 * ((layer + 63) // 64 * 64)
+    base = L.pflb_required_bytes(ctypes.byref(closed), 0)
+    assert L.pflb_required_bytes(ctypes.byref(p), 0) == (base + 255) // 256 * 256 + side
+    assert L.pflb_required_bytes(ctypes.byref(p), 2) == L.pflb_required_bytes(ctypes.byref(closed), 2)
 
 
 def test_required_bytes_and_unbound_errors(L):
