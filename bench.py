@@ -592,6 +592,25 @@ def main():
                       f"({r5['kernel_ms'] / rest:.3f}x the 90-degree-wall step)",
                       file=sys.stderr, flush=True)
             out["contact_angles"] = blk
+            # Section 4.4's dam break (its 537 x 198 x 50 box with the height along z):
+            # the XBC step variant, which also stores the boundary layer's pressure,
+            # and the open-face kernel after each step
+            cfg6 = pfinputs.dam_break()
+            n6 = 537 * 50 * 198
+            blk = {"workload": "dam_break D3Q19 537x50x198 (the paper's 537x198x50, height "
+                               "along z; no-slip walls, open top at P 0, water column H 100 "
+                               "by 200, rho 1000, nu_water 4.9e-6, nu_air 8.3e-3, g 4e-6, "
+                               "W 4, M 0.02, sigma 5.2e-3)"}
+            for st in ("fp32", "fp16s"):
+                r6 = time_storage(cfg6, st, max(50, args.steps // 4), args.warmup)
+                blk[st] = {"mlups": round(n6 / (r6["kernel_ms"] * 1e-3) / 1e6, 1),
+                           "kernel_ms": round(r6["kernel_ms"], 4),
+                           "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * n6 /
+                                                 (r6["kernel_ms"] * 1e-3) / 1e9, 1),
+                           "nonfinite": r6["nonfinite"]}
+                print(f"[bench] dam_break {st}: {r6['kernel_ms']:.4f} ms/step",
+                      file=sys.stderr, flush=True)
+            out["dam_break"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu

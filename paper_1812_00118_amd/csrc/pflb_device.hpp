@@ -385,7 +385,6 @@ struct ZRow {
     uint32_t base;                 // z*nx*ny
     uint32_t dzm, dzp;
     uint32_t solid;                // bit4: z-1 beyond a wall, bit5: z+1
-    uint32_t open;                 // the bits of solid whose face is open
 };
 
 __device__ __forceinline__ Col make_col(const Geom& G, int x, int y) {
@@ -410,7 +409,6 @@ __device__ __forceinline__ ZRow make_zrow(const Geom& G, int z) {
     r.dzp = (z == G.nz - 1) ? 0u - (nz - 1u) * G.sxy : G.sxy;
     r.solid = 0;
     if (G.wz) r.solid = (z == 0 ? 16u : 0u) | (z == G.nz - 1 ? 32u : 0u);
-    r.open = r.solid & G.open;
     return r;
 }
 

@@ -55,8 +55,12 @@ struct StepTable<true> {
     StepBatch bt;
 };
 
+// The FP16S XBC variants are held to two waves per SIMD: they need a few registers
+// more than 256 and would otherwise run one wave per SIMD; the spills this costs are
+// cheaper (measured: all-wall boxes with contact angles or moving walls 1.7-1.9x faster).
 template <class L, class ST, int TX, int TY, int WALLS, bool XBC, bool BATCHED>
 __global__ void __launch_bounds__(TX * TY)
+__attribute__((amdgpu_waves_per_eu(XBC && ST::HALF ? 2 : 1)))
 k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
        const char* __restrict__ src, char* __restrict__ dst, StepTable<BATCHED> tab) {
     static_assert(!(BATCHED && XBC), "contexts with moving walls or contact angles are stepped one by one");
@@ -202,13 +206,6 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                 pn[i] = sphi[(z + L::cz(i)) & 3][ty + OY + L::cy(i)][tx + 1 + L::cx(i)];
             });
             const Macro a = macros<L>(m, pn, gc);
-            if constexpr (XBC && (WS & WALLS_Z) != 0) {
-                // a site next to an open face keeps its pressure of this step for the
-                // populations that enter through the face (k_open)
-                if (r.open)
-                    reinterpret_cast<float*>(dst + G.side_off)[(r.open & 32u ? (size_t)G.SL : 0) +
-                                                               own.base] = a.P;
-            }
             const uint32_t solid = own.solid | r.solid;
             auto collide_to = [&](auto& out) {
                 if constexpr (WS == WALLS_NONE || !XBC) {
@@ -651,10 +648,10 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 // that enters site x through an open face comes from the boundary-layer site s' = x -
 // c_i with its z put back into the layer, as its post-collision value there, and for g
 // plus 2 w_i (P_f - P(s'))/T: the ghost beyond the face copies the layer (zero normal
-// gradient of phi and u) with the pressure taken linearly to P_f at the face.  The step
-// stored that value's source slot (s', i), read by the site one plane inwards, and
-// treated the face as a wall: x reads the incoming value as the bounce-back of i, from
-// its own slot (x, opp(i)), which this kernel overwrites.  A population whose source
+// gradient of phi and u) with the pressure taken linearly to P_f at the face (P(s') from
+// k_open_P).  The step stored that value's source slot (s', i), read by the site one
+// plane inwards, and treated the face as a wall: x reads the incoming value as the
+// bounce-back of i, from its own slot (x, opp(i)), which this kernel overwrites.  A population whose source
 // also crosses a closed x or y wall keeps its bounce-back.  The kernel reads slots that
 // move into the domain and writes slots that leave it, so no slot is both read and
 // written; every slot is still read exactly once by the next step.
@@ -714,6 +711,61 @@ __device__ __forceinline__ void open_site(const Geom& G, const Model& m, const C
     });
 }
 
+// Pressure of the boundary-layer sites of the open faces at the step just taken, from
+// the zeroth moments of g before (gathered from src) and after (the slots dst holds) the
+// collision: Eq. 6 gives sum g^eq = P/T - sum K/2, the filtered part has no zeroth
+// moment, so sum g* = P/T + sum K/2; with P = T sum g + T rho_dif u.grad(phi)/2 and
+// sum K = rho_dif u.grad(phi) (Eq. 7; Gamma has moments 1 and u) the two sums average
+// to P/T.  One thread per site of a face, blockIdx.y = face.
+template <class L, class ST, int WALLS>
+__global__ void __launch_bounds__(256) k_open_P(Geom G, Codec cd, const char* __restrict__ src,
+                                                char* __restrict__ dst) {
+    const int face = blockIdx.y;
+    if (!(G.open & (face ? 32u : 16u))) return;
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= G.sxy) return;
+    const int y = (int)(t / (uint32_t)G.nx), x = (int)(t - (uint32_t)y * (uint32_t)G.nx);
+    const int z = face ? G.nz - 1 : 0;
+    const Col c = make_col(G, x, y);
+    const ZRow r = make_zrow(G, z);
+    float h[L::Q], g[L::Q];
+    pull_site<L, ST, WALLS>(src, G, c, r, cd, h, g);
+    double pre = 0.0, post = 0.0;
+    static_for<0, L::Q>([&](auto I) { pre += (double)g[decltype(I)::value]; });
+    const size_t S = G.S;
+    const size_t s = site_of(G, x, y, z);
+    if constexpr (!ST::HALF) {
+        static_for<0, L::Q>([&](auto I) {
+            post += (double)reinterpret_cast<const float2*>(dst)[(size_t)decltype(I)::value * S + s].y;
+        });
+    } else {
+        // each slot decodes with its reader's reference: the site c_I away, or the site
+        // itself (reference of opp(I)) where c_I leaves through a wall
+        const uint4* mom = reinterpret_cast<const uint4*>(dst + StoreF16S::mom_off(G.S));
+        const MomF own = unpack_mom(mom[s]);
+        post = (double)reinterpret_cast<const float2*>(dst)[s].y;
+        const uint32_t solid = c.solid | r.solid;
+        static_for<1, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const float2 q = __half22float2(reinterpret_cast<const __half2*>(
+                dst + StoreF16S::dev_off(G.S) + (size_t)(i - 1) * S * 4)[s]);
+            float rh, rg;
+            if (dest_beyond<L, i, WALLS>(solid)) {
+                ref_of<L, opp(i)>(own, rh, rg);
+            } else {
+                int dx = x + L::cx(i), dy = y + L::cy(i), dz = z + L::cz(i);
+                dx = dx < 0 ? dx + G.nx : (dx >= G.nx ? dx - G.nx : dx);
+                dy = dy < 0 ? dy + G.ny : (dy >= G.ny ? dy - G.ny : dy);
+                dz = dz < 0 ? dz + G.nz : (dz >= G.nz ? dz - G.nz : dz);
+                ref_of<L, i>(unpack_mom(mom[site_of(G, dx, dy, dz)]), rh, rg);
+            }
+            post += (double)fmaf(q.y, cd.isg, rg);
+        });
+    }
+    reinterpret_cast<float*>(dst + G.side_off)[(face ? (size_t)G.SL : 0) + t] =
+        (float)((pre + post) * (1.0 / 6.0));
+}
+
 template <class L, class ST>
 __global__ void __launch_bounds__(256) k_open(Geom G, Model m, Codec cd, char* __restrict__ b) {
     const int face = blockIdx.y;
@@ -768,8 +820,8 @@ static hipError_t launch_tile(const Launch& a, const StepArgs& x) {
 template <class L, class ST, int WALLS>
 static hipError_t launch_step_t(const Launch& a, const StepArgs& x) {
     if constexpr ((WALLS & WALLS_XYZ) != WALLS_NONE) {
-        // moving walls, contact angles or open faces: one tile shape per lattice
-        if (a.m.moving || a.m.wetting || a.G.open) {
+        // moving walls or contact angles: one tile shape per lattice
+        if (a.m.moving || a.m.wetting) {
             if constexpr (L::USES_Y) return launch_tile<L, ST, WALLS, 64, 4, true>(a, x);
             else return launch_tile<L, ST, WALLS, 64, 1, true>(a, x);
         }
@@ -822,10 +874,20 @@ static hipError_t dispatch_step(const Launch& a, const StepArgs& x) {
     return dispatch_walls<LatD2Q9, StoreF32>(a, x);
 }
 
+// open faces, after a step src -> dst: the boundary layers' pressures, then the
+// populations entering through the faces
 template <class L, class ST>
-static hipError_t open_t(const Launch& a, void* b) {
-    hipLaunchKernelGGL((k_open<L, ST>), dim3((a.G.sxy + 255u) / 256u, 2), dim3(256), 0, a.stream,
-                       a.G, a.m, a.cd, static_cast<char*>(b));
+static hipError_t open_t(const Launch& a, const void* src, void* dst) {
+    const dim3 grid((a.G.sxy + 255u) / 256u, 2);
+    const char* s = static_cast<const char*>(src);
+    char* d = static_cast<char*>(dst);
+    if (a.wide)
+        hipLaunchKernelGGL((k_open_P<L, ST, WALLS_XYZ | ADDR64>), grid, dim3(256), 0, a.stream,
+                           a.G, a.cd, s, d);
+    else
+        hipLaunchKernelGGL((k_open_P<L, ST, WALLS_XYZ>), grid, dim3(256), 0, a.stream, a.G, a.cd,
+                           s, d);
+    hipLaunchKernelGGL((k_open<L, ST>), grid, dim3(256), 0, a.stream, a.G, a.m, a.cd, d);
     return hipGetLastError();
 }
 
@@ -834,8 +896,9 @@ hipError_t launch_step(const Launch& a, const void* src, void* dst) {
         a, StepArgs{static_cast<const char*>(src), static_cast<char*>(dst), nullptr, 0});
     if (e != hipSuccess || !a.G.open) return e;
     if (a.q == 19)
-        return a.half ? open_t<LatD3Q19, StoreF16S>(a, dst) : open_t<LatD3Q19, StoreF32>(a, dst);
-    return a.half ? open_t<LatD2Q9, StoreF16S>(a, dst) : open_t<LatD2Q9, StoreF32>(a, dst);
+        return a.half ? open_t<LatD3Q19, StoreF16S>(a, src, dst)
+                      : open_t<LatD3Q19, StoreF32>(a, src, dst);
+    return a.half ? open_t<LatD2Q9, StoreF16S>(a, src, dst) : open_t<LatD2Q9, StoreF32>(a, src, dst);
 }
 
 hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n) {
