@@ -35,7 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # the float32 rest populations of both sets and an fp16 moments word of 8 values, and
 # per moving population one fp16 deviation per set)
 BYTES_PER_SITE = {("19", "fp32"): 2 * 2 * 19 * 4, ("19", "fp16s"): 2 * (8 + 16 + 18 * 4),
-                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * (8 + 16 + 8 * 4)}
+                  ("9", "fp32"): 2 * 2 * 9 * 4, ("9", "fp16s"): 2 * (8 + 16 + 8 * 4),
+                  # in place: the phi pass reads the Q h values and writes phi, the step
+                  # reads phi and both sets and writes both sets
+                  ("19", "fp32_inplace"): 19 * 4 + 4 + 4 + 2 * 2 * 19 * 4,
+                  ("9", "fp32_inplace"): 9 * 4 + 4 + 4 + 2 * 2 * 9 * 4}
+# device bytes of the state per site (both buffers of the pull storages, one in place)
+STATE_BYTES = {"fp32": 2 * 19 * 8, "fp16s": 2 * (8 + 16 + 18 * 4), "fp32_inplace": 19 * 8}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_rising_bubble_traffic.txt")
 CSRC = os.path.join(ROOT, "paper_1812_00118_amd", "csrc")
 
@@ -149,10 +155,11 @@ def largest_domain_block(steps=20, warmup=5):
                        "memory holds (state, the start's work buffer and fields), x,y "
                        "periodic, z walls, R 64"}
     dev = torch.device("cuda")
-    for st in ("fp32", "fp16s"):
-        # two state buffers, the 2 Q N floats of the start's work, phi and u (16 B), and
-        # the temporaries of building phi
-        per_site = 2 * BYTES_PER_SITE[("19", st)] // 2 + 2 * 19 * 4 + 16 + 24
+    for st in ("fp32", "fp16s", "fp32_inplace"):
+        # the state, the 2 Q N floats of the start's work (none in place, where the
+        # equilibria go straight into the state; the phi field instead), phi and u
+        # (16 B), and the temporaries of building phi
+        per_site = STATE_BYTES[st] + (4 if st == "fp32_inplace" else 2 * 19 * 4) + 16 + 24
         free = torch.cuda.mem_get_info()[0]
         nz = int(0.92 * free / per_site / (nx * ny))
         nz = min(nz, (2 ** 32 - 64) // (nx * ny))
@@ -183,7 +190,7 @@ def largest_domain_block(steps=20, warmup=5):
         _, bad = sim.mass()
         ms = e0.elapsed_time(e1) / steps
         blk[st] = {"shape": [nx, ny, nz], "sites": n, "addr64": n > 2 ** 28 - 64,
-                   "state_GB": round(2 * BYTES_PER_SITE[("19", st)] // 2 * n / 1e9, 1),
+                   "state_GB": round(STATE_BYTES[st] * n / 1e9, 1),
                    "mlups": round(n / (ms * 1e-3) / 1e6, 1), "kernel_ms": round(ms, 3),
                    "achieved_GBs": round(BYTES_PER_SITE[("19", st)] * n / (ms * 1e-3) / 1e9, 1),
                    "nonfinite": bad}
@@ -611,6 +618,20 @@ def main():
                 print(f"[bench] dam_break {st}: {r6['kernel_ms']:.4f} ms/step",
                       file=sys.stderr, flush=True)
             out["dam_break"] = blk
+            # in-place storage (one state buffer) on the headline workload
+            blk = {"workload": desc[args.workload] + ", in-place FP32 storage",
+                   "bytes_per_site": BYTES_PER_SITE[("19", "fp32_inplace")]}
+            r7 = time_storage(cfg, "fp32_inplace", max(50, args.steps // 4), args.warmup)
+            blk.update({"mlups": round(N / (r7["kernel_ms"] * 1e-3) / 1e6, 1),
+                        "kernel_ms": round(r7["kernel_ms"], 4),
+                        "achieved_GBs": round(BYTES_PER_SITE[("19", "fp32_inplace")] * N /
+                                              (r7["kernel_ms"] * 1e-3) / 1e9, 1),
+                        "time_vs_pull_fp32": round(r7["kernel_ms"] /
+                                                   (ms if args.storage == "fp32" else oms), 3),
+                        "nonfinite": r7["nonfinite"]})
+            print(f"[bench] in-place fp32: {r7['kernel_ms']:.4f} ms/step",
+                  file=sys.stderr, flush=True)
+            out["inplace"] = blk
         if not args.no_surrogate:
             out["surrogate"] = surrogate_block(args.sur_train_steps)
         out["cpu_baseline"] = cpu

@@ -56,6 +56,11 @@ extern "C" {
                                /* an fp16 deviation from the first-order equilibrium */
                                /* of its reading site's previous moments (FP32      */
                                /* arithmetic throughout)                             */
+#define PFLB_STORE_FP32_INPLACE 2  /* float32 in one state buffer, streamed in place */
+                               /* (half the footprint of PFLB_STORE_FP32; not in the */
+                               /* paper): each step reads and writes the same slots  */
+                               /* of a site, alternating two layouts, after a pass   */
+                               /* that writes the phi field into the scratch buffer */
 
 /* buffer ids for pflb_required_bytes / pflb_bind.  A state buffer holds both
  * distribution sets (FP32: float2 (h_i, g_i) per slot, [Q][S]; FP16S: per site the
@@ -64,7 +69,12 @@ extern "C" {
  * population, [Q-1][S], decoded as w_i (sum h + 3 c_i . sum c h) + dev_h / 2^scale_h
  * and likewise for g, with the moments of the site that reads the slot); the step
  * reads one state buffer and writes the other.  The FP16S moments and deviations must
- * stay within the fp16 range (|sum g|, |sum c g| < 65504; |dev| 2^scale < 65504). */
+ * stay within the fp16 range (|sum g|, |sum c g| < 65504; |dev| 2^scale < 65504).
+ * PFLB_STORE_FP32_INPLACE uses PFLB_BUF_STATE0 only (Q float arrays of h, then Q of g,
+ * [2Q][S]; after an even number of steps since the state was set f_i(x) is in slot
+ * (x, i), after an odd number in slot (x - c_i, opp(i)), or in slot (x, i) where x - c_i
+ * lies beyond a wall); its PFLB_BUF_STATE1 needs 0 bytes and may be NULL, and its
+ * scratch buffer also holds the phi field (N floats). */
 #define PFLB_BUF_STATE0  0
 #define PFLB_BUF_STATE1  1
 #define PFLB_BUF_SCRATCH 2     /* reduction partial sums and flags                  */
@@ -88,7 +98,10 @@ extern "C" {
  *   dtheta_C     C of the dense-bubble correction (Eq. 14, with F = -1 where |phi - 1/2|
  *                > 0.35 and (phi - 1/2) lap(phi) > 0, else 0); 0 switches it off, 10
  *                diffuses dense bubbles away
- *   storage      PFLB_STORE_FP32 or PFLB_STORE_FP16S
+ *   storage      PFLB_STORE_FP32, PFLB_STORE_FP16S or PFLB_STORE_FP32_INPLACE (the
+ *                last without moving walls or open faces; its contexts are stepped one
+ *                by one by pflb_step_many and not taken by the batched read-out and
+ *                hand-over of the surrogate's guard)
  *   scale_log2   power-of-two scale exponents of the fp16 deviations of h and g
  *                (FP16S only; each in [-14, 24])
  *   wall_u       velocity of each wall face, rows x-, x+, y-, y+, z-, z+ and columns
@@ -162,8 +175,8 @@ const char* pflb_last_error(const pflb_ctx* ctx);
 size_t pflb_required_bytes(const pflb_params* p, int buffer);
 
 /* Bind the PFLB_NBUF caller-allocated device buffers, in PFLB_BUF_* order, each at
- * least pflb_required_bytes() long and 256-byte aligned.  The pointers are borrowed
- * until pflb_destroy or the next pflb_bind. */
+ * least pflb_required_bytes() long and 256-byte aligned (a buffer that needs 0 bytes
+ * may be NULL).  The pointers are borrowed until pflb_destroy or the next pflb_bind. */
 int pflb_bind(pflb_ctx* ctx, void* const* dev_ptrs, int n);
 
 /* Pre-collision equilibrium distributions from macroscopic fields (the paper does
@@ -180,7 +193,8 @@ int pflb_set_state(pflb_ctx* ctx, const float* h, const float* g, void* stream);
 int pflb_get_state(pflb_ctx* ctx, float* h, float* g, void* stream);
 
 /* Start from macroscopic fields: pflb_equilibrium into `work` (2*Q*N floats of
- * caller device memory) followed by pflb_set_state. */
+ * caller device memory) followed by pflb_set_state.  With PFLB_STORE_FP32_INPLACE the
+ * equilibria are written straight into the state and `work` is not used (may be NULL). */
 int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const float* P,
                      float* work, void* stream);
 
@@ -190,6 +204,7 @@ int pflb_init_fields(pflb_ctx* ctx, const float* phi, const float* u, const floa
  * two kernels held in a fixed device array of the library instead of a work buffer.
  *   Limit: 2*Q*N*4 <= PFLB_NOALLOC_SCRATCH_BYTES (64 MiB: N <= 441,505 D3Q19 sites,
  *   932,067 D2Q9 sites); larger domains return PFLB_ERR_PARAM and change nothing.
+ *   Contexts with PFLB_STORE_FP32_INPLACE stage nothing and have no such limit.
  *   The call allocates nothing (no hipMalloc, no library allocation).  The array is
  *   one per GPU, held from its first use on that GPU until the process ends, and
  *   shared by every call on that GPU: calls on one GPU that overlap in time (other

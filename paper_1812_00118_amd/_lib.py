@@ -12,7 +12,7 @@ ERRORS = {-1: "PFLB_ERR_PARAM", -2: "PFLB_ERR_ALIGN", -3: "PFLB_ERR_UNBOUND",
 ERR_NONFINITE = -5
 
 BC_PERIODIC, BC_WALL = 0, 1
-STORE_FP32, STORE_FP16S = 0, 1
+STORE_FP32, STORE_FP16S, STORE_FP32_INPLACE = 0, 1, 2
 NBUF = 3
 
 

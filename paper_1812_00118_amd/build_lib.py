@@ -9,7 +9,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpflb.so")
 
-SOURCES = ["pflb_kernels.hip", "pflb_api.hip", "sur_kernels.hip", "sur_api.hip"]
+SOURCES = ["pflb_kernels.hip", "pflb_inplace.hip", "pflb_api.hip", "sur_kernels.hip",
+           "sur_api.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

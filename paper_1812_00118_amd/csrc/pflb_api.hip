@@ -70,8 +70,9 @@ std::string check_params(const pflb_params* p) {
         if (!finite(p->g[a])) return "gravity must be finite";
     if (p->hoc != 0 && p->hoc != 1) return "hoc must be 0 or 1";
     if (!finite(p->dtheta_C)) return "dtheta_C must be finite";
-    if (p->storage != PFLB_STORE_FP32 && p->storage != PFLB_STORE_FP16S)
-        return "storage must be PFLB_STORE_FP32 or PFLB_STORE_FP16S";
+    if (p->storage != PFLB_STORE_FP32 && p->storage != PFLB_STORE_FP16S &&
+        p->storage != PFLB_STORE_FP32_INPLACE)
+        return "storage must be PFLB_STORE_FP32, PFLB_STORE_FP16S or PFLB_STORE_FP32_INPLACE";
     if (p->storage == PFLB_STORE_FP16S)
         for (int k = 0; k < 2; ++k)
             if (p->scale_log2[k] < -14 || p->scale_log2[k] > 24) return "scale_log2 out of [-14, 24]";
@@ -110,6 +111,8 @@ std::string check_params(const pflb_params* p) {
         if (p->wet_cos[f] != 0.0) return "a contact angle given for an open face";
     }
     if (any_open && any_moving) return "moving walls and open faces together are not supported";
+    if (p->storage == PFLB_STORE_FP32_INPLACE && (any_open || any_moving))
+        return "in-place storage has no moving walls or open faces";
     return "";
 }
 
@@ -143,6 +146,14 @@ size_t scratch_bytes() {
     const size_t b = mass_scratch_bytes();
     return (b + 65535) & ~(size_t)65535;
 }
+
+// in-place storage: the phi field follows the reduction scratch
+size_t scratch_bytes(const pflb_params* p, uint32_t N) {
+    if (p->storage != PFLB_STORE_FP32_INPLACE) return scratch_bytes();
+    return scratch_bytes() + (size_t)pop_stride(N) * 4;
+}
+
+bool inplace(const pflb_params* p) { return p->storage == PFLB_STORE_FP32_INPLACE; }
 
 uint32_t sites(const pflb_params* p) { return (uint32_t)p->nx * p->ny * p->nz; }
 
@@ -284,6 +295,7 @@ void derive(pflb_ctx* c) {
     }
     c->L.q = p.lattice;
     c->L.half = p.storage == PFLB_STORE_FP16S;
+    c->L.inplace = p.storage == PFLB_STORE_FP32_INPLACE;
     c->L.tile = 0;
     const char* tenv = getenv("PFLB_TILE");
     if (tenv && atoi(tenv) >= 0 && atoi(tenv) <= 3) c->L.tile = atoi(tenv);
@@ -308,8 +320,24 @@ int need_bound(pflb_ctx* c) {
     return PFLB_OK;
 }
 
-void* state(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1]; }
+// In-place storage keeps its state in buffer 0 and `cur` is then its layout (the parity
+// of the steps since the state was set).
+void* state(pflb_ctx* c) {
+    if (c->L.inplace) return c->buf[PFLB_BUF_STATE0];
+    return c->buf[c->cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1];
+}
+// the buffer a pull-storage step writes
 void* other(pflb_ctx* c) { return c->buf[c->cur == 0 ? PFLB_BUF_STATE1 : PFLB_BUF_STATE0]; }
+float* phi_field(pflb_ctx* c) {
+    return reinterpret_cast<float*>(static_cast<char*>(c->buf[PFLB_BUF_SCRATCH]) + scratch_bytes());
+}
+
+// one step of context c on stream st from its current buffer or layout `cur`
+hipError_t launch_one(pflb_ctx* c, const Launch& a, int cur) {
+    if (c->L.inplace) return launch_step_inplace(a, c->buf[PFLB_BUF_STATE0], cur, phi_field(c));
+    return launch_step(a, c->buf[cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1],
+                       c->buf[cur == 0 ? PFLB_BUF_STATE1 : PFLB_BUF_STATE0]);
+}
 
 struct FileHeader {
     char magic[8];
@@ -318,13 +346,14 @@ struct FileHeader {
     double wall_u[6][3], wet_cos[6];
     int open[6];
     double open_P[6];
+    int layout;               // in-place storage: the layout of the saved state
     long long steps;
     unsigned long long set_bytes;
 };
 
 void fill_header(const pflb_ctx* c, FileHeader* h) {
     memset(h, 0, sizeof(*h));
-    memcpy(h->magic, "PFLBCK04", 8);
+    memcpy(h->magic, "PFLBCK05", 8);
     const pflb_params& p = c->p;
     h->lattice = p.lattice; h->nx = p.nx; h->ny = p.ny; h->nz = p.nz;
     for (int a = 0; a < 3; ++a) { h->bc[a] = p.bc[a]; h->g[a] = p.g[a]; }
@@ -340,6 +369,7 @@ void fill_header(const pflb_ctx* c, FileHeader* h) {
         h->open[f] = p.open[f];
         h->open_P[f] = p.open[f] ? p.open_P[f] : 0.0;
     }
+    h->layout = c->L.inplace ? c->cur : 0;
     h->steps = c->steps;
     h->set_bytes = set_bytes(&c->p, c->N);
 }
@@ -356,8 +386,9 @@ int pflb_create(const pflb_params* p, pflb_ctx** out) {
     if (!c) return PFLB_ERR_NOMEM;
     c->p = *p;
     derive(c);
-    c->bytes[PFLB_BUF_STATE0] = c->bytes[PFLB_BUF_STATE1] = set_bytes(p, c->N);
-    c->bytes[PFLB_BUF_SCRATCH] = scratch_bytes();
+    c->bytes[PFLB_BUF_STATE0] = set_bytes(p, c->N);
+    c->bytes[PFLB_BUF_STATE1] = inplace(p) ? 0 : set_bytes(p, c->N);
+    c->bytes[PFLB_BUF_SCRATCH] = scratch_bytes(p, c->N);
     *out = c;
     return PFLB_OK;
 }
@@ -373,10 +404,12 @@ size_t pflb_required_bytes(const pflb_params* p, int buffer) {
     if (!check_params(p).empty()) return 0;
     const uint32_t N = sites(p);
     switch (buffer) {
-        case PFLB_BUF_STATE0: case PFLB_BUF_STATE1:
+        case PFLB_BUF_STATE0:
             return set_bytes(p, N);
+        case PFLB_BUF_STATE1:
+            return inplace(p) ? 0 : set_bytes(p, N);
         case PFLB_BUF_SCRATCH:
-            return scratch_bytes();
+            return scratch_bytes(p, N);
         default:
             return 0;
     }
@@ -386,6 +419,7 @@ int pflb_bind(pflb_ctx* c, void* const* dev_ptrs, int n) {
     if (!c) return PFLB_ERR_PARAM;
     if (!dev_ptrs || n != PFLB_NBUF) return fail(c, PFLB_ERR_PARAM, "pflb_bind needs PFLB_NBUF pointers");
     for (int k = 0; k < n; ++k) {
+        if (!dev_ptrs[k] && c->bytes[k] == 0) continue;      // a buffer that needs no bytes
         if (!dev_ptrs[k]) return fail(c, PFLB_ERR_PARAM, "NULL buffer pointer");
         if (!aligned(dev_ptrs[k])) return fail(c, PFLB_ERR_ALIGN, "buffer not 256-byte aligned");
     }
@@ -414,7 +448,8 @@ int pflb_set_state(pflb_ctx* c, const float* h, const float* g, void* stream) {
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
     c->cur = 0;
-    hipError_t e = launch_set_state(a, c->N, h, g, state(c));
+    hipError_t e = c->L.inplace ? launch_set_state_inplace(a, c->N, h, g, state(c))
+                                : launch_set_state(a, c->N, h, g, state(c));
     if (e != hipSuccess) return hip_fail(c, e, "set_state launch");
     c->steps = 0;
     return PFLB_OK;
@@ -426,8 +461,25 @@ int pflb_get_state(pflb_ctx* c, float* h, float* g, void* stream) {
     if (!h || !g) return fail(c, PFLB_ERR_PARAM, "NULL distribution pointer");
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
-    hipError_t e = launch_get_state(a, c->N, state(c), h, g);
+    hipError_t e = c->L.inplace ? launch_get_state_inplace(a, c->N, state(c), c->cur, h, g)
+                                : launch_get_state(a, c->N, state(c), h, g);
     if (e != hipSuccess) return hip_fail(c, e, "get_state launch");
+    return PFLB_OK;
+}
+
+// In-place storage: layout 0 is the equilibrium kernel's output format with stride S,
+// so the equilibria are written straight into the state (no staging, no work buffer).
+static int init_inplace(pflb_ctx* c, const float* phi, const float* u, const float* P,
+                        void* stream) {
+    if (!phi || !u) return fail(c, PFLB_ERR_PARAM, "NULL field pointer");
+    Launch a = c->L;
+    a.stream = (hipStream_t)stream;
+    float* h = static_cast<float*>(state(c));
+    float* g = h + (size_t)c->Q * c->L.G.S;
+    c->cur = 0;
+    hipError_t e = launch_equilibrium(a, c->N, phi, u, P, h, g, c->L.G.S);
+    if (e != hipSuccess) return hip_fail(c, e, "equilibrium launch");
+    c->steps = 0;
     return PFLB_OK;
 }
 
@@ -435,6 +487,7 @@ int pflb_init_fields(pflb_ctx* c, const float* phi, const float* u, const float*
                      void* stream) {
     int r = need_bound(c);
     if (r) return r;
+    if (c->L.inplace) return init_inplace(c, phi, u, P, stream);
     if (!work) return fail(c, PFLB_ERR_PARAM, "NULL work buffer");
     float* h = work;
     float* g = work + (size_t)c->Q * c->N;
@@ -489,6 +542,7 @@ int pflb_init_fields_noalloc(pflb_ctx* c, const float* phi, const float* u, cons
     int r = need_bound(c);
     if (r) return r;
     if (!phi || !u) return fail(c, PFLB_ERR_PARAM, "NULL field pointer");
+    if (c->L.inplace) return init_inplace(c, phi, u, P, stream);
     const size_t need = (size_t)2 * c->Q * c->N * sizeof(float);
     if (need > (size_t)PFLB_NOALLOC_SCRATCH_BYTES)
         return fail(c, PFLB_ERR_PARAM,
@@ -521,7 +575,7 @@ int pflb_step(pflb_ctx* c, int nsteps, void* stream) {
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
     for (int s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(a, state(c), other(c));
+        hipError_t e = launch_one(c, a, c->cur);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->cur ^= 1;
         c->steps += 1;
@@ -547,9 +601,7 @@ int pflb_step_graph(pflb_ctx* c, int nsteps, void* stream) {
         int cur = c->cur;
         hipError_t le = hipSuccess;
         for (int k = 0; k < nsteps && le == hipSuccess; ++k) {
-            void* src = c->buf[cur == 0 ? PFLB_BUF_STATE0 : PFLB_BUF_STATE1];
-            void* dst = c->buf[cur == 0 ? PFLB_BUF_STATE1 : PFLB_BUF_STATE0];
-            le = launch_step(a, src, dst);
+            le = launch_one(c, a, cur);
             cur ^= 1;
         }
         e = hipStreamEndCapture(st, &g);
@@ -579,7 +631,8 @@ int pflb_read(pflb_ctx* c, float* phi, float* P, float* J, float* u, void* strea
     if (!phi) return fail(c, PFLB_ERR_PARAM, "phi output is required");
     Launch a = c->L;
     a.stream = (hipStream_t)stream;
-    hipError_t e = launch_read(a, c->N, state(c), phi, P, J, u);
+    hipError_t e = c->L.inplace ? launch_read_inplace(a, c->N, state(c), c->cur, phi, P, J, u)
+                                : launch_read(a, c->N, state(c), phi, P, J, u);
     if (e != hipSuccess) return hip_fail(c, e, "read launch");
     return PFLB_OK;
 }
@@ -648,7 +701,9 @@ int pflb_load(pflb_ctx* c, const char* path, void* stream) {
         return fail(c, PFLB_ERR_IO, "short checkpoint header");
     }
     const long long steps = h.steps;
+    const int layout = h.layout;
     h.steps = want.steps;
+    if (c->L.inplace && (layout == 0 || layout == 1)) h.layout = want.layout;
     if (memcmp(&h, &want, sizeof(h)) != 0) {
         fclose(f);
         return fail(c, PFLB_ERR_PARAM, "checkpoint parameters differ from the context's");
@@ -664,7 +719,7 @@ int pflb_load(pflb_ctx* c, const char* path, void* stream) {
     const bool ok = fread(host.data(), 1, nb, f) == nb;
     fclose(f);
     if (!ok) return fail(c, PFLB_ERR_IO, "short checkpoint body");
-    c->cur = 0;
+    c->cur = c->L.inplace ? layout : 0;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(state(c), host.data(), nb, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -701,7 +756,7 @@ int check_many(pflb_ctx* const* c, int n) {
         if (!c[k]->bound) return fail(c[0], PFLB_ERR_UNBOUND, "context in a batch is not bound");
         const Launch& a = c[0]->L;
         const Launch& b = c[k]->L;
-        if (b.q != a.q || b.half != a.half || b.G.nx != a.G.nx || b.G.ny != a.G.ny ||
+        if (b.q != a.q || b.half != a.half || b.inplace != a.inplace || b.G.nx != a.G.nx || b.G.ny != a.G.ny ||
             b.G.nz != a.G.nz || b.G.wx != a.G.wx || b.G.wy != a.G.wy || b.G.wz != a.G.wz)
             return fail(c[0], PFLB_ERR_PARAM,
                         "contexts of a batch must share lattice, storage, sizes and walls");
@@ -715,6 +770,8 @@ int pflb_read_many(pflb_ctx* const* c, int n, float* const* phi, float* const* P
                    float* const* J, hipStream_t st) {
     int r = check_many(c, n);
     if (r) return r;
+    if (c[0]->L.inplace)
+        return fail(c[0], PFLB_ERR_PARAM, "batched read-out takes contexts with pull storage");
     if (!phi) return fail(c[0], PFLB_ERR_PARAM, "phi outputs are required");
     for (int k0 = 0; k0 < n; k0 += BATCH_MAX) {
         const int nb = n - k0 < BATCH_MAX ? n - k0 : BATCH_MAX;
@@ -746,6 +803,8 @@ int pflb_reconstruct_many(pflb_ctx* const* c, int n, const float* const* phi,
                           hipStream_t st) {
     int r = check_many(c, n);
     if (r) return r;
+    if (c[0]->L.inplace)
+        return fail(c[0], PFLB_ERR_PARAM, "the hand-over takes contexts with pull storage");
     if (!phi || !J || !work) return fail(c[0], PFLB_ERR_PARAM, "NULL field or work pointer");
     if (advance < 0) return fail(c[0], PFLB_ERR_PARAM, "advance < 0");
     const size_t per = (size_t)2 * c[0]->Q * c[0]->N;   // floats of work per context
@@ -792,7 +851,8 @@ extern "C" int pflb_step_many(pflb_ctx* const* c, int n, int nsteps, void* strea
     // differently).
     std::vector<pflb_ctx*> gr;
     for (int k = 0; k < n; ++k) {
-        if (!c[k]->L.m.moving && !c[k]->L.m.wetting && !c[k]->L.wide && !c[k]->L.G.open) {
+        if (!c[k]->L.m.moving && !c[k]->L.m.wetting && !c[k]->L.wide && !c[k]->L.G.open &&
+            !c[k]->L.inplace) {
             gr.push_back(c[k]);
         } else if ((r = pflb_step(c[k], nsteps, stream))) {
             if (c[k] != c[0]) fail(c[0], r, pflb_last_error(c[k]));

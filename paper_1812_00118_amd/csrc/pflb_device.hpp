@@ -175,11 +175,20 @@ struct StepBatch {
 // ---------------------------------------------------------------------------
 struct StoreF32 {
     static constexpr bool HALF = false;
+    static constexpr bool INPLACE = false;
+    __host__ __device__ static constexpr size_t bytes_per_site(int q) { return (size_t)q * 8; }
+};
+
+// FP32 in place (one buffer): Q arrays of h, then Q arrays of g, each of stride S floats
+struct StoreF32InPlace {
+    static constexpr bool HALF = false;
+    static constexpr bool INPLACE = true;
     __host__ __device__ static constexpr size_t bytes_per_site(int q) { return (size_t)q * 8; }
 };
 
 struct StoreF16S {
     static constexpr bool HALF = true;
+    static constexpr bool INPLACE = false;
     __host__ __device__ static constexpr size_t bytes_per_site(int q) {
         return 8 + 16 + (size_t)(q - 1) * 4;
     }
@@ -833,6 +842,43 @@ struct SiteWriter16 {
         store_nt(b + elem_off<WALLS, 8>(site), (T - Sout) + D, g0);
     }
 };
+
+// ---------------------------------------------------------------------------
+// site coordinates and the phi stencil from a phi field (the non-hot kernels)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void site_coords(const Geom& G, uint32_t s, int& x, int& y, int& z) {
+    z = (int)(s / G.sxy);
+    const uint32_t r = s - (uint32_t)z * G.sxy;
+    y = (int)(r / (uint32_t)G.nx);
+    x = (int)(r - (uint32_t)y * (uint32_t)G.nx);
+}
+
+__device__ __forceinline__ uint32_t site_of(const Geom& G, int x, int y, int z) {
+    return (uint32_t)z * G.sxy + (uint32_t)y * (uint32_t)G.nx + (uint32_t)x;
+}
+
+// phi(x + c_k) for all k from a phi field, with the ghost rules (mirror, wetting)
+template <class L>
+__device__ __forceinline__ void phi_stencil(const Geom& G, const Model& m,
+                                            const float* __restrict__ phi,
+                                            int x, int y, int z, float (&pn)[L::Q]) {
+    static_for<0, L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const int vx = x + L::cx(i), vy = y + L::cy(i), vz = z + L::cz(i);
+        const int xx = map_coord(vx, G.nx, G.wx);
+        const int yy = map_coord(vy, G.ny, G.wy);
+        const int zz = map_coord(vz, G.nz, G.wz);
+        pn[i] = phi[site_of(G, xx, yy, zz)];
+        if (m.wetting) pn[i] = wet_ghost(G, m, vx, vy, vz, pn[i]);
+    });
+}
+
+// user vector component a (0..D-1) -> internal axis
+template <class L>
+__device__ __forceinline__ int user_axis(int a) {
+    if constexpr (L::USES_Y) return a;
+    return a == 0 ? 0 : 2;
+}
 
 // float64 phi as hi + lo floats
 __device__ __forceinline__ float split_hi_lo(double s, float& lo) {

@@ -15,6 +15,7 @@ struct Launch {
     int bz;             // planes per workgroup in the fused step
     int tile;           // D3Q19 tile shape: 0: 64x4, 1: 64x8, 2: 32x8, 3: 32x4
     bool wide;          // more than 2^28 - 64 sites: 64-bit slot addresses
+    bool inplace;       // FP32 in-place storage: one state buffer, layout by step parity
     Geom G;
     Model m;
     Codec cd;
@@ -25,8 +26,9 @@ hipError_t launch_step(const Launch& a, const void* src, void* dst);
 // one step of n <= BATCH_MAX contexts without moving walls or contact angles
 // (blockIdx.y = context)
 hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n);
+// h, g: Q arrays of stride hs (0: N) each
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
-                              const float* P, float* h, float* g);
+                              const float* P, float* h, float* g, size_t hs = 0);
 hipError_t launch_set_state(const Launch& a, uint32_t N, const float* h, const float* g,
                             void* b);
 hipError_t launch_get_state(const Launch& a, uint32_t N, const void* b, float* h, float* g);
@@ -34,6 +36,19 @@ hipError_t launch_read(const Launch& a, uint32_t N, const void* b, float* phi, f
                        float* J, float* U);
 hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch);
 size_t state_bytes(int q, bool half, uint32_t S);
+
+// In-place storage (one state buffer).  Layout 0 holds f_i(x) in slot (x, i); layout 1
+// holds it in slot (x - c_i, opp(i)), or in slot (x, i) where x - c_i lies beyond a wall.
+// A step from layout L reads and writes the same slots of each site and leaves layout
+// 1 - L; phi (N floats) is the phi field of the state, written by the step's first
+// kernel and read by its second.
+hipError_t launch_step_inplace(const Launch& a, void* b, int layout, float* phi);
+hipError_t launch_set_state_inplace(const Launch& a, uint32_t N, const float* h, const float* g,
+                                    void* b);
+hipError_t launch_get_state_inplace(const Launch& a, uint32_t N, const void* b, int layout,
+                                    float* h, float* g);
+hipError_t launch_read_inplace(const Launch& a, uint32_t N, const void* b, int layout, float* phi,
+                               float* P, float* J, float* U);
 
 // Batched launches over contexts that share the lattice, the storage and the geometry
 // (blockIdx.y = context); per-context pointers and constants go by value in the kernel

@@ -240,43 +240,6 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
 
 
 // ---------------------------------------------------------------------------
-// per-site helpers for the non-hot kernels
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void site_coords(const Geom& G, uint32_t s, int& x, int& y, int& z) {
-    z = (int)(s / G.sxy);
-    const uint32_t r = s - (uint32_t)z * G.sxy;
-    y = (int)(r / (uint32_t)G.nx);
-    x = (int)(r - (uint32_t)y * (uint32_t)G.nx);
-}
-
-__device__ __forceinline__ uint32_t site_of(const Geom& G, int x, int y, int z) {
-    return (uint32_t)z * G.sxy + (uint32_t)y * (uint32_t)G.nx + (uint32_t)x;
-}
-
-// phi(x + c_k) for all k from a phi field, with the ghost rules (mirror, wetting)
-template <class L>
-__device__ __forceinline__ void phi_stencil(const Geom& G, const Model& m,
-                                            const float* __restrict__ phi,
-                                            int x, int y, int z, float (&pn)[L::Q]) {
-    static_for<0, L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const int vx = x + L::cx(i), vy = y + L::cy(i), vz = z + L::cz(i);
-        const int xx = map_coord(vx, G.nx, G.wx);
-        const int yy = map_coord(vy, G.ny, G.wy);
-        const int zz = map_coord(vz, G.nz, G.wz);
-        pn[i] = phi[site_of(G, xx, yy, zz)];
-        if (m.wetting) pn[i] = wet_ghost(G, m, vx, vy, vz, pn[i]);
-    });
-}
-
-// user vector component a (0..D-1) -> internal axis
-template <class L>
-__device__ __forceinline__ int user_axis(int a) {
-    if constexpr (L::USES_Y) return a;
-    return a == 0 ? 0 : 2;
-}
-
-// ---------------------------------------------------------------------------
 // equilibrium start and hand-over.  Each kernel body is a per-site function, called by
 // a single-context kernel (parameters by value) and by a batched kernel whose
 // blockIdx.y picks one context of a Batch (same lattice, storage and geometry).
@@ -296,14 +259,15 @@ __device__ __forceinline__ float inv_rho_prime(const Model& m, const float (&pn)
 }
 
 // pre-collision equilibria of site s from phi, P (NULL: 0) and the velocity, given as
-// u or (u == NULL) as the momentum J
+// u or (u == NULL) as the momentum J; direction i of h and g at i * hs + s
 template <class L>
 __device__ __forceinline__ void equilibrium_site(const Geom& G, const Model& m, uint32_t N,
                                                  uint32_t s, const float* __restrict__ phi,
                                                  const float* __restrict__ u,
                                                  const float* __restrict__ J,
                                                  const float* __restrict__ P,
-                                                 float* __restrict__ h, float* __restrict__ g) {
+                                                 float* __restrict__ h, float* __restrict__ g,
+                                                 size_t hs) {
     int x, y, z;
     site_coords(G, s, x, y, z);
     float pn[L::Q];
@@ -327,8 +291,8 @@ __device__ __forceinline__ void equilibrium_site(const Geom& G, const Model& m, 
         float hdev, geq, K;
         eq_dir<L, i>(a, t, hdev, geq, K);
         if constexpr (i == 0) hdev = fmaf(a.phi, kappa<L>(), hdev);
-        h[(size_t)i * N + s] = fmaf(a.phi, L::w(i), hdev);
-        g[(size_t)i * N + s] = geq;
+        h[(size_t)i * hs + s] = fmaf(a.phi, L::w(i), hdev);
+        g[(size_t)i * hs + s] = geq;
     });
 }
 
@@ -336,10 +300,10 @@ template <class L>
 __global__ void __launch_bounds__(256)
 k_equilibrium(Geom G, Model m, uint32_t N, const float* __restrict__ phi,
               const float* __restrict__ u, const float* __restrict__ P,
-              float* __restrict__ h, float* __restrict__ g) {
+              float* __restrict__ h, float* __restrict__ g, size_t hs) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     if (s >= N) return;
-    equilibrium_site<L>(G, m, N, s, phi, u, nullptr, P, h, g);
+    equilibrium_site<L>(G, m, N, s, phi, u, nullptr, P, h, g, hs);
 }
 
 // hand-over: equilibria from (phi, P, J) of context blockIdx.y into its work (h, then g)
@@ -349,7 +313,7 @@ __global__ void __launch_bounds__(256) k_equilibrium_j_b(Geom G, uint32_t N, Bat
     if (s >= N) return;
     const BatchEnt& e = bt.e[blockIdx.y];
     equilibrium_site<L>(G, e.m, N, s, e.phi, nullptr, e.J, e.P, e.work,
-                        e.work + (size_t)L::Q * N);
+                        e.work + (size_t)L::Q * N, N);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,7 +535,16 @@ template <class L, class ST, int WALLS>
 __device__ __forceinline__ double slot_sum(const Geom& G, const char* b, uint32_t s,
                                            const Codec& cd, bool& bad) {
     double acc = 0.0;
-    if constexpr (!ST::HALF) {
+    if constexpr (ST::INPLACE) {
+        // in-place layouts: every slot is read exactly once by the next step as well
+        const float* f = reinterpret_cast<const float*>(b);
+        static_for<0, L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const float hv = f[(size_t)i * G.S + s], gv = f[(size_t)(L::Q + i) * G.S + s];
+            bad |= !isfinite(hv) || !isfinite(gv);
+            acc += (double)hv;
+        });
+    } else if constexpr (!ST::HALF) {
         // FP32: the slots of site s in storage order (each slot is gathered once)
         static_for<0, L::Q>([&](auto I) {
             const float2 v =
@@ -908,16 +881,17 @@ hipError_t launch_step_batch(const Launch& a, const StepBatch& bt, int n) {
 
 template <class L>
 static hipError_t equilibrium_t(const Launch& a, uint32_t N, const float* phi, const float* u,
-                                const float* P, float* h, float* g) {
+                                const float* P, float* h, float* g, size_t hs) {
     hipLaunchKernelGGL((k_equilibrium<L>), grid1(N), dim3(256), 0, a.stream, a.G, a.m, N, phi,
-                       u, P, h, g);
+                       u, P, h, g, hs);
     return hipGetLastError();
 }
 
 hipError_t launch_equilibrium(const Launch& a, uint32_t N, const float* phi, const float* u,
-                              const float* P, float* h, float* g) {
-    return a.q == 19 ? equilibrium_t<LatD3Q19>(a, N, phi, u, P, h, g)
-                     : equilibrium_t<LatD2Q9>(a, N, phi, u, P, h, g);
+                              const float* P, float* h, float* g, size_t hs) {
+    if (hs == 0) hs = N;
+    return a.q == 19 ? equilibrium_t<LatD3Q19>(a, N, phi, u, P, h, g, hs)
+                     : equilibrium_t<LatD2Q9>(a, N, phi, u, P, h, g, hs);
 }
 
 template <class L, class ST>
@@ -1060,6 +1034,9 @@ static hipError_t mass_t(const Launch& a, uint32_t N, const void* b, void* scrat
 }
 
 hipError_t launch_mass(const Launch& a, uint32_t N, const void* b, void* scratch) {
+    if (a.inplace)
+        return a.q == 19 ? mass_t<LatD3Q19, StoreF32InPlace>(a, N, b, scratch)
+                         : mass_t<LatD2Q9, StoreF32InPlace>(a, N, b, scratch);
     if (a.q == 19)
         return a.half ? mass_t<LatD3Q19, StoreF16S>(a, N, b, scratch)
                       : mass_t<LatD3Q19, StoreF32>(a, N, b, scratch);

@@ -6,7 +6,7 @@ import numpy as np
 import torch
 
 from ._lib import (BC_PERIODIC, BC_WALL, ERR_NONFINITE, NBUF, Params, PflbError,
-                   STORE_FP16S, STORE_FP32, lib)
+                   STORE_FP16S, STORE_FP32, STORE_FP32_INPLACE, lib)
 
 _BC = {"periodic": BC_PERIODIC, "wall": BC_WALL, BC_PERIODIC: BC_PERIODIC, BC_WALL: BC_WALL}
 
@@ -47,7 +47,8 @@ class Sim:
         p.eps = float(cfg.get("eps", 1e-10))
         p.hoc = int(cfg.get("hoc", 1))
         p.dtheta_C = float(cfg.get("dtheta_C", 0.0))
-        p.storage = {"fp32": STORE_FP32, "fp16s": STORE_FP16S}[storage]
+        p.storage = {"fp32": STORE_FP32, "fp16s": STORE_FP16S,
+                     "fp32_inplace": STORE_FP32_INPLACE}[storage]
         sl = scale_log2 if scale_log2 is not None else default_scales(p.rho_H)
         p.scale_log2[0], p.scale_log2[1] = int(sl[0]), int(sl[1])
         wu = cfg.get("wall_u")
@@ -132,7 +133,8 @@ class Sim:
         u_t = self._dev(np.asarray(u)[:self.D] if not torch.is_tensor(u) else u[:self.D],
                         (self.D,) + self.shape)
         P_t = self._dev(P, self.shape) if P is not None else None
-        if self._work is None:
+        if self._work is None and self.params.storage != STORE_FP32_INPLACE:
+            # in-place storage takes the equilibria straight into its state
             self._work = torch.empty(2 * self.Q * self.N, device=self.device)
         self._check(self.L.pflb_init_fields(self.ctx, _ptr(phi_t), _ptr(u_t), _ptr(P_t),
                                             _ptr(self._work), self._stream()))
