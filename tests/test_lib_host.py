@@ -201,6 +201,33 @@ def test_create_accepts_open_faces(L, kw):
     assert L.pflb_required_bytes(ctypes.byref(p), 2) == L.pflb_required_bytes(ctypes.byref(closed), 2)
 
 
+def test_inplace_storage_buffers(L):
+    """In-place storage: one state buffer of the FP32 size, no second one (NULL binds),
+    the phi field in the scratch buffer; moving walls and open faces are refused."""
+    p = _params(storage=2)
+    fp32 = _params()
+    N = 8 * 8 * 8
+    assert L.pflb_required_bytes(ctypes.byref(p), 0) == L.pflb_required_bytes(ctypes.byref(fp32), 0)
+    assert L.pflb_required_bytes(ctypes.byref(p), 1) == 0
+    assert (L.pflb_required_bytes(ctypes.byref(p), 2) ==
+            L.pflb_required_bytes(ctypes.byref(fp32), 2) + 4 * N)
+    ctx = ctypes.c_void_p()
+    assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
+    try:
+        arr = (ctypes.c_void_p * 3)(4096 * 256, None, 8192 * 256)
+        assert L.pflb_bind(ctx, arr, 3) == 0
+        arr = (ctypes.c_void_p * 3)(None, None, 8192 * 256)
+        assert L.pflb_bind(ctx, arr, 3) == -1            # the state buffer is needed
+    finally:
+        L.pflb_destroy(ctx)
+    for bad in (dict(storage=2, wall=(5, 0, 0.01)), dict(storage=2, open=(5, 0.0)),
+                dict(storage=3)):
+        q = _params(**bad)
+        c = ctypes.c_void_p(1)
+        assert L.pflb_create(ctypes.byref(q), ctypes.byref(c)) == -1
+        assert not c.value
+
+
 def test_required_bytes_and_unbound_errors(L):
     p = _params()
     ctx = ctypes.c_void_p()
