@@ -69,6 +69,30 @@ int pfsur_get_params(pfsur_ctx* ctx, float* host);
  * activations plus the backward buffers). */
 size_t pfsur_workspace_bytes(const pfsur_cfg* cfg, int batch, int training);
 
+/* Where 3x3 layer `layer` (0..16, network order as listed above) reads and writes its
+ * activations in the workspace of (cfg, batch, training), so that a caller can inspect
+ * every layer's BF16 activations after pfsur_forward or a training step.  All buffers
+ * are NHWC BF16 at the resolution (H >> level, W >> level) of their level.
+ *   in_off      byte offset of the input buffer, or (size_t)-1 for the network input x
+ *   in_cs/in_c0 its channel stride and the first channel the layer reads (Cin of them)
+ *   in_mode     0: read at the layer's resolution; 1: nearest 2x upsampling of a buffer
+ *               at level + 1; 2: the 2x2 averages of the level above, already stored
+ *               compact at the layer's resolution by the producing layer
+ *   out_off, out_cs, out_c0   the output buffer (SiLU activations, Cout channels); at
+ *               inference the last layer's activations are not stored (its epilogue
+ *               feeds the 1x1 head straight away)
+ *   pool_off, pool_cs   the buffer that also receives the 2x2 averages of the output
+ *               (BF16 of 0.25 (((a(y,x) + a(y,x+1)) + a(y+1,x)) + a(y+1,x+1)) of the stored
+ *               BF16 activations, summed in float32), or (size_t)-1
+ * Returns PFLB_OK or PFLB_ERR_PARAM (invalid cfg, batch or layer). */
+typedef struct pfsur_layer_io {
+    size_t in_off, out_off, pool_off;
+    int in_cs, in_c0, in_mode, out_cs, out_c0, pool_cs;
+    int Cin, Cout, level;
+} pfsur_layer_io;
+int pfsur_layer_io_of(const pfsur_cfg* cfg, int batch, int training, int layer,
+                      pfsur_layer_io* out);
+
 /* Pack a batch of solver fields into the network input x (BF16 NHWC, PFSUR_IN_CH).  The
  * network works with the velocity u = J / rho(phi), rho(phi) = rho_L + clamp(phi, 0, 1)
  * (rho_H - rho_L), not with the momentum J, whose values span the density ratio: channels

@@ -41,6 +41,14 @@ class Params(ctypes.Structure):
                 ("open_P", ctypes.c_double * 6)]
 
 
+class LayerIO(ctypes.Structure):
+    _fields_ = [("in_off", ctypes.c_size_t), ("out_off", ctypes.c_size_t),
+                ("pool_off", ctypes.c_size_t),
+                ("in_cs", ctypes.c_int), ("in_c0", ctypes.c_int), ("in_mode", ctypes.c_int),
+                ("out_cs", ctypes.c_int), ("out_c0", ctypes.c_int), ("pool_cs", ctypes.c_int),
+                ("Cin", ctypes.c_int), ("Cout", ctypes.c_int), ("level", ctypes.c_int)]
+
+
 class SurCfg(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("in_shift", ctypes.c_float * 4), ("in_scale", ctypes.c_float * 4),
@@ -78,6 +86,8 @@ _SIGS = {
     "pfsur_set_params": (ctypes.c_int, [_vp, _vp]),
     "pfsur_get_params": (ctypes.c_int, [_vp, _vp]),
     "pfsur_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(SurCfg), ctypes.c_int, ctypes.c_int]),
+    "pfsur_layer_io_of": (ctypes.c_int, [ctypes.POINTER(SurCfg), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(LayerIO)]),
     "pfsur_pack": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_int, _vp, _vp]),
     "pfsur_pack_target": (ctypes.c_int, [_vp] * 7 + [ctypes.POINTER(ctypes.c_double),

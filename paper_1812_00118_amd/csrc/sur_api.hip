@@ -511,6 +511,37 @@ size_t pfsur_workspace_bytes(const pfsur_cfg* cfg, int batch, int training) {
     return make_plan(cfg->H, cfg->W, batch, training != 0).total;
 }
 
+int pfsur_layer_io_of(const pfsur_cfg* cfg, int batch, int training, int layer,
+                      pfsur_layer_io* out) {
+    if (!out || !check_cfg(cfg).empty() || batch < 1 || batch > cfg->max_batch || layer < 0 ||
+        layer >= NL)
+        return PFLB_ERR_PARAM;
+    const Plan p = make_plan(cfg->H, cfg->W, batch, training != 0);
+    const LayerDef& L = LAYERS[layer];
+    const size_t none = ~(size_t)0;
+    memset(out, 0, sizeof(*out));
+    if (L.pool_in >= 0) {          // the compact 2x2 averages the producing layer stored
+        out->in_off = p.act[L.pool_in];
+        out->in_cs = BUFS[L.pool_in].C;
+        out->in_c0 = 0;
+        out->in_mode = 2;
+    } else {
+        out->in_off = L.in_buf == X ? none : p.act[L.in_buf];
+        out->in_cs = BUFS[L.in_buf].C;
+        out->in_c0 = L.in_c0;
+        out->in_mode = L.mode == MODE_UP ? 1 : 0;
+    }
+    out->out_off = p.act[L.out_buf];
+    out->out_cs = BUFS[L.out_buf].C;
+    out->out_c0 = L.out_c0;
+    out->pool_off = L.pool_out >= 0 ? p.act[L.pool_out] : none;
+    out->pool_cs = L.pool_out >= 0 ? BUFS[L.pool_out].C : 0;
+    out->Cin = L.Cin;
+    out->Cout = L.Cout;
+    out->level = L.level;
+    return PFLB_OK;
+}
+
 int pfsur_pack(pfsur_ctx* c, const float* phi, const float* P, const float* J, const double* rho,
                int batch, void* x, void* stream) {
     int r = check_batch(c, batch);

@@ -96,6 +96,32 @@ class Surrogate:
         off = (-t.data_ptr()) % 256
         return ctypes.c_void_p(t.data_ptr() + off)
 
+    def layer_io(self, batch, training, layer):
+        """Where 3x3 layer `layer` reads and writes its activations in the workspace of
+        (batch, training): a dict of the pfsur_layer_io fields (offsets in bytes from the
+        workspace's start, None for the network input and for no pooled copy)."""
+        from ._lib import LayerIO
+        io = LayerIO()
+        rc = self.L.pfsur_layer_io_of(ctypes.byref(self.cfg), int(batch), int(training),
+                                      int(layer), ctypes.byref(io))
+        if rc != 0:
+            raise PflbError(rc, "pfsur_layer_io_of")
+        none = (1 << (8 * ctypes.sizeof(ctypes.c_size_t))) - 1
+        d = {f: getattr(io, f) for f, _ in LayerIO._fields_}
+        for k in ("in_off", "pool_off"):
+            if d[k] == none:
+                d[k] = None
+        return d
+
+    def workspace_tensor(self, batch, training):
+        """The workspace of (batch, training) as a uint8 tensor starting at the address
+        the library is given."""
+        ptr = self.workspace(batch, training).value
+        t = self._ws[(int(batch), bool(training))]
+        off = ptr - t.data_ptr()
+        n = int(self.L.pfsur_workspace_bytes(ctypes.byref(self.cfg), int(batch), int(training)))
+        return t[off:off + n]
+
     def release_workspaces(self):
         self._ws = {}
 

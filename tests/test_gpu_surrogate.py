@@ -170,6 +170,80 @@ def test_network_forward_matches_reference(net_case):
     assert np.abs(out - ref).max() <= 0.1 * np.abs(ref).max()
 
 
+def _ws_bf16(ws, off, B, H, W, C):
+    """An NHWC BF16 buffer of the workspace as float64 (B, H, W, C)."""
+    n = B * H * W * C
+    t = ws[off:off + 2 * n].view(torch.bfloat16).float().cpu().numpy()
+    return t.astype(np.float64).reshape(B, H, W, C)
+
+
+def test_network_layers_elementwise_at_full_depth(sur_mod):
+    """Every layer of the inference forward, element by element, at full depth: each
+    3x3 layer's stored BF16 activations against SiLU(conv) of the FP64 reference applied
+    to the BF16 input the GPU itself stored for it (upsampling and the compact pooled
+    input included), within BF16 output rounding (2^-8 |a|, the half-ulp of a value on
+    either side of a power of two) plus the FP32 accumulation bound (K - 1) 2^-24
+    sum|terms| carried through SiLU (slope <= 1.1); every pooled copy equal, bit for bit,
+    to BF16 of the float32 2x2 average of the stored activations in the stated order;
+    and the 1x1 head, fed by the last layer's BF16-rounded activations in its epilogue,
+    against the reference head on the reference activations (rounding decisions at the
+    BF16 boundary bounded by one BF16 ulp per channel)."""
+    rng = np.random.default_rng(21)
+    params = {k: (bf16(w), bf16(b)) for k, (w, b) in U.init_weights(13).items()}
+    B, H, W = 2, 64, 64
+    x = np.zeros((B, H, W, U.IN_CH))
+    x[..., :5] = bf16(rng.standard_normal((B, H, W, 5)))
+    s = sur_mod.Surrogate(H, W, B, NORM)
+    s.set_params(flat_params(params))
+    out = s.forward(dev_bf16(x)).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    ws = s.workspace_tensor(B, False)
+    names = [n for n, *_ in U.LAYERS]
+    worst = 0.0
+    for l, name in enumerate(names):
+        io = s.layer_io(B, False, l)
+        lv, cin, cout = io["level"], io["Cin"], io["Cout"]
+        Hl, Wl = H >> lv, W >> lv
+        if io["in_off"] is None:
+            xin = x.copy()
+        elif io["in_mode"] == 1:
+            buf = _ws_bf16(ws, io["in_off"], B, Hl // 2, Wl // 2, io["in_cs"])
+            xin = U.upsample2(buf[..., io["in_c0"]:io["in_c0"] + cin])
+        else:
+            buf = _ws_bf16(ws, io["in_off"], B, Hl, Wl, io["in_cs"])
+            xin = buf[..., io["in_c0"]:io["in_c0"] + cin]
+        w, b = params[name]
+        z = U.conv3x3(xin, w, b)
+        zabs = U.conv3x3(np.abs(xin), np.abs(w), np.abs(b))
+        a = U.silu(z)
+        K = 9 * cin + 1
+        # BF16 rounding of the output (at most 2^-8 |a|), the FP32 evaluation of SiLU
+        # (a few ulp: 1e-5 |a| is ample) and the accumulation bound through SiLU
+        tol = (2.0 ** -8 + 1e-5) * np.abs(a) + 1.1 * (K - 1) * U32 * zabs + 1e-30
+        if l == len(names) - 1:
+            # inference: the last layer's activations feed the head in its epilogue
+            wh, bh = params["head"]
+            ref = bf16(a) @ wh[:, 0, 0, :].T + bh
+            ulp = (2.0 ** -7 + 1e-5) * np.abs(a) + 1.1 * (K - 1) * U32 * zabs
+            htol = ulp @ np.abs(wh[:, 0, 0, :]).T + 32 * U32 * (np.abs(bf16(a)) @ np.abs(wh[:, 0, 0, :]).T + np.abs(bh))
+            err = np.abs(out - ref)
+            assert (err <= htol).all(), (name, err.max(), int((err > htol).sum()))
+            worst = max(worst, float((err / np.maximum(htol, 1e-30)).max()))
+            continue
+        obuf = _ws_bf16(ws, io["out_off"], B, Hl, Wl, io["out_cs"])
+        got = obuf[..., io["out_c0"]:io["out_c0"] + cout]
+        err = np.abs(got - a)
+        assert (err <= tol).all(), (name, err.max(), int((err > tol).sum()))
+        worst = max(worst, float((err / tol).max()))
+        if io["pool_off"] is not None:
+            pb = _ws_bf16(ws, io["pool_off"], B, Hl // 2, Wl // 2, io["pool_cs"])[..., :cout]
+            g32 = got.astype(np.float32)
+            avg = np.float32(0.25) * (((g32[:, 0::2, 0::2] + g32[:, 0::2, 1::2]) +
+                                       g32[:, 1::2, 0::2]) + g32[:, 1::2, 1::2])
+            assert np.array_equal(pb, bf16(avg)), name
+    print(f"\nlargest error / bound over the 17 layers and the head: {worst:.3f}")
+
+
 def test_network_gradients_match_reference(net_case):
     s, params, x, y = net_case
     g, loss = s.gradients(dev_bf16(x), torch.tensor(y, dtype=torch.float32).cuda())
