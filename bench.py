@@ -63,7 +63,8 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", choices=["fp16s", "fp32"], default="fp32")
+    ap.add_argument("--storage", choices=["fp16s", "fp32", "fp32_inplace"], default="fp32",
+                    help="fp32_inplace only with --no-compare (kernel traces of that storage)")
     ap.add_argument("--workload", choices=["rising_bubble", "droplet_impact"],
                     default="rising_bubble")
     ap.add_argument("--no-compare", action="store_true",
@@ -441,6 +442,10 @@ def main():
     if args.sur_profile:
         sur_profile()
         return
+    if args.storage == "fp32_inplace" and not args.no_compare:
+        print("--storage fp32_inplace needs --no-compare (the full run reports the in-place "
+              "storage in its own block)", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               f"decomposition is a design note, not part of this build.", file=sys.stderr)
@@ -489,7 +494,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": read_traffic(args.storage),
-                     "kernel": "k_step<D3Q19>", "bytes_per_site": bps,
+                     "kernel": ("k_ip_phi + k_ip_step<D3Q19>" if args.storage == "fp32_inplace"
+                                else "k_step<D3Q19>"), "bytes_per_site": bps,
                      "kernel_ms": round(ms, 4)},
         "nonfinite": main_run["nonfinite"],
     }
