@@ -123,21 +123,21 @@ extern "C" {
  *                phi; a ghost beyond two or three faces adds their terms.
  *   open, open_P a pressure condition on a wall face (Section 4's dam-break top; the
  *                paper does not say how it is imposed): open[f] = 1 makes face f open,
- *                with pressure open_P[f], rows as wall_u.  Only the faces of the z axis
- *                (D3Q19: rows 4, 5; D2Q9: the y faces, rows 2, 3) may be open, each on a
- *                wall axis with at least 2 sites, not wetting, and no face of the box
- *                may move while one is open.  The sites beyond an open face
- *                are copies of the boundary-layer sites they face (zero normal gradient
- *                of phi and u): a population entering a boundary-layer site x through the
- *                face comes from s' = x - c_i with its normal coordinate put back into
- *                the layer, as s' sent it in direction i, plus 2 w_i (P_f - P(s'))/T for
- *                g (the filtered collision depends on P only through w_i P / T); one
- *                that also crosses a closed face bounces back.  Populations leaving
- *                through the face are lost (outflow), so sum(phi) changes by the net
- *                flux.  A context with an open face is stepped alone (pflb_step_many
- *                does not batch it) and its state buffers also hold the boundary
- *                layers' pressures (pflb_required_bytes includes them).  All zeros: no
- *                open face.
+ *                with pressure open_P[f], rows as wall_u (D2Q9: rows 0-3).  An open face
+ *                lies on a wall axis of at least 2 sites and has no contact angle, and no
+ *                face of the box may move while one is open.  The sites beyond an open
+ *                face are copies of the boundary-layer sites they face (zero normal
+ *                gradient of phi and u): a population entering a boundary-layer site x
+ *                through the face comes from s' = x - c_i with its out-of-range
+ *                coordinates put back into the layer, as s' sent it in direction i, plus
+ *                2 w_i (P_f - P(s'))/T for g (the filtered collision depends on P only
+ *                through w_i P / T); one that crosses several open faces takes the mean
+ *                of their P_f, one that also crosses a closed face bounces back.
+ *                Populations leaving through the face are lost (outflow), so sum(phi)
+ *                changes by the net flux.  A context with an open face is stepped alone
+ *                (pflb_step_many does not batch it) and its state buffers also hold the
+ *                boundary layers' pressures (pflb_required_bytes includes them).  All
+ *                zeros: no open face.
  */
 typedef struct pflb_params {
     int lattice;

@@ -102,11 +102,11 @@ std::string check_params(const pflb_params* p) {
         if (p->open[f] != 0 && p->open[f] != 1) return "open must be 0 or 1";
         if (!p->open[f]) continue;
         any_open = true;
-        // the z axis of the lattice (D2Q9: the user's y axis)
-        const int zaxis = p->lattice == 9 ? 1 : 2;
-        if (f / 2 != zaxis) return "only the faces of the z axis (D2Q9: y) may be open";
-        if (p->bc[zaxis] != PFLB_BC_WALL) return "an open face must be on a wall axis";
-        if ((p->lattice == 9 ? p->ny : p->nz) < 2) return "an open face needs at least 2 sites along its axis";
+        const int axis = f / 2;
+        if (axis >= naxes) return "open face on an axis the lattice does not have";
+        if (p->bc[axis] != PFLB_BC_WALL) return "an open face must be on a wall axis";
+        const int len = axis == 0 ? p->nx : (axis == 1 ? p->ny : p->nz);
+        if (len < 2) return "an open face needs at least 2 sites along its axis";
         if (!finite(p->open_P[f])) return "open-face pressure must be finite";
         if (p->wet_cos[f] != 0.0) return "a contact angle given for an open face";
     }
@@ -124,11 +124,14 @@ bool has_open(const pflb_params* p) {
 
 uint32_t pop_stride(uint32_t N) { return (N + 63u) & ~63u; }
 
-// the pressures of the two boundary layers of the z axis (open faces only): one float
-// per site of a layer, each layer of stride side_stride
+// the pressures of the boundary layers of the open faces: one float per site of a face's
+// layer, six layers of stride side_stride (the largest face, rounded up)
 uint32_t side_stride(const pflb_params* p) {
-    const uint32_t layer = p->lattice == 9 ? (uint32_t)p->nx : (uint32_t)p->nx * (uint32_t)p->ny;
-    return (layer + 63u) & ~63u;
+    // internal sizes (D2Q9: user (x, y) -> internal (x, z))
+    const uint64_t nx = (uint64_t)p->nx, ny = p->lattice == 9 ? 1 : (uint64_t)p->ny,
+                   nz = p->lattice == 9 ? (uint64_t)p->ny : (uint64_t)p->nz;
+    const uint64_t layer = std::max(ny * nz, std::max(nx * nz, nx * ny));
+    return (uint32_t)((layer + 63u) & ~(uint64_t)63u);
 }
 
 size_t side_offset(const pflb_params* p, uint32_t N) {
@@ -139,7 +142,7 @@ size_t side_offset(const pflb_params* p, uint32_t N) {
 size_t set_bytes(const pflb_params* p, uint32_t N) {
     if (!has_open(p))
         return state_bytes(p->lattice, p->storage == PFLB_STORE_FP16S, pop_stride(N));
-    return side_offset(p, N) + 2 * (size_t)side_stride(p) * 4;
+    return side_offset(p, N) + 6 * (size_t)side_stride(p) * 4;
 }
 
 size_t scratch_bytes() {
@@ -239,9 +242,10 @@ void derive(pflb_ctx* c) {
     G.S = pop_stride(c->N);
     G.sxy = (uint32_t)G.nx * (uint32_t)G.ny;
     G.open = 0;
-    const int zf = p.lattice == 19 ? 4 : 2;   // the z- face in the user's rows
-    if (p.open[zf]) G.open |= 16u;
-    if (p.open[zf + 1]) G.open |= 32u;
+    for (int f = 0; f < 6; ++f) {
+        const int fi = p.lattice == 19 ? f : (f < 2 ? f : (f < 4 ? f + 2 : -1));
+        if (fi >= 0 && p.open[f]) G.open |= 1u << fi;
+    }
     G.SL = side_stride(&p);
     G.side_off = side_offset(&p, c->N);
     Model& m = c->L.m;
@@ -263,8 +267,11 @@ void derive(pflb_ctx* c) {
         m.gx = (float)p.g[0]; m.gy = 0.0f; m.gz = (float)p.g[1];
     }
     m.beta = p.hoc ? 1.0f : 0.0f;
-    m.Pf[0] = p.open[zf] ? (float)p.open_P[zf] : 0.0f;
-    m.Pf[1] = p.open[zf + 1] ? (float)p.open_P[zf + 1] : 0.0f;
+    for (int f = 0; f < 6; ++f) m.Pf[f] = 0.0f;
+    for (int f = 0; f < 6; ++f) {
+        const int fi = p.lattice == 19 ? f : (f < 2 ? f : (f < 4 ? f + 2 : -1));
+        if (fi >= 0 && p.open[f]) m.Pf[fi] = (float)p.open_P[f];
+    }
     // wall faces and velocity components in internal axes (D2Q9: user y is internal z)
     m.moving = 0;
     m.wetting = 0;

@@ -101,8 +101,8 @@ struct Geom {
     int wx, wy, wz;     // 1: wall on both faces of the axis, 0: periodic
     uint32_t S;         // population stride of a set, in sites
     uint32_t sxy;       // nx * ny
-    uint32_t open;      // open (pressure) faces of the z axis: 16 z-, 32 z+ (wall bits)
-    uint32_t SL;        // stride of a face's side array, in sites (nx * ny rounded up)
+    uint32_t open;      // open (pressure) faces: bit f for face f (x-, x+, y-, y+, z-, z+)
+    uint32_t SL;        // stride of a face's side array, in sites (the largest face, rounded up)
     size_t side_off;    // byte offset of the side arrays in a state buffer
 };
 
@@ -120,7 +120,7 @@ struct Model {
     int moving;               // 1 if any wall moves
     float wk[6];              // wetting: (4/W) cos(contact angle) per face (internal)
     int wetting;              // 1 if any face has a contact angle other than 90 degrees
-    float Pf[2];              // pressure of the open z- and z+ faces
+    float Pf[6];              // pressure of each open face (x-, x+, y-, y+, z-, z+)
 };
 
 struct Codec {                // FP16S: power-of-two scales of the fp16 deviations

@@ -617,69 +617,108 @@ k_mass_final(const double* __restrict__ part, const int* __restrict__ flag,
 }
 
 // ---------------------------------------------------------------------------
-// open (pressure) faces of the z axis, after a step has written dst.  A population i
-// that enters site x through an open face comes from the boundary-layer site s' = x -
-// c_i with its z put back into the layer, as its post-collision value there, and for g
-// plus 2 w_i (P_f - P(s'))/T: the ghost beyond the face copies the layer (zero normal
-// gradient of phi and u) with the pressure taken linearly to P_f at the face (P(s') from
-// k_open_P).  The step stored that value's source slot (s', i), read by the site one
-// plane inwards, and treated the face as a wall: x reads the incoming value as the
-// bounce-back of i, from its own slot (x, opp(i)), which this kernel overwrites.  A population whose source
-// also crosses a closed x or y wall keeps its bounce-back.  The kernel reads slots that
-// move into the domain and writes slots that leave it, so no slot is both read and
-// written; every slot is still read exactly once by the next step.
-// One thread per site of a face, blockIdx.y = face (0: z-, 1: z+).
+// open (pressure) faces, after a step has written dst.  A population i that enters
+// site x through an open face comes from the boundary-layer site s' = x - c_i with its
+// out-of-range coordinates put back into the layer, as its post-collision value there,
+// and for g plus 2 w_i (P_f - P(s'))/T: the ghost beyond the face copies the layer (zero
+// normal gradient of phi and u) with the pressure taken linearly to P_f at the face
+// (P(s') from k_open_P; P_f the mean over the open faces crossed at an edge or corner).
+// The step stored that value's source slot (s', i), read by the site s' + c_i (inside:
+// on every axis the source crossed, s' sits on the boundary and c_i points inwards),
+// and treated the faces as walls: x reads the incoming value as the bounce-back of i,
+// from its own slot (x, opp(i)), which this kernel overwrites.  A population whose
+// source also crosses a closed face keeps its bounce-back.  The kernel reads slots that
+// move into the domain and writes slots that leave it through open faces, so no slot is
+// both read and written; every slot is still read exactly once by the next step.  A
+// population entering through several open faces is written by the first of them.
+// One thread per site of a face, blockIdx.y = face (x-, x+, y-, y+, z-, z+).
 // ---------------------------------------------------------------------------
-template <class L, class ST, int DIRZ>
+
+// coordinates of site t of face f's layer (the two other axes in increasing order, the
+// lower one fastest) and back
+__device__ __forceinline__ bool face_site(const Geom& G, int f, uint32_t t, int (&v)[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    const int a = f >> 1, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    if (t >= (uint32_t)n[b] * (uint32_t)n[c]) return false;
+    v[b] = (int)(t % (uint32_t)n[b]);
+    v[c] = (int)(t / (uint32_t)n[b]);
+    v[a] = (f & 1) ? n[a] - 1 : 0;
+    return true;
+}
+
+__device__ __forceinline__ size_t face_index(const Geom& G, int f, const int (&v)[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    const int a = f >> 1, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    return (size_t)v[c] * (size_t)n[b] + (size_t)v[b];
+}
+
+template <class L, class ST>
 __device__ __forceinline__ void open_site(const Geom& G, const Model& m, const Codec& cd,
-                                          char* __restrict__ b, int x, int y, int face) {
-    const int z = face ? G.nz - 1 : 0;
+                                          char* __restrict__ b, const int (&v)[3], int f) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    const int w[3] = {G.wx, G.wy, G.wz};
+    const int a = f >> 1;
+    const int inward = (f & 1) ? -1 : 1;        // c_i[a] of the populations entering
     const size_t S = G.S;
-    const size_t xs = site_of(G, x, y, z);
-    const float* Pside = reinterpret_cast<const float*>(b + G.side_off) + (face ? (size_t)G.SL : 0);
-    const float Pf = m.Pf[face];
+    const size_t xs = site_of(G, v[0], v[1], v[2]);
+    const float* Pside = reinterpret_cast<const float*>(b + G.side_off) + (size_t)f * G.SL;
     MomF mx{};
     if constexpr (ST::HALF)
         mx = unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[xs]);
     static_for<1, L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        if constexpr (L::cz(i) == DIRZ) {
-            int sx = x - L::cx(i), sy = y - L::cy(i);
-            bool closed = false;
-            if (sx < 0 || sx >= G.nx) {
-                closed = closed || G.wx;
-                sx = sx < 0 ? sx + G.nx : sx - G.nx;
+        const int c[3] = {L::cx(i), L::cy(i), L::cz(i)};
+        if (c[a] != inward) return;
+        // s' = x - c_i, and the site d = s' + c_i that reads slot (s', i): x itself on
+        // the axes the source stays inside or wraps across, one site inwards on those
+        // it crosses an open face of
+        int sp[3], d[3];
+        bool closed = false, first = true;
+        float Psum = 0.0f;
+        int nopen = 0;
+        for (int e = 0; e < 3; ++e) {
+            sp[e] = v[e] - c[e];
+            d[e] = v[e];
+            if (sp[e] >= 0 && sp[e] < n[e]) continue;
+            if (!w[e]) {                             // periodic: wrap
+                sp[e] = sp[e] < 0 ? sp[e] + n[e] : sp[e] - n[e];
+                continue;
             }
-            if (sy < 0 || sy >= G.ny) {
-                closed = closed || G.wy;
-                sy = sy < 0 ? sy + G.ny : sy - G.ny;
+            const int g = 2 * e + (sp[e] < 0 ? 0 : 1);   // the wall face crossed
+            if (!(G.open & (1u << g))) {
+                closed = true;
+                continue;
             }
-            if (!closed) {
-                const size_t sp = site_of(G, sx, sy, z);          // s'
-                const float shift = 6.0f * L::w(i) * (Pf - Pside[(size_t)sy * G.nx + sx]);
-                if constexpr (!ST::HALF) {
-                    float2 v = reinterpret_cast<const float2*>(b)[(size_t)i * S + sp];
-                    v.y += shift;
-                    reinterpret_cast<float2*>(b)[(size_t)opp(i) * S + xs] = v;
-                } else {
-                    // decode with the reference of the slot's reader (one plane inwards),
-                    // encode with the one x applies to its bounce-back of i
-                    const size_t d = site_of(G, x, y, z + DIRZ);
-                    const MomF md =
-                        unpack_mom(reinterpret_cast<const uint4*>(b + StoreF16S::mom_off(G.S))[d]);
-                    char* dev = b + StoreF16S::dev_off(G.S);
-                    const float2 q = __half22float2(
-                        reinterpret_cast<const __half2*>(dev + (size_t)(i - 1) * S * 4)[sp]);
-                    float rh, rg;
-                    ref_of<L, i>(md, rh, rg);
-                    const float hv = fmaf(q.x, cd.ish, rh);
-                    const float gv = fmaf(q.y, cd.isg, rg) + shift;
-                    ref_of<L, i>(mx, rh, rg);
-                    reinterpret_cast<__half2*>(dev + (size_t)(opp(i) - 1) * S * 4)[xs] =
-                        __halves2half2(__float2half_rn((hv - rh) * cd.sh),
-                                       __float2half_rn((gv - rg) * cd.sg));
-                }
-            }
+            if (g < f) first = false;
+            Psum += m.Pf[g];
+            ++nopen;
+            sp[e] = v[e];                            // back into the layer
+            d[e] = v[e] + c[e];
+        }
+        if (closed || !first) return;
+        const float Pf = nopen > 1 ? Psum / (float)nopen : Psum;
+        const size_t spi = site_of(G, sp[0], sp[1], sp[2]);
+        const float shift = 6.0f * L::w(i) * (Pf - Pside[face_index(G, f, sp)]);
+        if constexpr (!ST::HALF) {
+            float2 val = reinterpret_cast<const float2*>(b)[(size_t)i * S + spi];
+            val.y += shift;
+            reinterpret_cast<float2*>(b)[(size_t)opp(i) * S + xs] = val;
+        } else {
+            // decode with the reference of the slot's reader s' + c_i, encode with the
+            // one x applies to its bounce-back of i
+            const MomF md = unpack_mom(reinterpret_cast<const uint4*>(
+                b + StoreF16S::mom_off(G.S))[site_of(G, d[0], d[1], d[2])]);
+            char* dev = b + StoreF16S::dev_off(G.S);
+            const float2 q = __half22float2(
+                reinterpret_cast<const __half2*>(dev + (size_t)(i - 1) * S * 4)[spi]);
+            float rh, rg;
+            ref_of<L, i>(md, rh, rg);
+            const float hv = fmaf(q.x, cd.ish, rh);
+            const float gv = fmaf(q.y, cd.isg, rg) + shift;
+            ref_of<L, i>(mx, rh, rg);
+            reinterpret_cast<__half2*>(dev + (size_t)(opp(i) - 1) * S * 4)[xs] =
+                __halves2half2(__float2half_rn((hv - rh) * cd.sh),
+                               __float2half_rn((gv - rg) * cd.sg));
         }
     });
 }
@@ -693,12 +732,12 @@ __device__ __forceinline__ void open_site(const Geom& G, const Model& m, const C
 template <class L, class ST, int WALLS>
 __global__ void __launch_bounds__(256) k_open_P(Geom G, Codec cd, const char* __restrict__ src,
                                                 char* __restrict__ dst) {
-    const int face = blockIdx.y;
-    if (!(G.open & (face ? 32u : 16u))) return;
+    const int f = blockIdx.y;
+    if (!(G.open & (1u << f))) return;
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= G.sxy) return;
-    const int y = (int)(t / (uint32_t)G.nx), x = (int)(t - (uint32_t)y * (uint32_t)G.nx);
-    const int z = face ? G.nz - 1 : 0;
+    int v[3];
+    if (!face_site(G, f, t, v)) return;
+    const int x = v[0], y = v[1], z = v[2];
     const Col c = make_col(G, x, y);
     const ZRow r = make_zrow(G, z);
     float h[L::Q], g[L::Q];
@@ -735,19 +774,18 @@ __global__ void __launch_bounds__(256) k_open_P(Geom G, Codec cd, const char* __
             post += (double)fmaf(q.y, cd.isg, rg);
         });
     }
-    reinterpret_cast<float*>(dst + G.side_off)[(face ? (size_t)G.SL : 0) + t] =
+    reinterpret_cast<float*>(dst + G.side_off)[(size_t)f * G.SL + t] =
         (float)((pre + post) * (1.0 / 6.0));
 }
 
 template <class L, class ST>
 __global__ void __launch_bounds__(256) k_open(Geom G, Model m, Codec cd, char* __restrict__ b) {
-    const int face = blockIdx.y;
-    if (!(G.open & (face ? 32u : 16u))) return;
+    const int f = blockIdx.y;
+    if (!(G.open & (1u << f))) return;
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= G.sxy) return;
-    const int y = (int)(t / (uint32_t)G.nx), x = (int)(t - (uint32_t)y * (uint32_t)G.nx);
-    if (face) open_site<L, ST, -1>(G, m, cd, b, x, y, 1);
-    else open_site<L, ST, 1>(G, m, cd, b, x, y, 0);
+    int v[3];
+    if (!face_site(G, f, t, v)) return;
+    open_site<L, ST>(G, m, cd, b, v, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,7 +889,7 @@ static hipError_t dispatch_step(const Launch& a, const StepArgs& x) {
 // populations entering through the faces
 template <class L, class ST>
 static hipError_t open_t(const Launch& a, const void* src, void* dst) {
-    const dim3 grid((a.G.sxy + 255u) / 256u, 2);
+    const dim3 grid((a.G.SL + 255u) / 256u, 6);
     const char* s = static_cast<const char*>(src);
     char* d = static_cast<char*>(dst);
     if (a.wide)

@@ -73,6 +73,14 @@ OPEN_CASES = [
     ("d3q19-open-column", 19, (1, 1, 3), (W_, W_, W_), _open(zp=0.005)),
     ("d2q9-open-y", 9, (40, 21, 1), (W_, W_, P_), _open(ym=0.01, yp=-0.01)),
     ("d2q9-open-top-periodic-x", 9, (33, 5, 1), (P_, W_, P_), _open(yp=0.0)),
+    # x and y faces; edges and corners where open faces meet each other and closed ones
+    # (a population crossing several open faces takes the mean of their pressures)
+    ("d3q19-open-x", 19, (9, 7, 6), (W_, P_, P_), _open(xm=0.02, xp=-0.01)),
+    ("d3q19-open-edges", 19, (8, 7, 6), (W_, W_, W_), _open(xp=0.01, yp=-0.02, zp=0.0)),
+    ("d3q19-open-all", 19, (5, 4, 3), (W_, W_, W_),
+     _open(xm=0.01, xp=-0.01, ym=0.02, yp=0.0, zm=-0.01, zp=0.005)),
+    ("d2q9-open-x", 9, (20, 9, 1), (W_, P_, P_), _open(xm=0.01, xp=-0.01)),
+    ("d2q9-open-corner", 9, (12, 10, 1), (W_, W_, P_), _open(xp=0.01, yp=0.0)),
 ]
 
 
@@ -128,13 +136,20 @@ def test_one_step_open_faces(name, q, shape, bc, op, storage):
         assert abs((m1 - m0) - dm_ref) <= 2e-3 * np.abs(hr).max() * K
 
 
-def _channel(q, storage="fp32"):
-    """Water between no-slip walls across x, open faces along z (D2Q9: y) at +-dP/2."""
+def _channel(q, along="z"):
+    """Water between no-slip walls, open faces at +-dP/2 along z (D2Q9: y) with the walls
+    across x, or along x with the walls across z (D2Q9: y)."""
     dP = 0.6
-    if q == 19:
-        shape, bc, op = (9, 2, 16), (W_, P_, W_), _open(zm=dP / 2, zp=-dP / 2)
+    if along == "z":
+        if q == 19:
+            shape, bc, op = (9, 2, 16), (W_, P_, W_), _open(zm=dP / 2, zp=-dP / 2)
+        else:
+            shape, bc, op = (9, 16, 1), (W_, W_, P_), _open(ym=dP / 2, yp=-dP / 2)
     else:
-        shape, bc, op = (9, 16, 1), (W_, W_, P_), _open(ym=dP / 2, yp=-dP / 2)
+        if q == 19:
+            shape, bc, op = (16, 2, 9), (W_, P_, W_), _open(xm=dP / 2, xp=-dP / 2)
+        else:
+            shape, bc, op = (16, 9, 1), (W_, W_, P_), _open(xm=dP / 2, xp=-dP / 2)
     cfg = _cfg(q, shape, bc, open_P=op, nu_L=0.1, nu_H=0.1, g=(0.0, 0.0, 0.0))
     cfg["name"] = "channel"
     return cfg, dP
@@ -146,15 +161,16 @@ def _channel_fields(cfg):
     return phi, np.zeros((3,) + phi.shape, np.float32), np.zeros_like(phi)
 
 
-@pytest.mark.parametrize("q", [9, 19])
-def test_pressure_driven_channel_vs_oracle(q):
+@pytest.mark.parametrize("q,along", [(9, "z"), (19, "z"), (9, "x"), (19, "x")])
+def test_pressure_driven_channel_vs_oracle(q, along):
     """300 steps of the pressure-driven channel against the oracle's: the momentum at
     the FP32 bar.  phi leaves 1 only by ~1e-5 (what the zero-gradient ghost lets through
     the faces), where the interface normal grad(phi)/|grad(phi)| of Eq. 4's sharpening
     term is set by rounding: there phi is compared against the oracle's own divergence
     from a start perturbed by float32 half-ulp noise (4 times that floor, at least the
-    plain 1e-5)."""
-    cfg, _ = _channel(q)
+    plain 1e-5; the floor is the larger of the divergences a half-ulp start and a
+    float32-rounded state give the oracle)."""
+    cfg, _ = _channel(q, along)
     phi, u, P = _channel_fields(cfg)
     sim = _sim(cfg)
     sim.init_fields(phi, u, P)
@@ -166,16 +182,25 @@ def test_pressure_driven_channel_vs_oracle(q):
     h0, g0 = O.init(prm, phi.astype(np.float64), u.astype(np.float64), P.astype(np.float64))
     h, g = O.run(prm, h0, g0, 300)
     ro = O.read(prm, h, g)
+    dm_ref = O.mass(h) - O.mass(h0)
+    # the oracle's own divergence from two float32-sized disturbances: a start moved by
+    # half-ulp noise, and its populations rounded to float32 after every step (what a
+    # float32 state does to an otherwise exact step)
     rng = np.random.default_rng(99)
     hs = h0 * (1.0 + 2.0 ** -24 * rng.standard_normal(h0.shape))
     hp, gp = O.run(prm, hs, g0, 300)
-    floor = np.abs(O.read(prm, hp, gp)["phi"] - ro["phi"]).max()
-    dm_ref = O.mass(h) - O.mass(h0)
-    dm_floor = abs((O.mass(hp) - O.mass(hs)) - dm_ref)
+    hf, gf = (a.astype(np.float32).astype(np.float64) for a in (h0, g0))
+    for _ in range(300):
+        hf, gf = O.step(prm, hf, gf)
+        hf, gf = (a.astype(np.float32).astype(np.float64) for a in (hf, gf))
+    floor = max(np.abs(O.read(prm, hp, gp)["phi"] - ro["phi"]).max(),
+                np.abs(O.read(prm, hf, gf)["phi"] - ro["phi"]).max())
+    dm_floor = max(abs((O.mass(hp) - O.mass(hs)) - dm_ref),
+                   abs((O.mass(hf) - O.mass(h0)) - dm_ref))
     D = 3 if q == 19 else 2
     dphi = np.abs(r["phi"] - ro["phi"]).max()
     eJ = _jerr(r["J"], ro["J"][:D], cfg["rho_H"])
-    print(f"\nchannel D{D}: max|dphi| {dphi:.2e} (oracle floor {floor:.2e}, max|phi - 1| "
+    print(f"\nchannel D{D} along {along}: max|dphi| {dphi:.2e} (oracle floor {floor:.2e}, max|phi - 1| "
           f"{np.abs(ro['phi'] - 1).max():.2e}), rel J err {eJ:.2e}, |J| "
           f"{np.abs(ro['J']).max():.3e}")
     assert not bad
@@ -187,35 +212,35 @@ def test_pressure_driven_channel_vs_oracle(q):
     assert abs((m1 - m0) - dm_ref) <= max(1e-6 * m0, 4.0 * dm_floor)
 
 
-@pytest.mark.parametrize("q", [9, 19])
-def test_pressure_driven_channel_is_poiseuille(q):
+@pytest.mark.parametrize("q,along", [(9, "z"), (19, "z"), (9, "x"), (19, "x")])
+def test_pressure_driven_channel_is_poiseuille(q, along):
     """The GPU's channel at steady state (3000 steps): P linear between the faces (at
     -1/2 and n - 1/2 along the channel) and the plane Poiseuille profile across it,
     u = (dP/L)/(2 mu) s (H - s), s the distance from the wall, no cross flow."""
-    cfg, dP = _channel(q)
+    cfg, dP = _channel(q, along)
     phi, u, P = _channel_fields(cfg)
     sim = _sim(cfg)
     sim.init_fields(phi, u, P)
     sim.step(3000)
     r = {k: _np(v) for k, v in sim.read().items()}
     rho, nu = cfg["rho_H"], cfg["nu_H"]
-    nx = cfg["shape"][0]
-    L = cfg["shape"][2] if q == 19 else cfg["shape"][1]
-    along = np.arange(L) + 0.5
-    P_exact = dP / 2 - dP * along / L
-    Pz = r["P"].reshape(L, -1) if q == 19 else r["P"][0]       # (along, rest)
-    assert np.abs(Pz - P_exact[:, None]).max() <= 1e-3 * dP
-    s = np.arange(nx) + 0.5
-    prof = (dP / L) / (2.0 * rho * nu) * s * (nx - s)
+    D = 3 if q == 19 else 2
+    # numpy axes of the fields (nz, ny, nx); the flow axis and the wall-normal axis
+    flow_ax = {"z": (0 if q == 19 else 1), "x": 2}[along]
+    wall_ax = 2 if along == "z" else (0 if q == 19 else 1)
+    comp = {"z": (2 if q == 19 else 1), "x": 0}[along]   # J component along the flow
+    Lc = r["P"].shape[flow_ax]
+    H = r["P"].shape[wall_ax]
+    pos = np.arange(Lc) + 0.5
+    P_exact = dP / 2 - dP * pos / Lc
+    Pm = np.moveaxis(r["P"], flow_ax, 0).reshape(Lc, -1)
+    assert np.abs(Pm - P_exact[:, None]).max() <= 1e-3 * dP
+    s = np.arange(H) + 0.5
+    prof = (dP / Lc) / (2.0 * rho * nu) * s * (H - s)
     J = r["J"]
-    if q == 19:
-        ua = J[2] / rho                      # (z, y, x)
-        cross = np.abs(J[:2]).max() / rho
-    else:
-        ua = J[1] / rho                      # (1, y, x): user y is along the channel
-        cross = np.abs(J[0]).max() / rho
-    ua = ua.reshape(-1, nx)
-    assert np.abs(ua - prof[None, :]).max() <= 1e-2 * prof.max()
+    ua = np.moveaxis(J[comp] / rho, wall_ax, 0).reshape(H, -1)
+    assert np.abs(ua - prof[:, None]).max() <= 1e-2 * prof.max()
+    cross = max(np.abs(J[k]).max() for k in range(D) if k != comp) / rho
     assert cross <= 1e-4 * prof.max()
 
 

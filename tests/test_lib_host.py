@@ -142,10 +142,10 @@ def _params(**kw):
                                  dict(wet=(4, 1.5)), dict(wet=(5, float("nan"))),
                                  dict(wet=(0, 0.5)),
                                  dict(lattice=9, nz=1, bc=(1, 1, 0), wet=(4, 0.5)),
-                                 # open faces: z axis only (D2Q9: y), on a wall axis of
-                                 # at least 2 sites, finite pressure, no contact angle on
+                                 # open faces: on a wall axis of at least 2 sites that
+                                 # the lattice has, finite pressure, no contact angle on
                                  # the face, no moving wall anywhere, flag 0 or 1
-                                 dict(bc=(1, 0, 1), open=(0, 0.0)),
+                                 dict(open=(0, 0.0)),
                                  dict(bc=(0, 0, 0), open=(5, 0.0)),
                                  dict(open=(5, float("nan"))), dict(open=(4, float("inf"))),
                                  dict(open=(5, 0.0), wall=(4, 0, 0.01)),
@@ -184,18 +184,26 @@ def test_create_accepts_contact_angles_on_wall_faces(L, wet):
 
 
 @pytest.mark.parametrize("kw", [dict(open=(5, 0.0)), dict(open=(4, -0.01), wet=(5, 0.3)),
+                                dict(bc=(1, 0, 1), open=(0, 0.0)),
+                                dict(bc=(1, 1, 1), nx=12, ny=5, nz=7, open=(3, 0.1)),
                                 dict(lattice=9, nz=1, bc=(1, 1, 0), open=(3, 0.02)),
-                                dict(lattice=9, nz=1, bc=(0, 1, 0), open=(2, 0.0))])
+                                dict(lattice=9, nz=1, bc=(0, 1, 0), open=(2, 0.0)),
+                                dict(lattice=9, nz=1, nx=20, ny=9, bc=(1, 0, 0), open=(1, 0.0))])
 def test_create_accepts_open_faces(L, kw):
-    """Open z faces (D2Q9: y faces); the state buffers grow by the two boundary layers'
-    pressures (one float per layer site, layers of stride rounded up to 64 sites)."""
+    """Open faces on wall axes; the state buffers grow by the boundary layers' pressures
+    (one float per layer site, six layers of the largest face's size rounded up to 64
+    sites)."""
     p = _params(**kw)
     ctx = ctypes.c_void_p()
     assert L.pflb_create(ctypes.byref(p), ctypes.byref(ctx)) == 0
     L.pflb_destroy(ctx)
     closed = _params(**{k: v for k, v in kw.items() if k != "open"})
-    layer = p.nx * (p.ny if p.lattice == 19 else 1)
-    side = 2 * 4 * ((layer + 63) // 64 * 64)
+    if p.lattice == 19:
+        nx, ny, nz = p.nx, p.ny, p.nz
+    else:
+        nx, ny, nz = p.nx, 1, p.ny
+    layer = max(ny * nz, nx * nz, nx * ny)
+    side = 6 * 4 * ((layer + 63) // 64 * 64)
     base = L.pflb_required_bytes(ctypes.byref(closed), 0)
     assert L.pflb_required_bytes(ctypes.byref(p), 0) == (base + 255) // 256 * 256 + side
     assert L.pflb_required_bytes(ctypes.byref(p), 2) == L.pflb_required_bytes(ctypes.byref(closed), 2)
