@@ -150,6 +150,15 @@ constexpr int TP = 16;                 // output patch edge
 constexpr int HP = TP + 2;             // halo patch edge
 constexpr int APAD = 40;               // BF16 per staged pixel (32 channels + pad)
 constexpr int BPAD = 9 * 32 + 8;       // BF16 per staged output channel
+// Row pitch of the staged halo patch: HP pixels of APAD BF16 plus RPAD BF16, so that a
+// row is 112 16-byte units (16 mod 32).  The 32 lanes of a B-operand read cover two patch
+// rows of 16 pixels, and gfx950's LDS serves such a 16-byte read in 512-byte groups of
+// 32 lanes: with rows HP * APAD apart, two lanes 14 pixels apart in the two rows meet in
+// one bank (measured: 1/6 of the LDS cycles of a probe in this pattern were conflict
+// stalls, for every APAD); with the pitch at 16 mod 32 units the second row's 16 units
+// are exactly the ones the first row leaves free.
+constexpr int RPAD = 176;
+constexpr int ROWA = HP * APAD + RPAD; // BF16 per staged patch row
 constexpr int A_ITEMS = HP * HP * 4;   // 16-byte items of the halo patch
 constexpr int A_PER_T = (A_ITEMS + 255) / 256;
 
@@ -362,8 +371,8 @@ __device__ __forceinline__ void tile_epilogue_head(const ConvP& a, const f32x16 
     }
 }
 
-// 32-channel tiles use 45 KB of LDS, so three workgroups fit a CU when the registers
-// allow it; 64-channel tiles (64 KB) fit two, and so does the fused-head variant, whose
+// 32-channel tiles use 50 KB of LDS, so three workgroups fit a CU (160 KB) when the
+// registers allow it; 64-channel tiles (69 KB) fit two, and so does the fused-head variant, whose
 // head arithmetic needs the registers of two workgroups per CU.
 // Epilogue variants: staged (always for 64-channel tiles; for 32-channel tiles only when
 // the layer also writes pooled output), direct, or the fused 1x1 head.
@@ -374,9 +383,10 @@ k_conv_tiled(ConvP a, int tiles_per_wg) {
     constexpr int B_ITEMS = NT * 36;             // 16-byte items of the weight tile
     constexpr int B_PER_T = (B_ITEMS + 255) / 256;
     constexpr int NB = NT / 32;
-    __shared__ __align__(16) __bf16 sA[HP * HP * APAD];
+    __shared__ __align__(16) __bf16 sA[HP * ROWA];
     __shared__ __align__(16) __bf16 sB[NT * BPAD];
-    static_assert(4 * 64 * OROW <= HP * HP * APAD, "epilogue staging must fit the patch buffer");
+    static_assert(4 * 64 * OROW <= HP * ROWA, "epilogue staging must fit the patch buffer");
+    static_assert((ROWA * 2 / 16) % 32 == 16, "patch rows 16 mod 32 16-byte units apart");
     static_assert(EPI != EPI_HEAD || (NT == 32 && MODE == MODE_SAME), "head fusion: 32 channels");
     __shared__ float sH[EPI == EPI_HEAD ? 4 * 32 + 4 : 1];
     if constexpr (EPI == EPI_HEAD) {   // ordered before use by the first tile's barriers
@@ -426,8 +436,10 @@ k_conv_tiled(ConvP a, int tiles_per_wg) {
 #pragma unroll
         for (int k = 0; k < A_PER_T; ++k) {
             const int i = threadIdx.x + 256 * k;
-            if (i < A_ITEMS)
-                *reinterpret_cast<bf16x8*>(&sA[(i >> 2) * APAD + 8 * (i & 3)]) = ra[k];
+            if (i < A_ITEMS) {
+                const int pi = i >> 2, py = pi / HP, px = pi - py * HP;
+                *reinterpret_cast<bf16x8*>(&sA[py * ROWA + px * APAD + 8 * (i & 3)]) = ra[k];
+            }
         }
     };
     auto load_b = [&](int it) {
@@ -489,7 +501,7 @@ k_conv_tiled(ConvP a, int tiles_per_wg) {
 #pragma unroll
                 for (int mb = 0; mb < 2; ++mb)
                     A[mb] = *reinterpret_cast<const bf16x8*>(
-                        &sA[((prow + 2 * mb + dy) * HP + pcol + dx) * APAD + 16 * h + 8 * g]);
+                        &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     Bm[nb] = *reinterpret_cast<const bf16x8*>(
