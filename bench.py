@@ -93,11 +93,18 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 4}), flush=True)
 
 
-def time_storage(cfg, storage, steps, warmup):
+def time_storage(cfg, storage, steps, warmup, perturb_seed=None):
+    """Time `steps` steps after `warmup`; perturb_seed: start from phi moved by float32
+    half-ulp noise (relative 2^-24, seeded), for the conditioning of the run."""
+    import numpy as np
     import torch
     from paper_1812_00118_amd import Sim
     import pfinputs
     phi, u, P = pfinputs.fields(cfg)
+    if perturb_seed is not None:
+        rng = np.random.default_rng(perturb_seed)
+        phi = (phi.astype(np.float64) *
+               (1.0 + 2.0 ** -24 * rng.standard_normal(phi.shape))).astype(np.float32)
     sim = Sim(cfg, storage=storage)
     sim.init_fields(phi, u, P)
     sim.release_work()
@@ -515,8 +522,14 @@ def main():
             "max_abs_dphi_fp16s_vs_fp32": dphi,
             "after_steps": main_run["steps_done"],
         }
-        print(f"[bench] {other}: {oms:.4f} ms/step; max|dphi| fp16s vs fp32 {dphi:.2e}",
-              file=sys.stderr, flush=True)
+        # the run's own conditioning: FP32 against FP32 from a start whose phi moved by
+        # float32 half-ulp noise, after the same steps
+        fp32_run = main_run if args.storage == "fp32" else o
+        p = time_storage(cfg, "fp32", args.steps, args.warmup, perturb_seed=7)
+        cond = (p["phi"] - fp32_run["phi"]).abs().max().item()
+        out["compare"]["max_abs_dphi_fp32_vs_fp32_halfulp_start"] = cond
+        print(f"[bench] {other}: {oms:.4f} ms/step; max|dphi| fp16s vs fp32 {dphi:.2e} "
+              f"(fp32 vs fp32 from a half-ulp start: {cond:.2e})", file=sys.stderr, flush=True)
         if args.workload == "rising_bubble":
             cfg2 = pfinputs.droplet_impact()
             n2 = 256 * 256 * 128
