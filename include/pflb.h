@@ -99,7 +99,7 @@ extern "C" {
  *                > 0.35 and (phi - 1/2) lap(phi) > 0, else 0); 0 switches it off, 10
  *                diffuses dense bubbles away
  *   storage      PFLB_STORE_FP32, PFLB_STORE_FP16S or PFLB_STORE_FP32_INPLACE (the
- *                last without moving walls or open faces; its contexts are stepped one
+ *                last without open faces; its contexts are stepped one
  *                by one by pflb_step_many and not taken by the batched read-out and
  *                hand-over of the surrogate's guard)
  *   scale_log2   power-of-two scale exponents of the fp16 deviations of h and g

@@ -111,8 +111,8 @@ std::string check_params(const pflb_params* p) {
         if (p->wet_cos[f] != 0.0) return "a contact angle given for an open face";
     }
     if (any_open && any_moving) return "moving walls and open faces together are not supported";
-    if (p->storage == PFLB_STORE_FP32_INPLACE && (any_open || any_moving))
-        return "in-place storage has no moving walls or open faces";
+    if (p->storage == PFLB_STORE_FP32_INPLACE && any_open)
+        return "in-place storage has no open faces";
     return "";
 }
 

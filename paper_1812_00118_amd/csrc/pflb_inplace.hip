@@ -144,7 +144,15 @@ k_ip_step(Geom G, Model m, uint32_t N, char* __restrict__ b, const float* __rest
     const GMom gm = g_moments<L>(g);
     const Macro a = macros<L>(m, pn, gm);
     IpWriter<L, LY> out{b, G, x, y, z, s};
-    collide_stream<L>(m, a, lo, h, gm, out);
+    if (m.moving) {
+        // moving walls: the momentum correction of the populations sent into them
+        const uint32_t solid = make_col(G, x, y).solid | make_zrow(G, z).solid;
+        WallWriter<L, IpWriter<L, LY>> wout{out, m, solid, 6.0f * a.phi, 6.0f * a.rho,
+                                            solid != 0u};
+        collide_stream<L>(m, a, lo, h, gm, wout);
+    } else {
+        collide_stream<L>(m, a, lo, h, gm, out);
+    }
 }
 
 // state upload: pre-collision populations (h, g: Q arrays of N) into layout 0

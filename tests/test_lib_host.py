@@ -211,7 +211,7 @@ def test_create_accepts_open_faces(L, kw):
 
 def test_inplace_storage_buffers(L):
     """In-place storage: one state buffer of the FP32 size, no second one (NULL binds),
-    the phi field in the scratch buffer; moving walls and open faces are refused."""
+    the phi field in the scratch buffer; open faces are refused."""
     p = _params(storage=2)
     fp32 = _params()
     N = 8 * 8 * 8
@@ -228,8 +228,7 @@ def test_inplace_storage_buffers(L):
         assert L.pflb_bind(ctx, arr, 3) == -1            # the state buffer is needed
     finally:
         L.pflb_destroy(ctx)
-    for bad in (dict(storage=2, wall=(5, 0, 0.01)), dict(storage=2, open=(5, 0.0)),
-                dict(storage=3)):
+    for bad in (dict(storage=2, open=(5, 0.0)), dict(storage=3)):
         q = _params(**bad)
         c = ctypes.c_void_p(1)
         assert L.pflb_create(ctypes.byref(q), ctypes.byref(c)) == -1
