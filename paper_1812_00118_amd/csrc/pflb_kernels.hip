@@ -26,6 +26,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 // stores of a finished plane may stay in flight across it; __syncthreads() would wait
 // for them (vmcnt(0)) at every plane.  The memory clobber keeps the compiler from
 // moving LDS accesses across it.
+// Keeps v computed on every lane at this point: a value used only under a per-lane
+// condition is otherwise sunk into that branch, and so are its loads
+__device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
+
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -108,16 +112,20 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     const bool active = x < G.nx && y < G.ny;
 
     const Col own = make_col(G, map_coord(x, G.nx, G.wx), map_coord(y, G.ny, G.wy));
-    // ring position of this thread (if any)
+    // ring position of this thread: its own if tid < NR; FP32 threads past the ring take
+    // their wave's first ring position (or, in a wave without one, the last), so that
+    // every thread gathers a ring site with no branch and the duplicates fall in lines
+    // their wave or a neighbouring one loads anyway; only the ring threads store theirs
     int rhx = 0, rhy = 0;
     const bool has_ring = tid < NR;
+    const int rid = (HALF || tid < NR) ? tid : ((tid & ~63) < NR ? (tid & ~63) : NR - 1);
     if constexpr (L::USES_Y) {
-        if (tid < HX) { rhx = tid; rhy = 0; }
-        else if (tid < 2 * HX) { rhx = tid - HX; rhy = HY - 1; }
-        else if (tid < 2 * HX + TY) { rhx = 0; rhy = 1 + tid - 2 * HX; }
-        else { rhx = HX - 1; rhy = 1 + tid - 2 * HX - TY; }
+        if (rid < HX) { rhx = rid; rhy = 0; }
+        else if (rid < 2 * HX) { rhx = rid - HX; rhy = HY - 1; }
+        else if (rid < 2 * HX + TY) { rhx = 0; rhy = 1 + rid - 2 * HX; }
+        else { rhx = HX - 1; rhy = 1 + rid - 2 * HX - TY; }
     } else {
-        rhx = (tid == 0) ? 0 : HX - 1;
+        rhx = (rid == 0) ? 0 : HX - 1;
     }
     const Col ring = make_col(G, map_coord(x0 - 1 + rhx, G.nx, G.wx),
                               L::USES_Y ? map_coord(y0 - 1 + rhy, G.ny, G.wy) : 0);
@@ -165,13 +173,31 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
 
     float hA[Q], loA, hB[Q], loB;
     GMom gA, gB;
-    {   // plane z0 - 1 (for the neighbours only) and plane z0
+    if constexpr (HALF) {   // plane z0 - 1 (for the neighbours only) and plane z0
         const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
         side_site(own, rm, z0 - 1, ty + OY, tx + 1, x, y);
         if (has_ring) side_site(ring, rm, z0 - 1, rhy, rhx, rrx, rry);
         const ZRow r0 = make_zrow(G, z0);
         own_site(r0, z0, hA, gA, loA);
         if (has_ring) side_site(ring, r0, z0, rhy, rhx, rrx, rry);
+    } else {
+        // FP32: the four gathers with no branch between them, so that their loads are in
+        // flight together; the ring threads store their ring values after
+        const ZRow rm = make_zrow(G, map_coord(z0 - 1, G.nz, G.wz));
+        const ZRow r0 = make_zrow(G, z0);
+        float f[Q];
+        const float pm = (float)pull_site_h<L, ST, WALLS>(src, G, own, rm, cd, f);
+        const float p0 = split_hi_lo(pull_site_m<L, WALLS>(src, G, own, r0, hA, gA), loA);
+        const float qm = (float)pull_site_h<L, ST, WALLS>(src, G, ring, rm, cd, f);
+        const float q0 = (float)pull_site_h<L, ST, WALLS>(src, G, ring, r0, cd, f);
+        keep(qm);
+        keep(q0);
+        sphi[(z0 - 1) & 3][ty + OY][tx + 1] = wet(pm, x, y, z0 - 1);
+        sphi[z0 & 3][ty + OY][tx + 1] = wet(p0, x, y, z0);
+        if (has_ring) {
+            sphi[(z0 - 1) & 3][rhy][rhx] = wet(qm, rrx, rry, z0 - 1);
+            sphi[z0 & 3][rhy][rhx] = wet(q0, rrx, rry, z0);
+        }
     }
     // One plane: gather plane z+1 into (hn, gn), then collide plane z from (hc, gc)
     // (h values and g moments).
@@ -189,13 +215,18 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
                 // the plane above the chunk, for the neighbours only
                 side_site(own, rn, z + 1, ty + OY, tx + 1, x, y);
             }
+            if (has_ring) side_site(ring, rn, z + 1, rhy, rhx, rrx, rry);
         } else {
-            // (one phi store after either gather: measured faster than a store per branch)
-            const double pn64 = (z + 1 < zend) ? pull_site_m<L, WALLS>(src, G, own, rn, hn, gn)
-                                               : pull_site_h<L, ST, WALLS>(src, G, own, rn, cd, hn);
+            // the own and the ring gather with no branch between them, so that their loads
+            // are in flight together (the plane above the chunk is gathered as a collided
+            // one: the same lines, its g moments unused)
+            const double pn64 = pull_site_m<L, WALLS>(src, G, own, rn, hn, gn);
+            float f[Q];
+            const float qn = (float)pull_site_h<L, ST, WALLS>(src, G, ring, rn, cd, f);
+            keep(qn);
             sphi[(z + 1) & 3][ty + OY][tx + 1] = wet(split_hi_lo(pn64, lo_n), x, y, z + 1);
+            if (has_ring) sphi[(z + 1) & 3][rhy][rhx] = wet(qn, rrx, rry, z + 1);
         }
-        if (has_ring) side_site(ring, rn, z + 1, rhy, rhx, rrx, rry);
         lds_barrier();
         __builtin_amdgcn_s_setprio(0);
         if (active) {
@@ -274,9 +305,10 @@ k_step_rows(Geom G, Model m, int ntx, int nblk, const char* __restrict__ src,
     const int x = x0 + tx;
     const bool active = x < G.nx;
     const Col own = make_col(G, map_coord(x, G.nx, G.wx), 0);
-    // ring sites x0 - 1 (lane 0) and x0 + 64 (lane 1); every lane gathers the one of its
-    // parity (the wave's loads of one address fall in one line), so the ring needs no
-    // branch, and lanes 0 and 1 store it
+    // ring sites x0 - 1 (lane 0) and x0 + 64 (lane 1); every lane computes the one of its
+    // parity, so the ring needs no branch of its own (the compiler moves the ring's loads
+    // under the store's condition, lanes 0 and 1: measured faster here than keeping them
+    // on every lane), and lanes 0 and 1 store it
     const bool has_ring = tx < 2;
     const int rhx = (tx & 1) ? HX - 1 : 0;
     const Col ring = make_col(G, map_coord(x0 - 1 + rhx, G.nx, G.wx), 0);
