@@ -115,14 +115,15 @@ k_step(Geom G, Model m, Codec cd, int BZ, int ntx, int nty, int nblk,
     const bool active = x < G.nx && y < G.ny;
 
     const Col own = make_col(G, map_coord(x, G.nx, G.wx), map_coord(y, G.ny, G.wy));
-    // Without walls across x or y (whose ring gathers take per-lane wall tests) the own
-    // and the ring gathers of a plane are issued with no branch between them, so that
-    // their loads are in flight together: every thread gathers a ring site (threads past
-    // the ring take their wave's first ring position or, in a wave without one, the last,
-    // so the duplicates fall in lines their wave or a neighbouring one loads anyway) and
-    // only the ring threads store theirs.  Measured: rising bubble FP32 unchanged, FP16S
-    // 3% faster, droplet impact 2% and 4.5%; with x/y walls it measured slower.
-    constexpr bool TOGETHER = (WS & WALLS_XY) == 0;
+    // Without walls across x or y (whose ring gathers take per-lane wall tests) and
+    // outside the XBC variants the own and the ring gathers of a plane are issued with no
+    // branch between them, so that their loads are in flight together: every thread
+    // gathers a ring site (threads past the ring take their wave's first ring position
+    // or, in a wave without one, the last, so the duplicates fall in lines their wave or a
+    // neighbouring one loads anyway) and only the ring threads store theirs.  Measured:
+    // rising bubble FP32 unchanged, FP16S 3% faster, droplet impact 2% and 4.5%; with x/y
+    // walls, and in the XBC variants (FP16S moving walls 27% slower), it measured slower.
+    constexpr bool TOGETHER = (WS & WALLS_XY) == 0 && !XBC;
     int rhx = 0, rhy = 0;
     const bool has_ring = tid < NR;
     const int rid = (!TOGETHER || tid < NR) ? tid : ((tid & ~63) < NR ? (tid & ~63) : NR - 1);
