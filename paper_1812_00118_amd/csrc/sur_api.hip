@@ -63,6 +63,10 @@ constexpr LayerDef LAYERS[NL] = {
     {"d0b", D0A, 0, 32, 32, 0, MODE_SAME, D0B, 0},
 };
 constexpr int HEAD_C = 32;
+static_assert(LAYERS[0].Cin == 8 && LAYERS[0].Cout == 32 && LAYERS[0].mode == MODE_SAME &&
+                  LAYERS[1].in_buf == LAYERS[0].out_buf && LAYERS[1].Cin == 32 &&
+                  LAYERS[1].Cout == 32 && LAYERS[1].mode == MODE_SAME,
+              "the first layer is fused into the second at inference");
 static_assert(LAYERS[NL - 1].Cout == HEAD_C && LAYERS[NL - 1].mode == MODE_SAME &&
                   LAYERS[NL - 1].pool_out < 0,
               "the head is fused into the last layer at inference");
@@ -244,6 +248,7 @@ int run_forward(pfsur_ctx* c, const void* x, float* out, int B, char* ws, bool t
                 hipStream_t st) {
     const int H = c->cfg.H, W = c->cfg.W;
     const Plan p = make_plan(H, W, B, training);
+    ConvP a_first;   // inference: the first layer runs inside the second's kernel
     for (int l = 0; l < NL; ++l) {
         const LayerDef& L = LAYERS[l];
         ConvP a;
@@ -272,7 +277,14 @@ int run_forward(pfsur_ctx* c, const void* x, float* out, int B, char* ws, bool t
             a.head_b = c->master + PL.head + PFSUR_OUT_CH * HEAD_C;
             a.head_out = out;
         }
-        SUR_TRY(conv3x3(a, st), "conv forward");
+        if (!training && l == 0) {
+            a_first = a;
+            continue;
+        }
+        if (!training && l == 1)
+            SUR_TRY(conv_stem(a_first, a, st), "conv forward");
+        else
+            SUR_TRY(conv3x3(a, st), "conv forward");
     }
     if (training) {
         const size_t P0 = (size_t)B * H * W;

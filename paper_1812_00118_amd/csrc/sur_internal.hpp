@@ -68,6 +68,9 @@ struct DensTab {
 };
 
 hipError_t conv3x3(const ConvP& a, hipStream_t st);
+// the first two layers at inference: a0 the first (8 input channels, its outputs not
+// stored), a the second (32 -> 32 channels, same resolution)
+hipError_t conv_stem(const ConvP& a0, const ConvP& a, hipStream_t st);
 hipError_t wgrad(const WgradP& a, hipStream_t st);
 int wgrad_nsplit(int B, int H, int W, int Cout, int Cin, int* per_split);
 hipError_t reduce_splits(const float* part, int nsplit, size_t n, float* out, int acc,

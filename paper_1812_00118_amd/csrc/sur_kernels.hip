@@ -588,6 +588,153 @@ __global__ void __launch_bounds__(256, 2) k_conv_first(ConvP a) {
 }
 
 // ---------------------------------------------------------------------------
+// Inference stem: the first layer (8 input channels) computed straight into the second
+// layer's staged halo patch.  A workgroup's 16x16 output tile of the second layer needs
+// the first layer's activations on its 18x18 halo patch; it computes them from a 20x20
+// patch of the input with k_conv_first's MFMA sequence, bias, SiLU and BF16 rounding (so
+// they are bitwise the values the first layer would have stored, the periodic wrap
+// commuting with the convolution) and writes them where k_conv_tiled stages its input;
+// the second layer then runs as k_conv_tiled<32> with the staged epilogue.  Both layers'
+// weight operands stay in registers; workgroups walk runs of tiles with the next tile's
+// input loads in flight.  The first layer's activations never reach HBM; training keeps
+// the two layers apart (its backward pass needs them).  Needs H, W >= 16 (one period of
+// wrap covers the patch).  Measured: 151 us at batch 32 against 158 us for the two
+// kernels (the pair is bound by its per-tile chain of load, two MFMA phases and stores,
+// not by the HBM bytes it saves).
+// ---------------------------------------------------------------------------
+constexpr int HP2 = HP + 2;                       // input patch edge
+constexpr int STEM_PIX = HP * HP;                 // first-layer pixels per tile
+constexpr int STEM_BLK = (STEM_PIX + 31) / 32;    // their 32-pixel MFMA blocks
+
+__global__ void __launch_bounds__(256, 2) k_conv_stem(ConvP a0, ConvP a, int tiles_per_wg) {
+    __shared__ __align__(16) __bf16 sX[HP2 * HP2 * 8];
+    __shared__ __align__(16) __bf16 sA[HP * ROWA];
+    static_assert(4 * 64 * OROW <= HP * ROWA, "epilogue staging must fit the patch buffer");
+    constexpr int X_PER_T = (HP2 * HP2 + 255) / 256;   // 16-byte input items per thread
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l32 = lane & 31, g = lane >> 5;
+    const int tx_n = (a.W + TP - 1) / TP, ty_n = (a.H + TP - 1) / TP;
+    const int ntile = a.B * tx_n * ty_n;
+    const int t_beg = blockIdx.x * tiles_per_wg;
+    const int t_end = min(ntile, t_beg + tiles_per_wg);
+    const bf16x8 zero8 = (bf16x8){0, 0, 0, 0, 0, 0, 0, 0};
+    auto tile_xy = [&](int t, int& b, int& y0, int& x0) {
+        const int tx = t % tx_n;
+        t /= tx_n;
+        const int ty = t % ty_n;
+        b = t / ty_n;
+        x0 = tx * TP;
+        y0 = ty * TP;
+    };
+    // a tile's input pixels (y0 - 2 + qy, x0 - 2 + qx), into registers
+    bf16x8 rx[X_PER_T];
+    auto load_x = [&](int t) {
+        int b, y0, x0;
+        tile_xy(t, b, y0, x0);
+#pragma unroll
+        for (int k = 0; k < X_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it < HP2 * HP2) {
+                const int qy = it / HP2, qx = it - qy * HP2;
+                rx[k] = gather8<MODE_SAME>(a0.g, b, wrap(y0 - 2 + qy, a.H),
+                                           wrap(x0 - 2 + qx, a.W), 0);
+            }
+        }
+    };
+    // both layers' weight operands, held in registers for the workgroup's life (the
+    // values k_conv_first and k_conv_tiled stage in LDS): lane l32 is output channel l32;
+    // first layer: taps 2s + g (the tenth zero) of 8 channels; second layer: tap t, input
+    // channels 16h + 8g .. + 7
+    bf16x8 w0[5], w1[9][2];
+#pragma unroll
+    for (int s5 = 0; s5 < 5; ++s5) {
+        const int tap = 2 * s5 + g;
+        w0[s5] = tap < 9 ? *reinterpret_cast<const bf16x8*>(a0.w + ((size_t)l32 * 9 + tap) * 8)
+                         : zero8;
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            w1[tap][h] = *reinterpret_cast<const bf16x8*>(a.w + ((size_t)l32 * 9 + tap) * 32 +
+                                                          16 * h + 8 * g);
+    if (t_beg < t_end) load_x(t_beg);
+    for (int t = t_beg; t < t_end; ++t) {
+        int b, y0, x0;
+        tile_xy(t, b, y0, x0);
+        __syncthreads();                           // the previous tile is done with sX, sA
+#pragma unroll
+        for (int k = 0; k < X_PER_T; ++k) {
+            const int it = threadIdx.x + 256 * k;
+            if (it < HP2 * HP2) *reinterpret_cast<bf16x8*>(&sX[it * 8]) = rx[k];
+        }
+        __syncthreads();
+        if (t + 1 < t_end) load_x(t + 1);          // in flight while this tile computes
+        // the first layer on the 18x18 halo patch, 32 pixels (in row-major patch order) per
+        // MFMA block; the last block's spare lanes repeat its last pixel and store nothing
+        for (int k = wave; k < STEM_BLK; k += 4) {
+            const int p = 32 * k + l32;
+            const int pc = p < STEM_PIX ? p : STEM_PIX - 1;
+            const int py = pc / HP, px = pc - py * HP;
+            f32x16 acc;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const int tap = 2 * s + g;
+                const int dy = tap / 3, dx = tap % 3;
+                const bf16x8 Bm = w0[s];
+                const bf16x8 A = tap < 9 ? *reinterpret_cast<const bf16x8*>(
+                                               &sX[((py + dy) * HP2 + px + dx) * 8])
+                                         : zero8;
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm, A, acc, 0, 0, 0);
+            }
+            if (p < STEM_PIX) {
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x4 o;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float v =
+                            acc[4 * q + e] + (a0.bias ? a0.bias[8 * q + 4 * g + e] : 0.0f);
+                        o[e] = (__bf16)(a0.act ? silu(v) : v);
+                    }
+                    *reinterpret_cast<bf16x4*>(&sA[py * ROWA + px * APAD + 8 * q + 4 * g]) = o;
+                }
+            }
+        }
+        __syncthreads();
+        // the second layer, as k_conv_tiled<32> over its one input chunk
+        f32x16 acc[2][1];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[mb][0][j] = 0.0f;
+        const int prow = 4 * wave + (l32 >> 4), pcol = l32 & 15;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                bf16x8 A[2];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    A[mb] = *reinterpret_cast<const bf16x8*>(
+                        &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
+                const bf16x8 Bm = w1[tap][h];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm, A[mb], acc[mb][0],
+                                                                         0, 0, 0);
+            }
+        }
+        __syncthreads();                 // every wave is done reading the patch
+        tile_epilogue_staged<1>(a, acc, b, y0, x0, 0, wave, l32, g, sA);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient staged through LDS: dW[o, tap, c] = sum_p dz[p, o] in[p + off(tap), c].
 // A workgroup owns 32 output x 32 input channels and all 9 taps, and a contiguous range
 // of 16x16 pixel patches (split K).  Per patch, dz is staged transposed ([o][pixel]) and
@@ -1142,6 +1289,20 @@ static hipError_t launch_tiled(const ConvP& a, hipStream_t st) {
                            per);
     else
         hipLaunchKernelGGL((k_conv_tiled<NT, MODE_SAME, E>), grid, dim3(256), 0, st, a, per);
+    return hipGetLastError();
+}
+
+hipError_t conv_stem(const ConvP& a0, const ConvP& a, hipStream_t st) {
+    if (a0.g.C != 8 || a0.g.mode != MODE_SAME || a0.Cout != 32 || a.g.C != 32 ||
+        a.g.mode != MODE_SAME || a.Cout != 32 || a0.B != a.B || a0.H != a.H || a0.W != a.W ||
+        a.H < TP || a.W < TP || !a.out || a.head_out || a.fout || a.zout || a0.zout ||
+        (a.pout && (a.H % 2 || a.W % 2)))
+        return hipErrorInvalidValue;
+    // as many workgroups as are resident at once (2 per CU), each walking a run of tiles
+    // with the next tile's input loads in flight during the current tile's work
+    const int ntile = a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP);
+    const int per = std::max(1, (ntile + 511) / 512);
+    hipLaunchKernelGGL(k_conv_stem, dim3((ntile + per - 1) / per), dim3(256), 0, st, a0, a, per);
     return hipGetLastError();
 }
 

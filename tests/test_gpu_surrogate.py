@@ -187,7 +187,10 @@ def test_network_layers_elementwise_at_full_depth(sur_mod):
     to BF16 of the float32 2x2 average of the stored activations in the stated order;
     and the 1x1 head, fed by the last layer's BF16-rounded activations in its epilogue,
     against the reference head on the reference activations (rounding decisions at the
-    BF16 boundary bounded by one BF16 ulp per channel)."""
+    BF16 boundary bounded by one BF16 ulp per channel).  The first layer's activations,
+    which inference never stores (they stay in the second layer's kernel), are taken
+    from the training forward, which stores them; the stem test below shows they are the
+    same bits."""
     rng = np.random.default_rng(21)
     params = {k: (bf16(w), bf16(b)) for k, (w, b) in U.init_weights(13).items()}
     B, H, W = 2, 64, 64
@@ -197,15 +200,24 @@ def test_network_layers_elementwise_at_full_depth(sur_mod):
     s.set_params(flat_params(params))
     out = s.forward(dev_bf16(x)).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
-    ws = s.workspace_tensor(B, False)
+    ws_inf = s.workspace_tensor(B, False)
+    s.gradients(dev_bf16(x), torch.zeros((B, H, W, sur_mod.OUT_CH), device="cuda"))
+    torch.cuda.synchronize()
+    ws_train = s.workspace_tensor(B, True)
     names = [n for n, *_ in U.LAYERS]
     worst = 0.0
     for l, name in enumerate(names):
-        io = s.layer_io(B, False, l)
+        io = s.layer_io(B, l != 0, l)
+        ws = ws_train if l == 0 else ws_inf
         lv, cin, cout = io["level"], io["Cin"], io["Cout"]
         Hl, Wl = H >> lv, W >> lv
         if io["in_off"] is None:
             xin = x.copy()
+        elif l == 1:
+            # the first layer's activations as the training forward stored them
+            it = s.layer_io(B, True, 1)
+            buf = _ws_bf16(ws_train, it["in_off"], B, Hl, Wl, it["in_cs"])
+            xin = buf[..., it["in_c0"]:it["in_c0"] + cin]
         elif io["in_mode"] == 1:
             buf = _ws_bf16(ws, io["in_off"], B, Hl // 2, Wl // 2, io["in_cs"])
             xin = U.upsample2(buf[..., io["in_c0"]:io["in_c0"] + cin])
@@ -243,6 +255,43 @@ def test_network_layers_elementwise_at_full_depth(sur_mod):
             assert np.array_equal(pb, bf16(avg)), name
     print(f"\nlargest error / bound over the 17 layers and the head: {worst:.3f}")
 
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 64, 48), (3, 24, 40), (1, 16, 16)])
+def test_inference_stem_matches_separate_layers(sur_mod, B, H, W):
+    """At inference the first layer runs inside the second layer's kernel (its
+    activations computed on the second layer's halo patch in LDS, never stored); every
+    activation and pooled copy the inference forward stores equals, bit for bit, the
+    training forward's, which runs the two layers as separate kernels and stores the
+    first's.  Shapes with ragged tiles and the smallest image (one tile, the patch
+    wrapping on all sides)."""
+    rng = np.random.default_rng(H * W + B)
+    params = {k: (bf16(w), bf16(b)) for k, (w, b) in U.init_weights(17).items()}
+    x = np.zeros((B, H, W, U.IN_CH))
+    x[..., :5] = bf16(rng.standard_normal((B, H, W, 5)))
+    s = sur_mod.Surrogate(H, W, B, NORM)
+    s.set_params(flat_params(params))
+    s.forward(dev_bf16(x))
+    torch.cuda.synchronize()
+    ws_inf = s.workspace_tensor(B, False).cpu().numpy()
+    s.gradients(dev_bf16(x), torch.zeros((B, H, W, sur_mod.OUT_CH), device="cuda"))
+    torch.cuda.synchronize()
+    ws_train = s.workspace_tensor(B, True).cpu().numpy()
+
+    def words(ws, off, b, h, w, cs, c0, c):
+        a = ws[off:off + 2 * b * h * w * cs].view(np.uint16).reshape(b, h, w, cs)
+        return a[..., c0:c0 + c]
+
+    for l in range(1, len(U.LAYERS) - 1):
+        ii, it = s.layer_io(B, False, l), s.layer_io(B, True, l)
+        Hl, Wl = H >> ii["level"], W >> ii["level"]
+        a = words(ws_inf, ii["out_off"], B, Hl, Wl, ii["out_cs"], ii["out_c0"], ii["Cout"])
+        b = words(ws_train, it["out_off"], B, Hl, Wl, it["out_cs"], it["out_c0"], it["Cout"])
+        assert np.array_equal(a, b), (U.LAYERS[l][0], int((a != b).sum()))
+        if ii["pool_off"] is not None:
+            a = words(ws_inf, ii["pool_off"], B, Hl // 2, Wl // 2, ii["pool_cs"], 0, ii["Cout"])
+            b = words(ws_train, it["pool_off"], B, Hl // 2, Wl // 2, it["pool_cs"], 0, it["Cout"])
+            assert np.array_equal(a, b), (U.LAYERS[l][0], "pooled", int((a != b).sum()))
 
 def test_network_gradients_match_reference(net_case):
     s, params, x, y = net_case
