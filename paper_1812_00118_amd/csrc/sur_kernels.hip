@@ -492,26 +492,40 @@ k_conv_tiled(ConvP a, int tiles_per_wg) {
             if (nchunk > 1) load_b(it + 1);
             if (MODE != MODE_POOL) load_a(it + 1);
         }
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
+        // K steps s = 2 tap + h (h: the half of the chunk's 32 channels), the operands of
+        // step s + 1 read from LDS ahead of step s's MFMAs, so that the MFMAs cover the
+        // reads' latency (the accumulation order is unchanged)
+        auto ld = [&](int s, bf16x8 (&A)[2], bf16x8 (&Bm)[NB]) {
+            const int tap = s >> 1, h = s & 1;
             const int dy = tap / 3, dx = tap % 3;   // halo coordinates: +1 offset folded in
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                bf16x8 A[2], Bm[NB];
+            for (int mb = 0; mb < 2; ++mb)
+                A[mb] = *reinterpret_cast<const bf16x8*>(
+                    &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    A[mb] = *reinterpret_cast<const bf16x8*>(
-                        &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
+            for (int nb = 0; nb < NB; ++nb)
+                Bm[nb] = *reinterpret_cast<const bf16x8*>(
+                    &sB[(nb * 32 + l32) * BPAD + tap * 32 + 16 * h + 8 * g]);
+        };
+        bf16x8 Ac[2], Bc[NB];
+        ld(0, Ac, Bc);
+#pragma unroll
+        for (int s = 0; s < 18; ++s) {
+            bf16x8 An[2], Bn[NB];
+            if (s + 1 < 18) ld(s + 1, An, Bn);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    Bm[nb] = *reinterpret_cast<const bf16x8*>(
-                        &sB[(nb * 32 + l32) * BPAD + tap * 32 + 16 * h + 8 * g]);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bc[nb], Ac[mb],
+                                                                         acc[mb][nb], 0, 0, 0);
+            if (s + 1 < 18) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 2 + NB, 0);   // the next reads,
+                __builtin_amdgcn_sched_group_barrier(0x008, 2 * NB, 0);   // then these MFMAs
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
+                for (int mb = 0; mb < 2; ++mb) Ac[mb] = An[mb];
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm[nb], A[mb],
-                                                                             acc[mb][nb], 0, 0, 0);
+                for (int nb = 0; nb < NB; ++nb) Bc[nb] = Bn[nb];
             }
         }
         if (ch == nchunk - 1) {
@@ -712,21 +726,31 @@ __global__ void __launch_bounds__(256, 2) k_conv_stem(ConvP a0, ConvP a, int til
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[mb][0][j] = 0.0f;
         const int prow = 4 * wave + (l32 >> 4), pcol = l32 & 15;
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
+        // K steps s = 2 tap + h, the patch operands of step s + 1 read ahead of step s's
+        // MFMAs (as in k_conv_tiled; the accumulation order is unchanged)
+        auto ld = [&](int s, bf16x8 (&A)[2]) {
+            const int tap = s >> 1, h = s & 1;
             const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                bf16x8 A[2];
+            for (int mb = 0; mb < 2; ++mb)
+                A[mb] = *reinterpret_cast<const bf16x8*>(
+                    &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
+        };
+        bf16x8 Ac[2];
+        ld(0, Ac);
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    A[mb] = *reinterpret_cast<const bf16x8*>(
-                        &sA[(prow + 2 * mb + dy) * ROWA + (pcol + dx) * APAD + 16 * h + 8 * g]);
-                const bf16x8 Bm = w1[tap][h];
+        for (int s = 0; s < 18; ++s) {
+            bf16x8 An[2];
+            if (s + 1 < 18) ld(s + 1, An);
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Bm, A[mb], acc[mb][0],
-                                                                         0, 0, 0);
+            for (int mb = 0; mb < 2; ++mb)
+                acc[mb][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1[s >> 1][s & 1], Ac[mb],
+                                                                     acc[mb][0], 0, 0, 0);
+            if (s + 1 < 18) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // the next reads,
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // then these MFMAs
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) Ac[mb] = An[mb];
             }
         }
         __syncthreads();                 // every wave is done reading the patch
