@@ -1282,10 +1282,11 @@ static inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int NT>
 static hipError_t launch_tiled(const ConvP& a, hipStream_t st) {
-    // as many workgroups as are resident at once (3 or 2 per CU); each walks a
-    // contiguous run of tiles so that the loads of its next tile overlap the MFMAs of
+    // as many workgroups as are resident at once (3 per CU for 32-channel tiles, 2 for
+    // 64-channel tiles and the fused-head variant, as their launch bounds say); each walks
+    // a contiguous run of tiles so that the loads of its next tile overlap the MFMAs of
     // the current one
-    constexpr int resident = NT == 32 ? 768 : 512;
+    const int resident = NT == 32 && !a.head_out ? 768 : 512;
     const int ntile = a.B * ((a.H + TP - 1) / TP) * ((a.W + TP - 1) / TP);
     const int nblk_n = (a.Cout + NT - 1) / NT;
     const int per = std::max(1, (ntile * nblk_n + resident - 1) / resident);
