@@ -337,7 +337,7 @@ def surrogate_block(train_steps):
     fwd = {}
     for B in (1, 32):
         x = _sur_input((B, H, W, S.IN_CH), 1).to(torch.bfloat16)
-        fwd[B] = _events_ms(lambda: sur.forward(x), 10 if B == 1 else 4)
+        fwd[B] = _events_ms(lambda: sur.forward(x), 20 if B == 1 else 10)
     xb = _sur_input((8, H, W, S.IN_CH), 2).to(torch.bfloat16)
     yb = _sur_input((8, H, W, S.OUT_CH), 3)
     train_ms = _events_ms(lambda: sur.train_step(xb, yb, 0.0), 4)
