@@ -93,6 +93,20 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 4}), flush=True)
 
 
+def copy_ceiling(moved_bytes, reps=20):
+    """GB/s of a device-to-device copy that reads and writes moved_bytes / 2 each: the
+    rate a kernel moving the same bytes (read once, written once) could reach at best on
+    this GPU."""
+    import torch
+    n = moved_bytes // 2 // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _events_ms(lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def time_storage(cfg, storage, steps, warmup, perturb_seed=None):
     """Time `steps` steps after `warmup`; perturb_seed: start from phi moved by float32
     half-ulp noise (relative 2^-24, seeded), for the conditioning of the run."""
@@ -515,6 +529,11 @@ def main():
                      "kernel_ms": round(ms, 4)},
         "nonfinite": main_run["nonfinite"],
     }
+    # the same bytes moved by a plain device-to-device copy on this GPU (context for the
+    # fraction of the 8 TB/s peak: a copy does not reach it either)
+    copy_gbs = copy_ceiling(bps * N)
+    out["roofline"]["copy_GBs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     print(f"[bench] {args.storage}: {ms:.4f} ms/step, {mlups:.0f} MLUPS, "
           f"{achieved:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_compare:
