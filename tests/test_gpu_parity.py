@@ -611,6 +611,42 @@ def test_full_size_one_step_sampled(make):
     _close(gg, gr)
 
 
+@pytest.mark.parametrize("make", [pfinputs.droplet_impact, pfinputs.rising_bubble,
+                                  pfinputs.rayleigh_taylor],
+                         ids=["droplet_impact_256x256x128", "rising_bubble_128^3",
+                              "rayleigh_taylor_256x1024"])
+def test_full_size_one_step_sampled_fp16s(make):
+    """FP16-shifted storage at full size, in the benchmark's launch configuration: one
+    step from a seeded random state, checked at sampled sites against the oracle's
+    site-by-site step of the unencoded state, within the fp16 rounding of the deviations
+    (2e-3 of each set's largest population, as in the small one-step cases); sum(phi) is
+    kept to the float32 bar."""
+    cfg = make()
+    q = cfg["lattice"]
+    shape = cfg["shape"]
+    h0, g0 = pfinputs.random_state(q, shape, seed=13)
+    s = _sim(cfg, storage="fp16s")
+    s.set_state(h0, g0)
+    m0, bad0 = s.mass()
+    s.step(1)
+    m1, bad1 = s.mass()
+    assert not bad0 and not bad1
+    assert abs(m1 - m0) <= 1e-6 * abs(m0), (m0, m1)
+    h1, g1 = s.get_state()
+    sites = pfinputs.sample_sites(shape, 300, seed=4)
+    x, y, z = (torch.as_tensor(v, device=h1.device) for v in sites.T)
+    hg = _np(h1[:, z, y, x])
+    gg = _np(g1[:, z, y, x])
+    del h1, g1, s
+    torch.cuda.empty_cache()
+    hr, gr = O.step_sites(_oracle_params(cfg), h0, g0, sites)
+    eh = np.abs(hg - hr).max() / np.abs(hr).max()
+    eg = np.abs(gg - gr).max() / np.abs(gr).max()
+    print(f"\nfp16s {cfg['name']} {shape} one step, 300 sampled sites: relative error "
+          f"h {eh:.2e} g {eg:.2e}, mass drift {(m1 - m0) / m0:.2e}")
+    assert eh <= 2e-3 and eg <= 2e-3
+
+
 # Up to 2^28 - 64 sites the step addresses a slot as a uniform base plus a 32-bit lane
 # offset; 1000 x 1000 x 268 = 2.68e8 sites is just below, ragged in x (1000 = 15 * 64 +
 # 40), so the last sites' slots sit within 4 MB of the 2^31-byte offset range.  Beyond
